@@ -1,0 +1,198 @@
+/*
+ * odc.h -- C ABI of libodc.so: Occupancy-Based Dual Contouring on one AMD
+ * MI355X (gfx950).
+ *
+ * Method: Hwang & Sung, "Occupancy-Based Dual Contouring", SIGGRAPH Asia
+ * 2024.  Problem statement (Sec. 3): an occupancy function phi and a uniform
+ * grid over a cubic domain go in; a Manifold-Dual-Contouring mesh comes out.
+ * The path: (a) phi' at every grid corner; (b) the 1D point of every crossing
+ * edge by bisection (Sec. 5.1); (c) 2D points of every crossing-edge pair on
+ * a face by three line-binary searches (Sec. 5.2, App. A.1.3-A.1.4); (d) per
+ * cell partitions of the crossing edges (App. A.1.1), normals from the 2D
+ * points (Sec. 5.3) and the QEF of Eq. 2 for each partition's 3D point;
+ * (e) MDC quads split by the intersection-free rule (App. A.1.5).
+ *
+ * Memory: every pointer inside odc_field and odc_mesh_buffers is DEVICE
+ * memory owned by the caller; it must stay valid until odc_mesh_sync (or the
+ * stream work) completes.  Scratch belongs to the context.  Nothing is freed
+ * across the ABI.  Calls never throw; every call returns an odc_status and
+ * leaves a message in odc_last_error().  A context is not thread-safe: one
+ * host thread at a time.
+ *
+ * Grid conventions (N = res cells per axis, corners 0..N):
+ *   corner (i,j,k) id = i + (N+1)(j + (N+1)k); cell id = i + N(j + Nk)
+ *   x-edges id = i + N(j + (N+1)k), then y-edges Ex + i + (N+1)(j + Nk),
+ *   then z-edges Ex + Ey + i + (N+1)(j + (N+1)k), Ex = Ey = N(N+1)^2
+ *   faces with normal x: i + (N+1)(j + Nk); normal y: Fx + i + N(j + (N+1)k);
+ *   normal z: Fx + Fy + i + N(j + Nk), Fx = Fy = (N+1)N^2
+ */
+#ifndef ODC_H
+#define ODC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ODC_OK = 0,
+  ODC_ERR_INVALID_ARG = 1,   /* a NULL pointer, a size or parameter out of range */
+  ODC_ERR_OUT_OF_MEMORY = 2, /* scratch could not be allocated */
+  ODC_ERR_CAPACITY = 3,      /* output buffers too small; counts hold the sizes needed */
+  ODC_ERR_HIP = 4,           /* a HIP runtime call failed; see odc_last_error */
+  ODC_ERR_UNSUPPORTED = 5,   /* a field shape the kernels do not implement */
+  ODC_ERR_BUSY = 6           /* the server queue is full */
+} odc_status;
+
+typedef struct odc_context odc_context;
+
+/* Occupancy field (Sec. 3: phi': R^3 -> {0,1}).  Two kinds:
+ *  ODC_FIELD_CSG  analytic primitives, n_prims records of 20 floats:
+ *                 [0] op (0 union, 1 subtract, 2 intersect; left fold, first ignored)
+ *                 [1] type (0 sphere, 1 box, 2 half-space) [2..4] centre c
+ *                 [5..7] sphere radius at [5] | box half extents | half-space normal
+ *                 [8..16] box rotation rows R (box-local = R (x - c))
+ *                 Labels are decided in binary32: sphere (dx^2+dy^2)+dz^2 < r*r;
+ *                 box |(R_a0 dx + R_a1 dy) + R_a2 dz| < half_a; half-space
+ *                 (n_x dx + n_y dy) + n_z dz < 0.
+ *  ODC_FIELD_MLP  phi = sigmoid(z), z = out_scale * MLP(gamma(x)) - sdf_gain * sdf(x);
+ *                 gamma(x) = (x, sin(2^k pi x), cos(2^k pi x)), k < n_bands
+ *                 (in_dim = 3 + 6 n_bands <= 45); depth hidden ReLU layers of
+ *                 width 256; weights binary32: W1[256][in_dim], b1[256], then
+ *                 (W[256][256], b[256]) per further layer, w_out[256], b_out;
+ *                 sdf = min over n_spheres spheres (cx,cy,cz,r) of |x-c| - r.
+ *                 Inside iff z > 0 (phi > 0.5, strict). */
+enum { ODC_FIELD_CSG = 0, ODC_FIELD_MLP = 1 };
+
+typedef struct {
+  int32_t kind;
+  const float* prims;   /* CSG records, device */
+  int32_t n_prims;
+  const float* weights; /* MLP weights, device */
+  int32_t in_dim, width, depth, n_bands;
+  const float* spheres; /* MLP sdf spheres, device, 4 floats each */
+  int32_t n_spheres;
+  float sdf_gain, out_scale;
+} odc_field;
+
+/* Evaluation precision for MLP fields (ignored for CSG).
+ *  FP32           every query in binary32 on matrix cores (fp32 MFMA).
+ *  BF16_GUARDED   corner queries in bf16 on matrix cores with fp32
+ *                 accumulation; any corner whose bf16 logit lies within
+ *                 guard_logit of zero is re-evaluated by the fp32 path, and the
+ *                 searches of (b) and (c), whose queries sit at the surface,
+ *                 use the fp32 path directly. */
+enum { ODC_PREC_FP32 = 0, ODC_PREC_BF16_GUARDED = 1 };
+
+typedef struct {
+  double lo[3];          /* domain minimum corner */
+  double size;           /* domain edge length; h = size / res */
+  int32_t res;           /* cells per axis, 1..512 */
+  int32_t iters_1d;      /* bisection halvings per crossing edge, 1..23 (paper: 15) */
+  int32_t lin1, bin1;    /* step-1 line-binary search: samples, halvings (4, 11) */
+  int32_t lin2, bin2;    /* step-2 line-binary searches (3, 12) */
+  float range1, range2;  /* search ranges in cell widths (0.8, sqrt(2)/2) */
+  float qef_tau;         /* QEF eigenvalue truncation relative to the largest (1e-2) */
+  double fp64_cond;      /* QEF redone in binary64 above this condition number (1e6) */
+  int32_t precision;     /* ODC_PREC_* */
+  float guard_logit;     /* bf16 guard band on z: 2 atanh(0.02) for |phi - 0.5| < 0.01 */
+} odc_params;
+
+/* Output buffers (device, caller-owned).  vertices: 3 floats per vertex,
+ * world coordinates.  triangles: 3 int32 vertex ids each, oriented so the
+ * normal points from inside to outside.  vertices_local / vertex_ref are
+ * optional (NULL): a vertex's offset in cell widths from grid corner
+ * vertex_ref (binary32), exact enough to compare at 512^3. */
+typedef struct {
+  float* vertices;
+  int64_t cap_vertices;
+  int32_t* triangles;
+  int64_t cap_triangles;
+  float* vertices_local;
+  int32_t* vertex_ref;
+} odc_mesh_buffers;
+
+typedef struct {
+  int64_t n_vertices;      /* partition vertices + case-3 vertices */
+  int64_t n_triangles;
+  int64_t n_active_edges;  /* crossing edges */
+  int64_t n_pairs;         /* crossing-edge pairs on faces (2D points) */
+  int64_t n_active_cells;
+  int64_t n_case3;         /* quads split into four triangles */
+  int64_t n_flipped_faces; /* ambiguous faces given the manifold-fix pairing */
+  int64_t n_fp64_cells;    /* QEF solves redone in binary64 */
+  int64_t n_guard_corners; /* bf16 corner queries re-evaluated in fp32 */
+  int64_t n_queries;       /* occupancy queries issued */
+} odc_mesh_counts;
+
+/* Status text (static storage). */
+const char* odc_status_string(int32_t status);
+/* Detail of the last failure on this context (context-owned, valid until the next call). */
+const char* odc_last_error(const odc_context* ctx);
+
+/* Creates a context on HIP device `device`.  hip_stream: a hipStream_t to
+ * enqueue on, or NULL for a context-owned stream (default priority). */
+int32_t odc_context_create(int32_t device, void* hip_stream, odc_context** out);
+void odc_context_destroy(odc_context* ctx);
+
+/* Fills the paper's parameters (App. A.1.4, Sec. 5.1) for res cells over [lo, lo+size]^3. */
+void odc_params_default(odc_params* p, int32_t res);
+
+/* Meshes one field.  Enqueues on the context stream; synchronises it once
+ * internally after classification to size the active-set scratch.  Returns
+ * when the mesh kernels are enqueued.  Errors: INVALID_ARG for bad params,
+ * NULL pointers with non-zero capacity, or an MLP without weights;
+ * UNSUPPORTED for MLP width != 256, depth outside 1..8 or in_dim > 45;
+ * OUT_OF_MEMORY; HIP. */
+int32_t odc_mesh_extract(odc_context* ctx, const odc_field* field, const odc_params* params,
+                         const odc_mesh_buffers* out);
+
+/* Waits for the last extract and reports its counts.  ODC_ERR_CAPACITY if
+ * the vertices or triangles did not fit: nothing beyond the capacities was
+ * written and the counts hold the sizes needed. */
+int32_t odc_mesh_sync(odc_context* ctx, odc_mesh_counts* counts);
+
+/* Copies an intermediate array of the last extract (after odc_mesh_sync) into
+ * dst (device memory of cap_bytes).  *n receives the element count.
+ *  0 corner label words   uint32 per 32 corners, bit c%32 of word c/32 (1 = inside)
+ *  1 crossing edge ids    int32, ascending
+ *  2 1D points            float t per crossing edge, from the lower corner
+ *  3 pair records         int32 face id << 1 | slot, ascending
+ *  4 2D points            double2 face-local (u,v) per pair (u,v: the two other axes, ascending)
+ *  5 active cell ids      int32, ascending
+ *  6 cell partition map   uint32: 2 bits per cell-local edge (crossing edges only)
+ *  7 cell counts          uint32: npart | flipmask << 4 (bit lf: local face 2*axis+side)
+ *  8 vertex base          int32 per active cell
+ *  9 emission case        int32 per crossing edge: 0 none, 1, 2, 3
+ * Errors: INVALID_ARG for an unknown `which`; CAPACITY when cap_bytes is too small. */
+int32_t odc_get_intermediate(odc_context* ctx, int32_t which, void* dst, int64_t cap_bytes,
+                             int64_t* n);
+
+/* Evaluates the field at n world points (xyz: device, 3 floats each) into z
+ * (device, n floats): for MLP fields the logit z (inside iff z > 0) computed
+ * by the same matrix-core code as the meshing path in the given precision
+ * (ODC_PREC_BF16_GUARDED here means the plain bf16 evaluation, without the
+ * fp32 re-check); for CSG fields +1 inside, -1 outside.  Synchronous.
+ * Errors: INVALID_ARG, UNSUPPORTED (as for odc_mesh_extract), HIP. */
+int32_t odc_field_eval(odc_context* ctx, const odc_field* field, int32_t precision,
+                       const float* xyz, int64_t n, float* z);
+
+/* Stage timing.  When enabled, odc_mesh_extract records HIP events on the
+ * context stream between stages; after odc_mesh_sync, odc_get_stage_times
+ * writes the device time of each stage in milliseconds:
+ *  0 (a) corner labels (incl. the fp32 re-evaluation of the bf16 guard band)
+ *  1 classification and scans (crossing edges, face pairs, active cells)
+ *  2 compaction of the active sets (after one host synchronisation)
+ *  3 (b) 1D points          4 (c) 2D points
+ *  5 (d) partitions and vertex numbering     6 (d) normals and QEF
+ *  7 (e) emission
+ * *n receives the number of stages (8).  Errors: INVALID_ARG when timing is
+ * off or no extract has completed; CAPACITY when cap < 8. */
+int32_t odc_context_set_timing(odc_context* ctx, int32_t enable);
+int32_t odc_get_stage_times(odc_context* ctx, float* ms, int32_t cap, int32_t* n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1245 @@
+// HIP kernels of the ODC path for gfx950 and their launchers.
+//
+// Stage map (paper sections in brackets):
+//   labels            (a) phi' at every corner, bit-packed          [Sec. 3]
+//   classify/compact  crossing edges, face pairs, active cells      [Sec. 3, App. A.1.1]
+//   bisect            (b) 1D points                                 [Sec. 5.1]
+//   search2d          (c) 2D points                                 [Sec. 5.2, App. A.1.3-A.1.4]
+//   cell_count/qef    (d) partitions, normals, QEF 3D points        [App. A.1.1, Sec. 5.3, Eq. 2]
+//   emit              (e) quads, intersection-free split            [Sec. 4, App. A.1.5]
+//
+// Launch shapes.  Grid-wide passes (labels of analytic fields, classification)
+// run one thread per element with wave ballots packing 64 results into two
+// 32-bit words.  Per-element passes over the compacted active sets run one
+// thread per element for analytic fields; MLP fields run one wavefront per 32
+// elements so that each occupancy query of the search is a 32-column
+// matrix-core batch (odc_mlp.h).
+#include "odc_internal.h"
+
+namespace odc {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ void store_ballot(uint64_t b, int first_elem_of_wave, int nwords,
+                                             uint32_t* __restrict__ dst) {
+  const int lane = lane_id();
+  const int w0 = first_elem_of_wave >> 5;
+  if (lane == 0 && w0 < nwords) dst[w0] = (uint32_t)b;
+  if (lane == 32 && w0 + 1 < nwords) dst[w0 + 1] = (uint32_t)(b >> 32);
+}
+
+static inline int nblocks(long long n, int per = kBlock) { return (int)((n + per - 1) / per); }
+
+// ------------------------------------------------------------------ scan
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ in, int n,
+                                                     uint32_t* __restrict__ bsum) {
+  __shared__ uint32_t sh[256];
+  const int base = blockIdx.x * 1024;
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = base + threadIdx.x + k * 256;
+    if (i < n) s += in[i];
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t* __restrict__ bsum, int nb,
+                                                      uint32_t* __restrict__ total) {
+  __shared__ uint32_t sh[1024];
+  uint32_t carry = 0;
+  const int t = threadIdx.x;
+  for (int base = 0; base < nb; base += 1024) {
+    const int i = base + t;
+    const uint32_t v = i < nb ? bsum[i] : 0u;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const uint32_t x = t >= off ? sh[t - off] : 0u;
+      __syncthreads();
+      sh[t] += x;
+      __syncthreads();
+    }
+    if (i < nb) bsum[i] = carry + sh[t] - v;
+    carry += sh[1023];
+    __syncthreads();
+  }
+  if (t == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ in, int n,
+                                                    const uint32_t* __restrict__ bsum,
+                                                    uint32_t* __restrict__ out) {
+  __shared__ uint32_t sh[256];
+  const int t = threadIdx.x;
+  const int base = blockIdx.x * 1024 + 4 * t;
+  uint32_t v[4], s = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0u;
+    s += v[k];
+  }
+  sh[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const uint32_t x = t >= off ? sh[t - off] : 0u;
+    __syncthreads();
+    sh[t] += x;
+    __syncthreads();
+  }
+  uint32_t run = bsum[blockIdx.x] + sh[t] - s;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+}
+
+size_t scan_tmp_words(int n) { return (size_t)((n + 1023) / 1024) + 1; }
+
+hipError_t scan_exclusive(const uint32_t* in, uint32_t* out, int n, uint32_t* tmp,
+                          hipStream_t s) {
+  const int nb = (n + 1023) / 1024;
+  if (nb == 0) {
+    return hipMemsetAsync(out, 0, sizeof(uint32_t), s);
+  }
+  k_scan_reduce<<<nb, 256, 0, s>>>(in, n, tmp);
+  k_scan_blocks<<<1, 1024, 0, s>>>(tmp, nb, out + n);
+  k_scan_apply<<<nb, 256, 0, s>>>(in, n, tmp, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ MLP weights
+// Packs the binary32 weights into the fragment orders of odc_mlp.h.
+__global__ void k_pack_mlp(const float* __restrict__ w, int in_dim, int depth,
+                           float* __restrict__ w1f, float* __restrict__ whf,
+                           v8bf* __restrict__ w1b, v8bf* __restrict__ whb,
+                           float* __restrict__ bias, float* __restrict__ wout) {
+  const int kb1f = (in_dim + 1) / 2, kb1b = (in_dim + 15) / 16;
+  const size_t l1 = (size_t)kWidth * in_dim;
+  const size_t hid = (size_t)kWidth * kWidth;
+  const long long n_w1f = (long long)kb1f * 8 * 64;
+  const long long n_whf = (long long)(depth - 1) * kHiddenBlocksF32 * 8 * 64;
+  const long long n_w1b = (long long)kb1b * 8 * 64;
+  const long long n_whb = (long long)(depth - 1) * kHiddenBlocksBF16 * 8 * 64;
+  const long long total = n_w1f + n_whf + n_w1b + n_whb + depth * kWidth + kWidth;
+  for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < total;
+       id += (long long)gridDim.x * blockDim.x) {
+    long long r = id;
+    if (r < n_w1f) {
+      const int lane = r % 64, R = (r / 64) % 8, b = (int)(r / 512);
+      const int row = 32 * R + (lane & 31), k = 2 * b + (lane >> 5);
+      w1f[r] = k < in_dim ? w[(size_t)row * in_dim + k] : 0.0f;
+      continue;
+    }
+    r -= n_w1f;
+    if (r < n_whf) {
+      const int lane = r % 64, R = (r / 64) % 8, b = (int)((r / 512) % kHiddenBlocksF32);
+      const int l = (int)(r / (512LL * kHiddenBlocksF32));
+      const int row = 32 * R + (lane & 31), h = lane >> 5;
+      const int T = b >> 4, i = b & 15;
+      const int n = 32 * T + 8 * (i >> 2) + 4 * h + (i & 3);
+      const float* W = w + l1 + kWidth + (size_t)l * (hid + kWidth);
+      whf[r] = W[(size_t)row * kWidth + n];
+      continue;
+    }
+    r -= n_whf;
+    if (r < n_w1b) {
+      const int lane = r % 64, R = (r / 64) % 8, b = (int)(r / 512);
+      const int row = 32 * R + (lane & 31), h = lane >> 5;
+      v8bf v;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = 16 * b + 8 * h + j;
+        v[j] = (__bf16)(k < in_dim ? w[(size_t)row * in_dim + k] : 0.0f);
+      }
+      w1b[r] = v;
+      continue;
+    }
+    r -= n_w1b;
+    if (r < n_whb) {
+      const int lane = r % 64, R = (r / 64) % 8, b = (int)((r / 512) % kHiddenBlocksBF16);
+      const int l = (int)(r / (512LL * kHiddenBlocksBF16));
+      const int row = 32 * R + (lane & 31), h = lane >> 5;
+      const int T = b >> 1, beta = b & 1;
+      const float* W = w + l1 + kWidth + (size_t)l * (hid + kWidth);
+      v8bf v;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int n = 32 * T + 16 * beta + 8 * (j >> 2) + 4 * h + (j & 3);
+        v[j] = (__bf16)W[(size_t)row * kWidth + n];
+      }
+      whb[r] = v;
+      continue;
+    }
+    r -= n_whb;
+    if (r < (long long)depth * kWidth) {
+      const int l = (int)(r / kWidth), n = (int)(r % kWidth);
+      const size_t off = (l == 0) ? l1 : l1 + kWidth + (size_t)(l - 1) * (hid + kWidth) + hid;
+      bias[r] = w[off + n];
+      continue;
+    }
+    r -= (long long)depth * kWidth;
+    wout[r] = w[l1 + kWidth + (size_t)(depth - 1) * (hid + kWidth) + r];
+  }
+}
+
+hipError_t launch_pack_mlp(const float* weights, int in_dim, int depth, float* w1f, float* whf,
+                           v8bf* w1b, v8bf* whb, float* bias, float* wout, hipStream_t s) {
+  k_pack_mlp<<<1024, 256, 0, s>>>(weights, in_dim, depth, w1f, whf, w1b, whb, bias, wout);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- (a) labels
+__global__ __launch_bounds__(256) void k_labels_csg(Grid g, const float* __restrict__ prims,
+                                                    int np, uint32_t* __restrict__ labels) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  int lab = 0;
+  if (c < g.nc) {
+    const int n1 = g.N + 1;
+    const float gp[3] = {(float)(c % n1), (float)((c / n1) % n1), (float)(c / (n1 * n1))};
+    float x[3];
+    grid_world(g, gp, x);
+    lab = csg_inside(prims, np, x);
+  }
+  const uint64_t b = __ballot(lab);
+  store_ballot(b, c - lane_id(), (g.nc + 31) >> 5, labels);
+}
+
+template <int BF16>
+__global__ __launch_bounds__(256) void k_labels_mlp(Job j) {
+  __shared__ float act_lds[kBlock / 64][BF16 ? kActVecsBF16 * 4 : kActWords];
+  float* act = act_lds[threadIdx.x >> 6];
+  const Grid& g = j.g;
+  const int lane = lane_id(), col = lane & 31;
+  const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int nwaves = gridDim.x * (kBlock / 64);
+  const int ntiles = (g.nc + 31) >> 5;
+  const int n1 = g.N + 1;
+  for (int t = wave; t < ntiles; t += nwaves) {
+    const int c = t * 32 + col;
+    const bool valid = c < g.nc;
+    const int cc = valid ? c : g.nc - 1;
+    const float gp[3] = {(float)(cc % n1), (float)((cc / n1) % n1), (float)(cc / (n1 * n1))};
+    float x[3];
+    grid_world(g, gp, x);
+    const float z = BF16 ? mlp_logit_bf16(j.mlp, x, reinterpret_cast<v8bf*>(act))
+                         : mlp_logit_fp32(j.mlp, x, act);
+    const uint64_t b = __ballot(valid && z > 0.0f);
+    if (lane == 0) j.labels[t] = (uint32_t)b;
+    if (BF16) {
+      const bool q = valid && lane < 32 && fabsf(z) < j.guard_logit;
+      const uint64_t qb = __ballot(q);
+      if (qb) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(&j.counters[0], (unsigned long long)__popcll(qb));
+        base = __shfl(base, 0);
+        if (q) {
+          const unsigned long long r = base + __popcll(qb & ((1ull << lane) - 1ull));
+          if (r < (unsigned long long)j.guard_cap) j.guard_list[r] = (uint32_t)c;
+        }
+      }
+    }
+  }
+}
+
+// fp32 re-evaluation of the corners queued by the bf16 pass
+__global__ __launch_bounds__(256) void k_relabel_fp32(Job j) {
+  __shared__ float act_lds[kBlock / 64][kActWords];
+  float* act = act_lds[threadIdx.x >> 6];
+  const Grid& g = j.g;
+  const int lane = lane_id(), col = lane & 31;
+  const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int nwaves = gridDim.x * (kBlock / 64);
+  const unsigned long long nq = j.counters[0];
+  const int n = (int)(nq < (unsigned long long)j.guard_cap ? nq : j.guard_cap);
+  const int n1 = g.N + 1;
+  for (int t = wave; t * 32 < n; t += nwaves) {
+    const int x_i = t * 32 + col;
+    const bool valid = x_i < n;
+    const int c = (int)j.guard_list[valid ? x_i : n - 1];
+    const float gp[3] = {(float)(c % n1), (float)((c / n1) % n1), (float)(c / (n1 * n1))};
+    float x[3];
+    grid_world(g, gp, x);
+    const float z = mlp_logit_fp32(j.mlp, x, act);
+    if (valid && lane < 32) {
+      const uint32_t bit = 1u << (c & 31);
+      if (z > 0.0f) atomicOr(&j.labels[c >> 5], bit);
+      else atomicAnd(&j.labels[c >> 5], ~bit);
+    }
+  }
+}
+
+hipError_t launch_labels(Job& j, hipStream_t s) {
+  if (j.kind == 0) {
+    k_labels_csg<<<nblocks(j.g.nc), kBlock, 0, s>>>(j.g, j.prims, j.n_prims, j.labels);
+    return hipGetLastError();
+  }
+  const int ntiles = (j.g.nc + 31) / 32;
+  const int blocks = ntiles / 4 + 1 < 4096 ? ntiles / 4 + 1 : 4096;
+  if (j.precision == 0) {
+    k_labels_mlp<0><<<blocks, kBlock, 0, s>>>(j);
+  } else {
+    k_labels_mlp<1><<<blocks, kBlock, 0, s>>>(j);
+    k_relabel_fp32<<<2048, kBlock, 0, s>>>(j);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------- classification
+__global__ __launch_bounds__(256) void k_classify_edges(Grid g, const uint32_t* __restrict__ L,
+                                                        uint32_t* __restrict__ emask,
+                                                        uint32_t* __restrict__ ecount) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  const int ne = 3 * g.ea;
+  int x = 0;
+  if (e < ne) {
+    int a, p[3];
+    edge_pos(g, e, a, p);
+    const int c0 = corner_index(g, p[0], p[1], p[2]);
+    const int step = a == 0 ? 1 : (a == 1 ? g.N + 1 : (g.N + 1) * (g.N + 1));
+    x = bit_of(L, c0) != bit_of(L, c0 + step);
+  }
+  const uint64_t b = __ballot(x);
+  const int nw = (ne + 31) >> 5;
+  store_ballot(b, e - lane_id(), nw, emask);
+  const int lane = lane_id(), w0 = (e - lane) >> 5;
+  if (lane == 0 && w0 < nw) ecount[w0] = __popc((uint32_t)b);
+  if (lane == 32 && w0 + 1 < nw) ecount[w0 + 1] = __popc((uint32_t)(b >> 32));
+}
+
+// labels of the 8 corners of cell (i,j,k): bit lc = x + 2y + 4z
+__device__ __forceinline__ int cell_config(const Grid& g, const uint32_t* __restrict__ L, int i,
+                                           int j, int k) {
+  const int c = corner_index(g, i, j, k);
+  const int n1 = g.N + 1, n2 = n1 * n1;
+  return bit_of(L, c) | (bit_of(L, c + 1) << 1) | (bit_of(L, c + n1) << 2) |
+         (bit_of(L, c + n1 + 1) << 3) | (bit_of(L, c + n2) << 4) | (bit_of(L, c + n2 + 1) << 5) |
+         (bit_of(L, c + n2 + n1) << 6) | (bit_of(L, c + n2 + n1 + 1) << 7);
+}
+
+__device__ __forceinline__ void face_labels(const Grid& g, const uint32_t* __restrict__ L, int a,
+                                            const int p[3], int out[4]) {
+  int u, v;
+  other_axes(a, u, v);
+#pragma unroll
+  for (int lc = 0; lc < 4; ++lc) {
+    int q[3] = {p[0], p[1], p[2]};
+    q[u] += lc & 1;
+    q[v] += lc >> 1;
+    out[lc] = bit_of(L, corner_index(g, q[0], q[1], q[2]));
+  }
+}
+
+// Manifold fix (App. A.1.1): an ambiguous face whose plain partitions merge
+// its two pairs in both adjacent cells takes the other pairing.
+__device__ inline int face_flip(const Grid& g, const uint32_t* __restrict__ L,
+                                const uint32_t* __restrict__ table, int a, const int p[3]) {
+  if (p[a] <= 0 || p[a] >= g.N) return 0;
+  int merged = 1;
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    int c[3] = {p[0], p[1], p[2]};
+    int s_in_cell = 0;
+    if (side == 0) {
+      c[a] -= 1;
+      s_in_cell = 1;
+    }
+    const int cfg = cell_config(g, L, c[0], c[1], c[2]);
+    const uint32_t pm = table[cfg] & 0xFFFFFFu;
+    const int e0 = face_to_cell_edge(a, s_in_cell, 0);
+    const int e1 = face_to_cell_edge(a, s_in_cell, 1);
+    if (((pm >> (2 * e0)) & 3u) != ((pm >> (2 * e1)) & 3u)) merged = 0;
+  }
+  return merged;
+}
+
+__global__ __launch_bounds__(256) void k_classify_faces(Grid g, const uint32_t* __restrict__ L,
+                                                        const uint32_t* __restrict__ table,
+                                                        uint32_t* __restrict__ fact,
+                                                        uint32_t* __restrict__ famb,
+                                                        uint32_t* __restrict__ fflip,
+                                                        uint32_t* __restrict__ pcount) {
+  const int f = blockIdx.x * kBlock + threadIdx.x;
+  const int nf = 3 * g.fa;
+  int act = 0, amb = 0, flip = 0;
+  if (f < nf) {
+    int a, p[3], Lf[4];
+    face_pos(g, f, a, p);
+    face_labels(g, L, a, p, Lf);
+    const int n = __popc(face_crossing_mask(Lf));
+    act = n > 0;
+    amb = n == 4;
+    if (amb) flip = face_flip(g, L, table, a, p);
+  }
+  const uint64_t ba = __ballot(act), bb = __ballot(amb), bf = __ballot(flip);
+  const int nw = (nf + 31) >> 5;
+  const int first = f - lane_id();
+  store_ballot(ba, first, nw, fact);
+  store_ballot(bb, first, nw, famb);
+  store_ballot(bf, first, nw, fflip);
+  const int lane = lane_id(), w0 = first >> 5;
+  if (lane == 0 && w0 < nw) pcount[w0] = __popc((uint32_t)ba) + __popc((uint32_t)bb);
+  if (lane == 32 && w0 + 1 < nw)
+    pcount[w0 + 1] = __popc((uint32_t)(ba >> 32)) + __popc((uint32_t)(bb >> 32));
+}
+
+__global__ __launch_bounds__(256) void k_classify_cells(Grid g, const uint32_t* __restrict__ L,
+                                                        uint32_t* __restrict__ cmask,
+                                                        uint32_t* __restrict__ ccount) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  int x = 0;
+  if (c < g.ncell) {
+    const int N = g.N;
+    const int cfg = cell_config(g, L, c % N, (c / N) % N, c / (N * N));
+    x = cfg != 0 && cfg != 255;
+  }
+  const uint64_t b = __ballot(x);
+  const int nw = (g.ncell + 31) >> 5;
+  store_ballot(b, c - lane_id(), nw, cmask);
+  const int lane = lane_id(), w0 = (c - lane) >> 5;
+  if (lane == 0 && w0 < nw) ccount[w0] = __popc((uint32_t)b);
+  if (lane == 32 && w0 + 1 < nw) ccount[w0 + 1] = __popc((uint32_t)(b >> 32));
+}
+
+hipError_t launch_classify(Job& j, uint32_t* ecount, uint32_t* pcount, uint32_t* ccount,
+                           const uint32_t* table, hipStream_t s) {
+  k_classify_edges<<<nblocks(3LL * j.g.ea), kBlock, 0, s>>>(j.g, j.labels, j.emask, ecount);
+  k_classify_faces<<<nblocks(3LL * j.g.fa), kBlock, 0, s>>>(j.g, j.labels, table, j.fact,
+                                                             j.famb, j.fflip, pcount);
+  k_classify_cells<<<nblocks(j.g.ncell), kBlock, 0, s>>>(j.g, j.labels, j.cmask, ccount);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ compaction
+__global__ __launch_bounds__(256) void k_compact_bits(const uint32_t* __restrict__ mask,
+                                                      const uint32_t* __restrict__ prefix,
+                                                      int nw, int* __restrict__ list) {
+  const int w = blockIdx.x * kBlock + threadIdx.x;
+  if (w >= nw) return;
+  uint32_t m = mask[w];
+  int o = (int)prefix[w];
+  while (m) {
+    const int b = __ffs(m) - 1;
+    list[o++] = w * 32 + b;
+    m &= m - 1u;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_compact_pairs(const uint32_t* __restrict__ act,
+                                                       const uint32_t* __restrict__ amb,
+                                                       const uint32_t* __restrict__ prefix,
+                                                       int nw, int* __restrict__ list) {
+  const int w = blockIdx.x * kBlock + threadIdx.x;
+  if (w >= nw) return;
+  uint32_t m = act[w];
+  const uint32_t a2 = amb[w];
+  int o = (int)prefix[w];
+  while (m) {
+    const int b = __ffs(m) - 1;
+    const int f = w * 32 + b;
+    list[o++] = f << 1;
+    if ((a2 >> b) & 1u) list[o++] = (f << 1) | 1;
+    m &= m - 1u;
+  }
+}
+
+hipError_t launch_compact(Job& j, hipStream_t s) {
+  const int nwe = (3 * j.g.ea + 31) >> 5, nwf = (3 * j.g.fa + 31) >> 5,
+            nwc = (j.g.ncell + 31) >> 5;
+  k_compact_bits<<<nblocks(nwe), kBlock, 0, s>>>(j.emask, j.eprefix, nwe, j.elist);
+  k_compact_pairs<<<nblocks(nwf), kBlock, 0, s>>>(j.fact, j.famb, j.pprefix, nwf, j.plist);
+  k_compact_bits<<<nblocks(nwc), kBlock, 0, s>>>(j.cmask, j.cprefix, nwc, j.clist);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------- label functors
+struct CsgLabel {
+  const Grid* g;
+  const float* prims;
+  int n;
+  __device__ __forceinline__ int operator()(const float gp[3]) const {
+    float x[3];
+    grid_world(*g, gp, x);
+    return csg_inside(prims, n, x);
+  }
+};
+
+// wave-cooperative: every lane of the wave must call it together
+struct MlpLabel {
+  const Grid* g;
+  const Mlp* m;
+  float* act;  // this wavefront's LDS activation region
+  __device__ __forceinline__ int operator()(const float gp[3]) const {
+    float x[3];
+    grid_world(*g, gp, x);
+    return mlp_logit_fp32(*m, x, act) > 0.0f;
+  }
+};
+
+// ------------------------------------------------------------ (b) 1D points
+// Bisection (Sec. 5.1): k halvings of [0,1] keeping distinct end labels; the
+// point is the middle of the final bracket.
+template <class Lab>
+__device__ __forceinline__ float bisect_edge(const Job& j, const Lab& lab, int id) {
+  int a, p[3];
+  edge_pos(j.g, id, a, p);
+  const int l0 = bit_of(j.labels, corner_index(j.g, p[0], p[1], p[2]));
+  float lo = 0.0f, hi = 1.0f;
+  for (int it = 0; it < j.iters_1d; ++it) {
+    const float mid = (lo + hi) * 0.5f;
+    float gp[3] = {(float)p[0], (float)p[1], (float)p[2]};
+    gp[a] = (float)p[a] + mid;
+    if (lab(gp) == l0) lo = mid;
+    else hi = mid;
+  }
+  return (lo + hi) * 0.5f;
+}
+
+__global__ __launch_bounds__(256) void k_bisect_csg(Job j) {
+  const int x = blockIdx.x * kBlock + threadIdx.x;
+  if (x >= j.n_edges) return;
+  CsgLabel lab{&j.g, j.prims, j.n_prims};
+  j.et[x] = bisect_edge(j, lab, j.elist[x]);
+}
+
+__global__ __launch_bounds__(256) void k_bisect_mlp(Job j) {
+  __shared__ float act_lds[kBlock / 64][kActWords];
+  const int lane = lane_id(), col = lane & 31;
+  const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int nwaves = gridDim.x * (kBlock / 64);
+  MlpLabel lab{&j.g, &j.mlp, act_lds[threadIdx.x >> 6]};
+  for (int t = wave; t * 32 < j.n_edges; t += nwaves) {
+    const int x = t * 32 + col;
+    const bool valid = x < j.n_edges;
+    const float tt = bisect_edge(j, lab, j.elist[valid ? x : j.n_edges - 1]);
+    if (valid && lane < 32) j.et[x] = tt;
+  }
+}
+
+hipError_t launch_bisect(Job& j, hipStream_t s) {
+  if (j.n_edges == 0) return hipSuccess;
+  if (j.kind == 0) {
+    k_bisect_csg<<<nblocks(j.n_edges), kBlock, 0, s>>>(j);
+  } else {
+    const int tiles = (j.n_edges + 31) / 32;
+    const int blocks = tiles / 4 + 1 < 2048 ? tiles / 4 + 1 : 2048;
+    k_bisect_mlp<<<blocks, kBlock, 0, s>>>(j);
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ (c) 2D points
+struct FaceFrame {
+  int a, u, v;
+  int p[3];
+};
+
+__device__ __forceinline__ void face_edge_point(int fe, float t, float P[2]) {
+  P[0] = fe < 2 ? t : (float)(fe - 2);
+  P[1] = fe < 2 ? (float)fe : t;
+}
+
+__device__ __forceinline__ int face_edge_global(const Grid& g, const FaceFrame& fr, int fe) {
+  int q[3] = {fr.p[0], fr.p[1], fr.p[2]};
+  int axis;
+  if (fe < 2) {
+    axis = fr.u;
+    q[fr.v] += fe;
+  } else {
+    axis = fr.v;
+    q[fr.u] += fe - 2;
+  }
+  return edge_index(g, axis, q[0], q[1], q[2]);
+}
+
+// One line-binary search (App. A.1.3) driven one query at a time: samples
+// p0 + (R i / N) d for i = 1..N; the first whose label differs from s0 (else
+// i = N) bounds the bracket; then halvings compare the middle with the near
+// end, which keeps the label s0.
+struct LineBinary {
+  float p0[2], d[2];
+  float R, nr, fa;
+  int nl, s0, istar, found;
+  __device__ __forceinline__ void start(const float a[2], const float dir[2], int s, float r,
+                                        int n) {
+    p0[0] = a[0];
+    p0[1] = a[1];
+    d[0] = dir[0];
+    d[1] = dir[1];
+    s0 = s;
+    R = r;
+    nl = n;
+    istar = n;
+    found = 0;
+  }
+  __device__ __forceinline__ float param(int k) const {
+    return k < nl ? (R * (float)(k + 1)) / (float)nl : (nr + fa) * 0.5f;
+  }
+  __device__ __forceinline__ void point(float s, float P[2]) const {
+    const float su = s * d[0], sv = s * d[1];
+    P[0] = p0[0] + su;
+    P[1] = p0[1] + sv;
+  }
+  __device__ __forceinline__ void consume(int k, float s, int lab) {
+    if (k < nl) {
+      if (lab != s0 && !found) {
+        istar = k + 1;
+        found = 1;
+      }
+      if (k == nl - 1) {
+        nr = (istar == 1) ? 0.0f : (R * (float)(istar - 1)) / (float)nl;
+        fa = (R * (float)istar) / (float)nl;
+      }
+    } else if (lab == s0) {
+      nr = s;
+    } else {
+      fa = s;
+    }
+  }
+};
+
+// The three steps of Sec. 5.2 for pair `slot` of face `face`, as a fixed
+// sequence of 1 + (lin1 + bin1) + 2 (lin2 + bin2) occupancy queries so that a
+// wavefront can batch each query across its lanes.  `lab` is called from
+// exactly one place.
+template <class Lab>
+__device__ double2 search_pair(const Job& j, const Lab& lab, int face, int slot) {
+  const Grid& g = j.g;
+  FaceFrame fr;
+  face_pos(g, face, fr.a, fr.p);
+  other_axes(fr.a, fr.u, fr.v);
+  int L[4], pa[2], pb[2];
+  face_labels(g, j.labels, fr.a, fr.p, L);
+  face_pairs(L, bit_of(j.fflip, face), pa, pb);
+  const int fa = pa[slot], fb = pb[slot];
+  const float t1 = j.et[rank_of(j.emask, j.eprefix, face_edge_global(g, fr, fa))];
+  const float t2 = j.et[rank_of(j.emask, j.eprefix, face_edge_global(g, fr, fb))];
+  float P1[2], P2[2];
+  face_edge_point(fa, t1, P1);
+  face_edge_point(fb, t2, P2);
+  const float m[2] = {(P1[0] + P2[0]) * 0.5f, (P1[1] + P2[1]) * 0.5f};
+  const float du = P2[0] - P1[0], dv = P2[1] - P1[1];
+  const int n1 = j.lin1 + j.bin1, n2 = j.lin2 + j.bin2;
+  const int total = 1 + n1 + 2 * n2;
+  LineBinary lb;
+  int sm = 0;
+  float q[2] = {m[0], m[1]}, q1[2] = {0, 0}, s1 = 0.0f;
+  for (int step = 0; step < total; ++step) {
+    // the query of this step
+    float P[2], s = 0.0f;
+    int k = 0;
+    if (step == 0) {
+      P[0] = m[0];
+      P[1] = m[1];
+    } else {
+      k = step - 1;
+      if (k >= n1) k -= n1;
+      if (k >= n2) k -= n2;
+      s = lb.param(k);
+      lb.point(s, P);
+    }
+    float gp[3];
+    gp[fr.a] = (float)fr.p[fr.a];
+    gp[fr.u] = (float)fr.p[fr.u] + P[0];
+    gp[fr.v] = (float)fr.p[fr.v] + P[1];
+    const int l = lab(gp);
+    if (step == 0) {
+      // step 1: the ray from m orthogonal to l, towards a corner whose label
+      // differs from m's; when both sides qualify, the side of the corner the
+      // pair cuts off.  Which side a corner is on does not depend on t in
+      // (0,1), so it is evaluated at t = 1/2 where the products are exact.
+      sm = l;
+      const float dd = du * du, ee = dv * dv;
+      const float len = sqrtf(dd + ee);
+      const float perp[2] = {-dv / len, du / len};  // left of P1 -> P2
+      float H1[2], H2[2];
+      face_edge_point(fa, 0.5f, H1);
+      face_edge_point(fb, 0.5f, H2);
+      int nleft = 0, nright = 0, dleft = 0, dright = 0;
+#pragma unroll
+      for (int lc = 0; lc < 4; ++lc) {
+        const float cu = (float)(lc & 1), cv = (float)(lc >> 1);
+        const float cr = (H2[0] - H1[0]) * (cv - H1[1]) - (H2[1] - H1[1]) * (cu - H1[0]);
+        if (cr > 0.0f) {
+          ++nleft;
+          dleft |= L[lc] != sm;
+        } else {
+          ++nright;
+          dright |= L[lc] != sm;
+        }
+      }
+      const int go_left =
+          (dleft && !dright) ? 1 : ((dright && !dleft) ? 0 : (nleft <= nright ? 1 : 0));
+      const float d[2] = {go_left ? perp[0] : -perp[0], go_left ? perp[1] : -perp[1]};
+      lb.start(m, d, sm, j.range1, j.lin1);
+      continue;
+    }
+    lb.consume(k, s, l);
+    if (step == n1) {
+      // end of step 1: q; step 2 starts towards P1
+      s1 = lb.nr;
+      lb.point(s1, q);
+      const float wu = P1[0] - m[0], wv = P1[1] - m[1];
+      const float ww = wu * wu, vv = wv * wv;
+      const float lw = sqrtf(ww + vv);
+      const float uh[2] = {wu / lw, wv / lw};
+      lb.start(q, uh, sm, j.range2, j.lin2);
+    } else if (step == n1 + n2) {
+      lb.point(lb.nr, q1);
+      const float un[2] = {-lb.d[0], -lb.d[1]};
+      lb.start(q, un, sm, j.range2, j.lin2);
+    }
+  }
+  float q2[2];
+  lb.point(lb.nr, q2);
+  if (s1 == 0.0f) return make_double2(m[0], m[1]);
+  // step 3: intersection of line(P1,q1) and line(P2,q2).  On smooth surfaces
+  // l1 and l2 are nearly parallel (sin ~ 1e-4), where binary32 differences of
+  // the inputs alone move the apex by 1e-7/sin; the solve is binary64 (the
+  // differences of binary32 inputs are then exact) and the point is kept in
+  // binary64: where a cell cuts a tiny corner, its 2D points sit within 1e-5
+  // of their 1D points near face coordinate 1, below binary32 resolution
+  // there relative to the distance that sets the normal.
+  const double Au = (double)q1[0] - (double)P1[0], Av = (double)q1[1] - (double)P1[1];
+  const double Bu = (double)q2[0] - (double)P2[0], Bv = (double)q2[1] - (double)P2[1];
+  const double det = Au * Bv - Av * Bu;
+  if (det == 0.0) return make_double2(q[0], q[1]);
+  const double Du = (double)P2[0] - (double)P1[0], Dv = (double)P2[1] - (double)P1[1];
+  const double alpha = (Du * Bv - Dv * Bu) / det;
+  return make_double2((double)P1[0] + alpha * Au, (double)P1[1] + alpha * Av);
+}
+
+__global__ __launch_bounds__(256) void k_search2d_csg(Job j) {
+  const int x = blockIdx.x * kBlock + threadIdx.x;
+  if (x >= j.n_pairs) return;
+  CsgLabel lab{&j.g, j.prims, j.n_prims};
+  const int rec = j.plist[x];
+  j.pf[x] = search_pair(j, lab, rec >> 1, rec & 1);
+}
+
+__global__ __launch_bounds__(256) void k_search2d_mlp(Job j) {
+  __shared__ float act_lds[kBlock / 64][kActWords];
+  const int lane = lane_id(), col = lane & 31;
+  const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int nwaves = gridDim.x * (kBlock / 64);
+  MlpLabel lab{&j.g, &j.mlp, act_lds[threadIdx.x >> 6]};
+  for (int t = wave; t * 32 < j.n_pairs; t += nwaves) {
+    const int x = t * 32 + col;
+    const bool valid = x < j.n_pairs;
+    const int rec = j.plist[valid ? x : j.n_pairs - 1];
+    const double2 r = search_pair(j, lab, rec >> 1, rec & 1);
+    if (valid && lane < 32) j.pf[x] = r;
+  }
+}
+
+hipError_t launch_search2d(Job& j, hipStream_t s) {
+  if (j.n_pairs == 0) return hipSuccess;
+  if (j.kind == 0) {
+    k_search2d_csg<<<nblocks(j.n_pairs), kBlock, 0, s>>>(j);
+  } else {
+    const int tiles = (j.n_pairs + 31) / 32;
+    const int blocks = tiles / 4 + 1 < 2048 ? tiles / 4 + 1 : 2048;
+    k_search2d_mlp<<<blocks, kBlock, 0, s>>>(j);
+  }
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------- (d) partitions, QEF
+__device__ __forceinline__ void cell_of(const Grid& g, int cid, int c[3]) {
+  c[0] = cid % g.N;
+  c[1] = (cid / g.N) % g.N;
+  c[2] = cid / (g.N * g.N);
+}
+
+__device__ __forceinline__ int cell_flipmask(const Grid& g, const uint32_t* __restrict__ fflip,
+                                             const int c[3]) {
+  int fm = 0;
+#pragma unroll
+  for (int lf = 0; lf < 6; ++lf) {
+    const int a = lf >> 1;
+    int q[3] = {c[0], c[1], c[2]};
+    q[a] += lf & 1;
+    fm |= bit_of(fflip, face_index(g, a, q[0], q[1], q[2])) << lf;
+  }
+  return fm;
+}
+
+__global__ __launch_bounds__(256) void k_cell_count(Job j, const uint32_t* __restrict__ table,
+                                                    uint32_t* __restrict__ npart) {
+  const int x = blockIdx.x * kBlock + threadIdx.x;
+  if (x >= j.n_cells) return;
+  int c[3];
+  cell_of(j.g, j.clist[x], c);
+  const int cfg = cell_config(j.g, j.labels, c[0], c[1], c[2]);
+  const int fm = cell_flipmask(j.g, j.fflip, c);
+  int pm, np;
+  if (fm == 0) {
+    pm = (int)(table[cfg] & 0xFFFFFFu);
+    np = (int)(table[cfg] >> 24);
+  } else {
+    np = cube_partitions(cfg, fm, pm);
+  }
+  j.cpm[x] = (uint32_t)pm;
+  j.cnf[x] = (uint32_t)(np | (fm << 4));
+  npart[x] = (uint32_t)np;
+}
+
+hipError_t launch_cell_count(Job& j, uint32_t* npart, const uint32_t* table, hipStream_t s) {
+  if (j.n_cells == 0) return hipSuccess;
+  k_cell_count<<<nblocks(j.n_cells), kBlock, 0, s>>>(j, table, npart);
+  return hipGetLastError();
+}
+
+template <typename T>
+__device__ void jacobi3(T A[3][3], T V[3][3], T ev[3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) V[i][k] = (i == k) ? T(1) : T(0);
+  const T eps = sizeof(T) == 4 ? T(1e-7) : T(1e-18);
+  for (int sweep = 0; sweep < 32; ++sweep) {
+    const T off = fabs(A[0][1]) + fabs(A[0][2]) + fabs(A[1][2]);
+    const T diag = fabs(A[0][0]) + fabs(A[1][1]) + fabs(A[2][2]);
+    if (off == T(0) || off <= eps * diag) break;
+#pragma unroll
+    for (int pq = 0; pq < 3; ++pq) {
+      const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
+      if (A[p][q] == T(0)) continue;
+      const T theta = (A[q][q] - A[p][p]) / (T(2) * A[p][q]);
+      const T t = (theta >= T(0) ? T(1) : T(-1)) / (fabs(theta) + sqrt(theta * theta + T(1)));
+      const T cs = T(1) / sqrt(t * t + T(1)), sn = t * cs;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const T akp = A[k][p], akq = A[k][q];
+        A[k][p] = cs * akp - sn * akq;
+        A[k][q] = sn * akp + cs * akq;
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const T apk = A[p][k], aqk = A[q][k];
+        A[p][k] = cs * apk - sn * aqk;
+        A[q][k] = sn * apk + cs * aqk;
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const T vkp = V[k][p], vkq = V[k][q];
+        V[k][p] = cs * vkp - sn * vkq;
+        V[k][q] = sn * vkp + cs * vkq;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) ev[i] = A[i][i];
+}
+
+// 2D point (cell-local 3D) of the pair on local face (fa, side) that holds
+// cell-local edge le.
+__device__ __forceinline__ void cell_face_point(const Job& j, const int c[3], int fm, int fa,
+                                                int side, int le, double out[3]) {
+  const Grid& g = j.g;
+  int q[3] = {c[0], c[1], c[2]};
+  q[fa] += side;
+  const int face = face_index(g, fa, q[0], q[1], q[2]);
+  int L[4], pa[2], pb[2];
+  face_labels(g, j.labels, fa, q, L);
+  const int np = face_pairs(L, (fm >> (2 * fa + side)) & 1, pa, pb);
+  // face-local index of the edge
+  const int ax = le >> 2;
+  int b1, b2;
+  other_axes(ax, b1, b2);
+  const int off_b1 = le & 1, off_b2 = (le >> 1) & 1;
+  int u, v;
+  other_axes(fa, u, v);
+  const int other = (b1 == fa) ? b2 : b1;
+  const int off_other = (b1 == fa) ? off_b2 : off_b1;
+  const int fe = (ax == u) ? off_other : 2 + off_other;
+  (void)v;
+  int slot = 0;
+  for (int k = 0; k < np; ++k)
+    if (pa[k] == fe || pb[k] == fe) slot = k;
+  const int w = face >> 5;
+  const uint32_t below = (1u << (face & 31)) - 1u;
+  const int base = (int)j.pprefix[w] + __popc(j.fact[w] & below) + __popc(j.famb[w] & below);
+  const double2 pf = j.pf[base + slot];
+  out[fa] = (double)side;
+  out[u] = pf.x;
+  out[v] = pf.y;
+  (void)other;
+}
+
+// Normal of crossing edge le of cell c (Sec. 5.3): the cross product of the
+// directions from its 1D point to the 2D points on the cell's two faces that
+// hold it.  The differences are taken in binary64 from the binary64 2D points
+// and then rounded to T.  Returns false for a zero cross product.
+template <typename T>
+__device__ __forceinline__ bool edge_plane(const Job& j, const int c[3], int fm, int le,
+                                           T pe[3], T n[3]) {
+  const int ax = le >> 2;
+  int b1, b2;
+  other_axes(ax, b1, b2);
+  int off[3] = {0, 0, 0};
+  off[b1] = le & 1;
+  off[b2] = (le >> 1) & 1;
+  const int gid = edge_index(j.g, ax, c[0] + off[0], c[1] + off[1], c[2] + off[2]);
+  const float t = j.et[rank_of(j.emask, j.eprefix, gid)];
+  double ped[3] = {(double)off[0], (double)off[1], (double)off[2]};
+  ped[ax] = (double)t;
+  double f1[3], f2[3];
+  cell_face_point(j, c, fm, b1, off[b1], le, f1);
+  cell_face_point(j, c, fm, b2, off[b2], le, f2);
+  T d1[3], d2[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    pe[k] = (T)ped[k];
+    d1[k] = (T)(f1[k] - ped[k]);
+    d2[k] = (T)(f2[k] - ped[k]);
+  }
+  n[0] = d1[1] * d2[2] - d1[2] * d2[1];
+  n[1] = d1[2] * d2[0] - d1[0] * d2[2];
+  n[2] = d1[0] * d2[1] - d1[1] * d2[0];
+  const T nl = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  if (!(nl > T(0))) return false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) n[k] /= nl;
+  return true;
+}
+
+// QEF of one partition (Eq. 2 with normals from 2D points, Sec. 5.3) in
+// cell-local coordinates: mass point c of the 1D points, A = sum n n^T,
+// b = sum n n.(p_e - c), x = c + A^+_tau b with eigenvalues below
+// tau * max dropped, plus one refinement step x += A^+_tau (b - A x) that
+// recovers the accuracy the binary32 eigen-decomposition loses.  Returns
+// false when T is float and the normal matrix's condition number exceeds
+// fp64_cond (the caller redoes the solve in binary64).
+template <typename T>
+__device__ bool qef_partition(const Job& j, const int c[3], int cfg, int fm, uint32_t pm,
+                              int part, T x[3]) {
+  // pass 1: mass point of the 1D points
+  T cs[3] = {0, 0, 0};
+  int cnt = 0;
+  for (int le = 0; le < 12; ++le) {
+    if (!cube_edge_crosses(cfg, le) || (int)((pm >> (2 * le)) & 3u) != part) continue;
+    const int ax = le >> 2;
+    int b1, b2;
+    other_axes(ax, b1, b2);
+    int off[3] = {0, 0, 0};
+    off[b1] = le & 1;
+    off[b2] = (le >> 1) & 1;
+    const int gid = edge_index(j.g, ax, c[0] + off[0], c[1] + off[1], c[2] + off[2]);
+    T pe[3] = {(T)off[0], (T)off[1], (T)off[2]};
+    pe[ax] = (T)j.et[rank_of(j.emask, j.eprefix, gid)];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) cs[k] += pe[k];
+    ++cnt;
+  }
+  T cm[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    cm[k] = cs[k] / (T)(cnt > 0 ? cnt : 1);
+    x[k] = cm[k];
+  }
+  // pass 2: planes
+  T A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, b[3] = {0, 0, 0};
+  int used = 0;
+  for (int le = 0; le < 12; ++le) {
+    if (!cube_edge_crosses(cfg, le) || (int)((pm >> (2 * le)) & 3u) != part) continue;
+    T pe[3], n[3];
+    if (!edge_plane<T>(j, c, fm, le, pe, n)) continue;
+    const T dd = n[0] * (pe[0] - cm[0]) + n[1] * (pe[1] - cm[1]) + n[2] * (pe[2] - cm[2]);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      b[r] += n[r] * dd;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) A[r][k] += n[r] * n[k];
+    }
+    ++used;
+  }
+  if (used == 0) return true;
+  T M[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) M[r][k] = A[r][k];
+  T V[3][3], ev[3];
+  jacobi3<T>(M, V, ev);
+  const T lmax = fmax(ev[0], fmax(ev[1], ev[2]));
+  const T lmin = fmin(ev[0], fmin(ev[1], ev[2]));
+  if (sizeof(T) == 4 && (lmin <= T(0) || (double)lmax > j.fp64_cond * (double)lmin)) return false;
+  const T thr = (T)j.qef_tau * lmax;
+  T y[3] = {0, 0, 0};
+  for (int pass = 0; pass < 2; ++pass) {
+    T r[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) r[q] = b[q] - (A[q][0] * y[0] + A[q][1] * y[1] + A[q][2] * y[2]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (!(ev[k] >= thr) || ev[k] <= T(0)) continue;
+      const T vr = V[0][k] * r[0] + V[1][k] * r[1] + V[2][k] * r[2];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) y[a] += V[a][k] * vr / ev[k];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) x[a] += y[a];
+  return true;
+}
+
+__global__ __launch_bounds__(256) void k_cell_qef(Job j) {
+  const int x = blockIdx.x * kBlock + threadIdx.x;
+  int fp64 = 0;
+  if (x < j.n_cells) {
+    const int cid = j.clist[x];
+    int c[3];
+    cell_of(j.g, cid, c);
+    const int cfg = cell_config(j.g, j.labels, c[0], c[1], c[2]);
+    const uint32_t pm = j.cpm[x];
+    const int np = (int)(j.cnf[x] & 15u), fm = (int)(j.cnf[x] >> 4);
+    const int vb = (int)j.vbase[x];
+    for (int part = 0; part < np; ++part) {
+      float v[3];
+      float xf[3];
+      if (qef_partition<float>(j, c, cfg, fm, pm, part, xf)) {
+        v[0] = xf[0]; v[1] = xf[1]; v[2] = xf[2];
+      } else {
+        double xd[3];
+        qef_partition<double>(j, c, cfg, fm, pm, part, xd);
+        v[0] = (float)xd[0]; v[1] = (float)xd[1]; v[2] = (float)xd[2];
+        ++fp64;
+      }
+      const int vid = vb + part;
+      j.vloc[3 * vid] = v[0];
+      j.vloc[3 * vid + 1] = v[1];
+      j.vloc[3 * vid + 2] = v[2];
+      if (vid < j.cap_v) {
+        const float gp[3] = {(float)c[0] + v[0], (float)c[1] + v[1], (float)c[2] + v[2]};
+        float w[3];
+        grid_world(j.g, gp, w);
+        j.out_v[3 * vid] = w[0];
+        j.out_v[3 * vid + 1] = w[1];
+        j.out_v[3 * vid + 2] = w[2];
+        if (j.out_vloc) {
+          j.out_vloc[3 * vid] = v[0];
+          j.out_vloc[3 * vid + 1] = v[1];
+          j.out_vloc[3 * vid + 2] = v[2];
+        }
+        if (j.out_vref) j.out_vref[vid] = corner_index(j.g, c[0], c[1], c[2]);
+      }
+    }
+  }
+  // one atomic per wave
+  const uint64_t any = __ballot(fp64 != 0);
+  if (any) {
+    int tot = fp64;
+    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+    if (lane_id() == 0) atomicAdd(&j.counters[1], (unsigned long long)tot);
+  }
+}
+
+hipError_t launch_cell_qef(Job& j, hipStream_t s) {
+  if (j.n_cells == 0) return hipSuccess;
+  k_cell_qef<<<nblocks(j.n_cells), kBlock, 0, s>>>(j);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------- (e) emit
+__device__ __forceinline__ float triple3(const float a[3], const float b[3], const float c[3]) {
+  const float x = b[1] * c[2] - b[2] * c[1];
+  const float y = b[2] * c[0] - b[0] * c[2];
+  const float z = b[0] * c[1] - b[1] * c[0];
+  return a[0] * x + a[1] * y + a[2] * z;
+}
+
+__global__ __launch_bounds__(256) void k_emit_count(Job j, uint32_t* __restrict__ ntri,
+                                                    uint32_t* __restrict__ n3) {
+  const int x = blockIdx.x * kBlock + threadIdx.x;
+  if (x >= j.n_edges) return;
+  const Grid& g = j.g;
+  int a, p[3];
+  edge_pos(g, j.elist[x], a, p);
+  const int b = (a + 1) % 3, cc = (a + 2) % 3;
+  const int OFFB[4] = {0, -1, -1, 0}, OFFC[4] = {0, 0, -1, -1};
+  int vid[4];
+  float P[4][3];
+  for (int q = 0; q < 4; ++q) {
+    int c[3] = {p[0], p[1], p[2]};
+    c[b] += OFFB[q];
+    c[cc] += OFFC[q];
+    if (c[0] < 0 || c[1] < 0 || c[2] < 0 || c[0] >= g.N || c[1] >= g.N || c[2] >= g.N) {
+      j.ecase[x] = 0;
+      ntri[x] = 0;
+      n3[x] = 0;
+      return;
+    }
+    const int ci = rank_of(j.cmask, j.cprefix, c[0] + g.N * (c[1] + g.N * c[2]));
+    int off[3] = {p[0] - c[0], p[1] - c[1], p[2] - c[2]};
+    const int le = cell_edge(a, off);
+    const int part = (int)((j.cpm[ci] >> (2 * le)) & 3u);
+    vid[q] = (int)j.vbase[ci] + part;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) P[q][k] = (float)(c[k] - p[k]) + j.vloc[3 * vid[q] + k];
+  }
+  const int lower_in = bit_of(j.labels, corner_index(g, p[0], p[1], p[2]));
+  // c1..c4 counter-clockwise about +a; reversed when the inside end is the upper one
+  const int ord[4] = {0, lower_in ? 1 : 3, 2, lower_in ? 3 : 1};
+  float Q[4][3], pin[3] = {0, 0, 0}, pout[3] = {0, 0, 0};
+  (lower_in ? pout : pin)[a] = 1.0f;
+  int4 qd;
+  int* qv = &qd.x;
+  for (int q = 0; q < 4; ++q) {
+    qv[q] = vid[ord[q]];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Q[q][k] = P[ord[q]][k];
+  }
+  // App. A.1.5: vertex k concave against v_out (Eq. A1) or v_in (Eq. A2)
+  int concave[4];
+  for (int k = 0; k < 4; ++k) {
+    const int kp = (k + 3) & 3, kn = (k + 1) & 3;
+    float u0[3], u1[3], u2[3], w0[3], w1[3], w2[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      u0[t] = Q[k][t] - pout[t];
+      u1[t] = Q[kp][t] - pout[t];
+      u2[t] = Q[kn][t] - pout[t];
+      w0[t] = Q[k][t] - pin[t];
+      w1[t] = Q[kp][t] - pin[t];
+      w2[t] = Q[kn][t] - pin[t];
+    }
+    concave[k] = (triple3(u0, u1, u2) < 0.0f) || (triple3(w0, w1, w2) > 0.0f);
+  }
+  int cs = 3;
+  if (!concave[1] && !concave[3]) cs = 1;
+  else if (!concave[0] && !concave[2]) cs = 2;
+  j.ecase[x] = (uint32_t)cs;
+  j.quad[x] = qd;
+  ntri[x] = cs == 3 ? 4u : 2u;
+  n3[x] = cs == 3 ? 1u : 0u;
+}
+
+hipError_t launch_emit_count(Job& j, uint32_t* ntri, uint32_t* n3, hipStream_t s) {
+  if (j.n_edges == 0) return hipSuccess;
+  k_emit_count<<<nblocks(j.n_edges), kBlock, 0, s>>>(j, ntri, n3);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_emit_write(Job j) {
+  const int x = blockIdx.x * kBlock + threadIdx.x;
+  if (x >= j.n_edges) return;
+  const int cs = (int)j.ecase[x];
+  if (cs == 0) return;
+  const int4 qd = j.quad[x];
+  const int t0 = (int)j.tprefix[x];
+  int tri[4][3];
+  int nt = 2;
+  if (cs == 1) {
+    tri[0][0] = qd.x; tri[0][1] = qd.y; tri[0][2] = qd.z;
+    tri[1][0] = qd.x; tri[1][1] = qd.z; tri[1][2] = qd.w;
+  } else if (cs == 2) {
+    tri[0][0] = qd.x; tri[0][1] = qd.y; tri[0][2] = qd.w;
+    tri[1][0] = qd.y; tri[1][1] = qd.z; tri[1][2] = qd.w;
+  } else {
+    const int nvp = (int)j.vbase[j.n_cells];
+    const int ve = nvp + (int)j.c3prefix[x];
+    const int qv[4] = {qd.x, qd.y, qd.z, qd.w};
+    for (int k = 0; k < 4; ++k) {
+      tri[k][0] = ve;
+      tri[k][1] = qv[k];
+      tri[k][2] = qv[(k + 1) & 3];
+    }
+    nt = 4;
+    if (ve < j.cap_v) {
+      int a, p[3];
+      edge_pos(j.g, j.elist[x], a, p);
+      const float t = j.et[x];
+      float gp[3] = {(float)p[0], (float)p[1], (float)p[2]};
+      gp[a] = (float)p[a] + t;
+      float w[3];
+      grid_world(j.g, gp, w);
+      j.out_v[3 * ve] = w[0];
+      j.out_v[3 * ve + 1] = w[1];
+      j.out_v[3 * ve + 2] = w[2];
+      if (j.out_vloc) {
+        j.out_vloc[3 * ve] = a == 0 ? t : 0.0f;
+        j.out_vloc[3 * ve + 1] = a == 1 ? t : 0.0f;
+        j.out_vloc[3 * ve + 2] = a == 2 ? t : 0.0f;
+      }
+      if (j.out_vref) j.out_vref[ve] = corner_index(j.g, p[0], p[1], p[2]);
+    }
+  }
+  for (int k = 0; k < nt; ++k) {
+    if (t0 + k >= j.cap_t) break;
+    j.out_t[3 * (t0 + k)] = tri[k][0];
+    j.out_t[3 * (t0 + k) + 1] = tri[k][1];
+    j.out_t[3 * (t0 + k) + 2] = tri[k][2];
+  }
+}
+
+hipError_t launch_emit_write(Job& j, hipStream_t s) {
+  if (j.n_edges == 0) return hipSuccess;
+  k_emit_write<<<nblocks(j.n_edges), kBlock, 0, s>>>(j);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ field eval
+__global__ __launch_bounds__(256) void k_eval_csg(const float* __restrict__ prims, int np,
+                                                  const float* __restrict__ xyz, int n,
+                                                  float* __restrict__ z) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const float x[3] = {xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]};
+  z[i] = csg_inside(prims, np, x) ? 1.0f : -1.0f;
+}
+
+template <int BF16>
+__global__ __launch_bounds__(256) void k_eval_mlp(Mlp m, const float* __restrict__ xyz, int n,
+                                                  float* __restrict__ z) {
+  __shared__ float act_lds[kBlock / 64][BF16 ? kActVecsBF16 * 4 : kActWords];
+  float* act = act_lds[threadIdx.x >> 6];
+  const int lane = lane_id(), col = lane & 31;
+  const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int nwaves = gridDim.x * (kBlock / 64);
+  for (int t = wave; t * 32 < n; t += nwaves) {
+    const int i = t * 32 + col;
+    const int k = i < n ? i : n - 1;
+    const float x[3] = {xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2]};
+    const float v = BF16 ? mlp_logit_bf16(m, x, reinterpret_cast<v8bf*>(act))
+                         : mlp_logit_fp32(m, x, act);
+    if (i < n && lane < 32) z[i] = v;
+  }
+}
+
+hipError_t launch_eval(int kind, int precision, const float* prims, int np, const Mlp& m,
+                       const float* xyz, int n, float* z, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (kind == 0) {
+    k_eval_csg<<<nblocks(n), kBlock, 0, s>>>(prims, np, xyz, n, z);
+  } else {
+    const int tiles = (n + 31) / 32;
+    const int blocks = tiles / 4 + 1 < 2048 ? tiles / 4 + 1 : 2048;
+    if (precision == 0) k_eval_mlp<0><<<blocks, kBlock, 0, s>>>(m, xyz, n, z);
+    else k_eval_mlp<1><<<blocks, kBlock, 0, s>>>(m, xyz, n, z);
+  }
+  return hipGetLastError();
+}
+
+// R6 partition table: partmap | npart << 24 for each cube configuration
+__global__ void k_partition_table(uint32_t* table) {
+  const int cfg = threadIdx.x;
+  if (cfg >= 256) return;
+  int pm;
+  const int np = cube_partitions(cfg, 0, pm);
+  table[cfg] = (uint32_t)pm | ((uint32_t)np << 24);
+}
+
+hipError_t launch_partition_table(uint32_t* table, hipStream_t s) {
+  k_partition_table<<<1, 256, 0, s>>>(table);
+  return hipGetLastError();
+}
+
+}  // namespace odc

@@ -1,0 +1,55 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and
+exports every function include/odc.h declares; defaults follow the paper."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "odc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(odc_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_declared_symbols():
+    from paper_2409_13418_amd import odc
+    L = odc.load()
+    names = _declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(odc.EXPORTS) == set(names)
+
+
+def test_defaults_follow_the_paper():
+    from paper_2409_13418_amd import odc
+    p = odc.Params()
+    odc.load().odc_params_default(C.byref(p), 128)
+    assert (p.res, p.iters_1d, p.lin1, p.bin1, p.lin2, p.bin2) == (128, 15, 4, 11, 3, 12)
+    assert abs(p.range1 - 0.8) < 1e-7 and abs(p.range2 - math.sqrt(2) / 2) < 1e-7
+    assert abs(p.qef_tau - 1e-2) < 1e-9 and p.fp64_cond == 1e6
+    assert abs(p.guard_logit - 2 * math.atanh(0.02)) < 1e-7
+
+
+def test_status_strings():
+    from paper_2409_13418_amd import odc
+    L = odc.load()
+    assert L.odc_status_string(odc.OK) == b"ok"
+    assert L.odc_status_string(odc.ERR_CAPACITY) == b"output capacity exceeded"
+    assert L.odc_status_string(99) == b"unknown status"
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    from paper_2409_13418_amd import odc
+    with pytest.raises(odc.OdcError):
+        odc._lib_backup = odc._lib
+        try:
+            odc._lib = None
+            odc.load(str(tmp_path / "nope.so"))
+        finally:
+            odc._lib = odc._lib_backup
