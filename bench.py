@@ -8,6 +8,19 @@ occupancy queries included) of that field with its inputs resident in HBM.
 Metric: active cells meshed per second.
 
 Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+
+Other modes (not run by default):
+  --mode batch  64 seeded shapes (32 CSG, 32 MLP fields; res uniform over
+                {64, 96, 128, 192, 256}) meshed as one batch per step,
+                graph-replayed with the autotuned launch shape; reported with
+                the same shapes meshed one at a time on the plain fp32 path.
+  --mode copy   a plain device-to-device copy of --copy-mib MiB, repeated
+                --steps times: the reference kernel that scales the HBM byte
+                counters (FETCH_SIZE, WRITE_SIZE) of a profile.
+  --mode serve  Poisson arrivals (20 requests/s, 50/50 CSG/MLP, res 64/128/
+                256/512 with weights .4/.3/.2/.1) through the continuous-
+                batching server; p50/p99 latency (completion - arrival) and
+                active cells/s over the requests after a 10 s warm-up.
 """
 from __future__ import annotations
 
@@ -61,8 +74,191 @@ def cpu_baseline(field, grid, seconds: float, sub: int = 16, seed: int = 0) -> d
                       f"sphere-surface points, {cells} active cells in {spent:.1f} s"}
 
 
+def _batch_mode(args):
+    """64 shapes per step in one batched, graph-replayed launch."""
+    import torch
+    from paper_2409_13418_amd import odc
+
+    cfgs = I.batch_configs(64, 4000)
+    prec = odc.PREC_BF16_GUARDED if args.precision == "bf16" else odc.PREC_FP32
+    dfs = [odc.DeviceField(f) for f, _ in cfgs]
+    ps = [odc.default_params(g, prec if f.kind == odc.FIELD_MLP else odc.PREC_FP32)
+          for f, g in cfgs]
+    ctx = odc.Context(0)
+    # autotune on the largest MLP shape of the batch
+    big = max((k for k in range(len(cfgs)) if cfgs[k][0].kind == odc.FIELD_MLP),
+              key=lambda k: cfgs[k][1].res)
+    chosen = ctx.autotune(dfs[big], ps[big])
+    ctx.set_graph(True)
+    caps = [(max(4096, 10 * g.res * g.res), max(8192, 20 * g.res * g.res)) for _, g in cfgs]
+    for _ in range(args.warmup):
+        out = ctx.extract_batch(dfs, ps, caps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = ctx.extract_batch(dfs, ps, caps)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    cells = sum(o["n_active_cells"] for o in out)
+    # the same shapes one at a time, plain fp32 path, default launch shape
+    ref = odc.Context(0)
+    ps32 = [odc.default_params(g, odc.PREC_FP32) for _, g in cfgs]
+    for k in range(len(cfgs)):
+        ref.extract(dfs[k], ps32[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    cells32 = 0
+    for k in range(len(cfgs)):
+        cells32 += ref.extract(dfs[k], ps32[k])["n_active_cells"]
+    torch.cuda.synchronize()
+    ms32 = (time.perf_counter() - t1) * 1e3
+    assert cells32 == cells, (cells32, cells)
+    out = {
+        "metric": "active cells meshed/sec, 64-shape batch",
+        "value": cells / (ms / 1e3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16+fp32" if prec == odc.PREC_BF16_GUARDED else "fp32",
+        "data": "synthetic",
+        "config": {"workload": "batch64", "shapes": 64, "seeds": "4000..4063",
+                   "res": [g.res for _, g in cfgs], "precision_mlp": args.precision,
+                   "launch_blocks": list(chosen), "graph": True},
+        "active_cells": cells,
+        "sequential_fp32": {"value": cells / (ms32 / 1e3), "unit": "cells/s", "ms": ms32},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _serve_mode(args):
+    """Poisson request trace through the serving loop."""
+    import threading
+
+    import torch
+    from paper_2409_13418_amd import odc
+
+    warm_s = args.serve_warmup_s
+    rate = args.serve_rate
+    n_warm = int(round(warm_s * rate))
+    trace = I.serve_trace(n_warm + args.serve_requests, rate, 5)
+    prec = odc.PREC_BF16_GUARDED if args.precision == "bf16" else odc.PREC_FP32
+    # a pool of seeded fields per kind (the trace's field seed modulo the pool)
+    pool = 16
+    fields = {}
+    for kind, res, seed in {(k, r, s % pool) for _, k, r, s in trace}:
+        if (kind, seed) not in fields:
+            f = I.csg_random_field(6000 + seed) if kind == 0 else I.mlp_field(6100 + seed)
+            fields[(kind, seed)] = odc.DeviceField(f)
+    params = {}
+    for _, kind, res, _ in trace:
+        if (kind, res) not in params:
+            params[(kind, res)] = odc.default_params(
+                I.unit_grid(res, 15), prec if kind == 1 else odc.PREC_FP32)
+    ctx = odc.Context(0)
+    srv = odc.Server(ctx, int(args.serve_budget_gib * (1 << 30)), lanes=args.serve_lanes,
+                     max_batch=16)
+    free_bufs = {}
+    lock = threading.Lock()
+
+    def take(res):
+        with lock:
+            lst = free_bufs.setdefault(res, [])
+            if lst:
+                return lst.pop()
+        b = odc.OutputBuffers(max(4096, 10 * res * res), max(8192, 20 * res * res))
+        torch.cuda.current_stream().synchronize()  # the allocation is usable by other streams
+        return b
+
+    tickets = []
+    results = []
+    done = threading.Event()
+
+    def waiter():
+        i = 0
+        while True:
+            with lock:
+                if i >= len(tickets):
+                    if done.is_set():
+                        return
+                    t = None
+                else:
+                    t, res, buf = tickets[i]
+            if t is None:
+                time.sleep(0.001)
+                continue
+            r = srv.wait(t)
+            r["res"] = res
+            results.append(r)
+            with lock:
+                free_bufs.setdefault(res, []).append(buf)
+            i += 1
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t_start = time.perf_counter()
+    reset_done = False
+    for i, (at, kind, res, seed) in enumerate(trace):
+        if not reset_done and i == n_warm:
+            srv.reset_stats()
+            reset_done = True
+        delay = at - (time.perf_counter() - t_start)
+        if delay > 0:
+            time.sleep(delay)
+        buf = take(res)
+        t = srv.submit(fields[(kind, seed % pool)], params[(kind, res)], buf)
+        with lock:
+            tickets.append((t, res, buf))
+    done.set()
+    th.join()
+    st = srv.stats()
+    wall = time.perf_counter() - t_start
+    srv.close()
+    bad = [r for r in results if r["status"] != odc.OK]
+    by_res = {}
+    for r in results[n_warm:]:
+        by_res.setdefault(r["res"], []).append(r["latency_ms"])
+    out = {
+        "metric": "serve latency p50/p99 and active cells/sec",
+        "value": st["cells_per_s"], "unit": "cells/s", "n_gpus": 1,
+        "steps": args.serve_requests, "warmup": n_warm, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16+fp32" if prec == odc.PREC_BF16_GUARDED else "fp32", "data": "synthetic",
+        "config": {"workload": "serve_poisson", "rate_per_s": rate, "requests": args.serve_requests,
+                   "warmup_s": warm_s, "mix": "50/50 CSG/MLP", "res_weights":
+                   {"64": 0.4, "128": 0.3, "256": 0.2, "512": 0.1}, "lanes": args.serve_lanes,
+                   "budget_gib": args.serve_budget_gib, "field_pool": pool},
+        "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+        "max_ms": st["max_ms"], "completed": st["completed"], "failed": len(bad),
+        "batches": st["batches"], "window_s": st["window_s"], "wall_s": wall,
+        "arena_peak_gib": st["arena_peak_bytes"] / (1 << 30),
+        "p50_ms_by_res": {str(k): float(np.percentile(v, 50)) for k, v in sorted(by_res.items())},
+        "p99_ms_by_res": {str(k): float(np.percentile(v, 99)) for k, v in sorted(by_res.items())},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _copy_mode(args):
+    import torch
+    n = int(args.copy_mib) << 20
+    x = torch.ones(n, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    print(json.dumps({"mode": "copy", "bytes_read": n, "bytes_written": n, "copies": args.steps,
+                      "GB_per_s": 2 * n / dt / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--mode", choices=("single", "batch", "serve", "copy"), default="single")
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-requests", type=int, default=1200)
+    ap.add_argument("--serve-warmup-s", type=float, default=10.0)
+    ap.add_argument("--serve-lanes", type=int, default=2)
+    ap.add_argument("--serve-budget-gib", type=float, default=24.0)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
@@ -74,6 +270,13 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build meshes on one GPU only; run with --gpus 1"}))
         sys.exit(2)
+
+    if args.mode == "batch":
+        return _batch_mode(args)
+    if args.mode == "serve":
+        return _serve_mode(args)
+    if args.mode == "copy":
+        return _copy_mode(args)
 
     import torch
     from paper_2409_13418_amd import odc

@@ -42,7 +42,7 @@ typedef enum {
   ODC_ERR_CAPACITY = 3,      /* output buffers too small; counts hold the sizes needed */
   ODC_ERR_HIP = 4,           /* a HIP runtime call failed; see odc_last_error */
   ODC_ERR_UNSUPPORTED = 5,   /* a field shape the kernels do not implement */
-  ODC_ERR_BUSY = 6           /* the server queue is full */
+  ODC_ERR_BUSY = 6           /* reserved */
 } odc_status;
 
 typedef struct odc_context odc_context;
@@ -139,9 +139,9 @@ void odc_context_destroy(odc_context* ctx);
 /* Fills the paper's parameters (App. A.1.4, Sec. 5.1) for res cells over [lo, lo+size]^3. */
 void odc_params_default(odc_params* p, int32_t res);
 
-/* Meshes one field.  Enqueues on the context stream; synchronises it once
- * internally after classification to size the active-set scratch.  Returns
- * when the mesh kernels are enqueued.  Errors: INVALID_ARG for bad params,
+/* Meshes one field.  Enqueues the whole path on the context stream with no
+ * host synchronisation (active sets live in context scratch sized from the
+ * resolution; see odc_mesh_sync).  Errors: INVALID_ARG for bad params,
  * NULL pointers with non-zero capacity, or an MLP without weights;
  * UNSUPPORTED for MLP width != 256, depth outside 1..8 or in_dim > 45;
  * OUT_OF_MEMORY; HIP. */
@@ -150,8 +150,36 @@ int32_t odc_mesh_extract(odc_context* ctx, const odc_field* field, const odc_par
 
 /* Waits for the last extract and reports its counts.  ODC_ERR_CAPACITY if
  * the vertices or triangles did not fit: nothing beyond the capacities was
- * written and the counts hold the sizes needed. */
+ * written and the counts hold the sizes needed.  If the active sets outgrew
+ * the context's scratch, the extraction is redone with enough scratch before
+ * returning (the scratch estimate then grows for later calls). */
 int32_t odc_mesh_sync(odc_context* ctx, odc_mesh_counts* counts);
+
+/* Batched meshing: n fields (each with its own params and output buffers) in
+ * one launch per stage -- persistent kernels walk all jobs of the batch, so
+ * many small or uneven shapes fill the GPU together.  Asynchronous; results
+ * are identical to meshing each field alone.  n is 1..1024.  The same errors
+ * as odc_mesh_extract, per job. */
+int32_t odc_mesh_extract_batch(odc_context* ctx, int32_t n, const odc_field* fields,
+                               const odc_params* params, const odc_mesh_buffers* outs);
+/* Waits for the batch; counts[k] for job k.  ODC_ERR_CAPACITY if any job's
+ * outputs did not fit (its counts then hold the sizes needed). */
+int32_t odc_mesh_sync_batch(odc_context* ctx, int32_t n, odc_mesh_counts* counts);
+
+/* Graph replay.  When enabled (and stage timing is off), the launch sequence
+ * of a batch is captured once into a hipGraph and replayed for every later
+ * batch of the same size and field kinds; the kernels read all job data from
+ * device memory, so one graph serves any fields and resolutions. */
+int32_t odc_context_set_graph(odc_context* ctx, int32_t enable);
+
+/* Autotuner: times the extraction of `field` under candidate persistent grid
+ * sizes (grid-wide passes, per-element passes, matrix-core passes), keeps the
+ * fastest of each for this context and writes them to chosen[3] (may be
+ * NULL).  Synchronous. */
+int32_t odc_autotune(odc_context* ctx, const odc_field* field, const odc_params* params,
+                     int32_t* chosen);
+/* Sets the three grid sizes (blocks of 256 threads) directly. */
+int32_t odc_set_launch_config(odc_context* ctx, const int32_t* grid_elem_mlp_blocks);
 
 /* Copies an intermediate array of the last extract (after odc_mesh_sync) into
  * dst (device memory of cap_bytes).  *n receives the element count.
@@ -183,7 +211,7 @@ int32_t odc_field_eval(odc_context* ctx, const odc_field* field, int32_t precisi
  * writes the device time of each stage in milliseconds:
  *  0 (a) corner labels (incl. the fp32 re-evaluation of the bf16 guard band)
  *  1 classification and scans (crossing edges, face pairs, active cells)
- *  2 compaction of the active sets (after one host synchronisation)
+ *  2 compaction of the active sets
  *  3 (b) 1D points          4 (c) 2D points
  *  5 (d) partitions and vertex numbering     6 (d) normals and QEF
  *  7 (e) emission
@@ -191,6 +219,78 @@ int32_t odc_field_eval(odc_context* ctx, const odc_field* field, int32_t precisi
  * off or no extract has completed; CAPACITY when cap < 8. */
 int32_t odc_context_set_timing(odc_context* ctx, int32_t enable);
 int32_t odc_get_stage_times(odc_context* ctx, float* ms, int32_t cap, int32_t* n);
+
+/* ------------------------------------------------------------- serving
+ * A request loop with continuous batching on the context's GPU.  The server
+ * owns n_lanes extraction contexts (each with its own stream) and one device
+ * arena of hbm_budget_bytes for job scratch.  A scheduler thread admits
+ * queued jobs in arrival order into idle lanes as long as each job's scratch
+ * footprint (bit sets over the grid plus its active-set capacity) fits in
+ * the free arena, up to max_batch jobs and max_batch_corners grid corners
+ * per batch (a lone job may exceed the corner limit), and launches them as
+ * one batch (odc_mesh_extract_batch semantics).  Jobs arriving while other
+ * batches run are admitted as lanes and arena memory free up.  A job whose
+ * active sets outgrow the planned capacity is requeued at the head with the
+ * capacity it needed.  The server takes the context's launch configuration
+ * (e.g. after odc_autotune) at creation; the context itself stays free for
+ * other use.
+ *
+ * Every device pointer of a submitted job (field data, output buffers) must
+ * stay valid until odc_server_wait returns for its ticket.  submit, poll,
+ * wait and the statistics calls may come from any host threads; destroy
+ * must not overlap any other call on the server.  destroy waits for the
+ * batches in flight and drops queued jobs. */
+typedef struct odc_server odc_server;
+
+typedef struct {
+  int64_t hbm_budget_bytes;  /* scratch arena (>= 1 MiB) */
+  int32_t n_lanes;           /* batches in flight at once, 1..8; 0 = 2 */
+  int32_t max_batch;         /* jobs per batch; 0 = 16 */
+  int64_t max_batch_corners; /* grid corners per batch; 0 = 2^25 */
+} odc_server_config;
+
+typedef struct {
+  int32_t status;            /* odc_status of the job (CAPACITY: counts hold the sizes needed) */
+  int32_t attempts;          /* launches of the job (> 1 after a scratch overflow) */
+  odc_mesh_counts counts;    /* n_flipped_faces is -1 */
+  double submit_ms;          /* host steady clock, ms since the server started */
+  double admit_ms;           /* last admission into a lane */
+  double done_ms;            /* completion seen by the scheduler */
+} odc_request_result;
+
+typedef struct {
+  int64_t submitted, completed, failed; /* since the last reset */
+  int64_t queued, in_flight;            /* now */
+  int64_t batches;
+  int64_t active_cells;                 /* summed over completed jobs */
+  double p50_ms, p99_ms, mean_ms, max_ms; /* latency = done - submit, nearest rank */
+  double window_s;                      /* from the reset to the last completion */
+  double cells_per_s;                   /* active_cells / window_s */
+  int64_t arena_bytes, arena_peak_bytes;
+} odc_server_stats;
+
+/* Errors: INVALID_ARG for a bad configuration; OUT_OF_MEMORY when the arena
+ * cannot be allocated. */
+int32_t odc_server_create(odc_context* ctx, const odc_server_config* cfg, odc_server** out);
+void odc_server_destroy(odc_server* server);
+const char* odc_server_last_error(const odc_server* server);
+/* Scratch bytes a job would be admitted with. */
+int32_t odc_server_footprint(odc_server* server, const odc_field* field,
+                             const odc_params* params, int64_t* bytes);
+/* Queues one job and returns at once.  Errors: the argument checks of
+ * odc_mesh_extract; OUT_OF_MEMORY when the job's footprint exceeds the
+ * whole arena. */
+int32_t odc_server_submit(odc_server* server, const odc_field* field, const odc_params* params,
+                          const odc_mesh_buffers* out, uint64_t* ticket);
+/* *done = 1 once the job has finished (successfully or not). */
+int32_t odc_server_poll(odc_server* server, uint64_t ticket, int32_t* done);
+/* Blocks until the job has finished, writes its result and releases the
+ * ticket.  The call's own status is INVALID_ARG for an unknown ticket; the
+ * job's status is in result->status. */
+int32_t odc_server_wait(odc_server* server, uint64_t ticket, odc_request_result* result);
+/* Latency and throughput of the jobs submitted since the last reset. */
+int32_t odc_server_get_stats(odc_server* server, odc_server_stats* stats);
+int32_t odc_server_reset_stats(odc_server* server);
 
 #ifdef __cplusplus
 }

@@ -8,11 +8,12 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libodc.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("odc_kernels.hip", "odc_api.hip")]
-HEADERS = [os.path.join(HERE, "csrc", f) for f in ("odc_device.h", "odc_mlp.h", "odc_internal.h")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("odc_kernels.hip", "odc_api.hip", "odc_server.hip")]
+HEADERS = [os.path.join(HERE, "csrc", f) for f in ("odc_device.h", "odc_mlp.h", "odc_job.h", "odc_internal.h",
+                                                       "odc_context.h")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread",
     "-ffp-contract=off", "-fhip-fp32-correctly-rounded-divide-sqrt",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",

@@ -1,51 +1,24 @@
-// C ABI of libodc.so (include/odc.h): context, scratch and stage orchestration.
+// C ABI of libodc.so (include/odc.h): contexts, per-job scratch, batches,
+// graph replay, the autotuner and the stage timers.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
 
 #include <string>
+#include <vector>
 
-#include "../../include/odc.h"
-#include "odc_internal.h"
-
-namespace odc {
-hipError_t launch_partition_table(uint32_t* table, hipStream_t s);
-}
+#include "odc_context.h"
 
 using namespace odc;
 
 namespace {
 
-// Device buffer that only grows.  Growing waits for the stream first, so no
-// kernel still uses the old allocation.
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-};
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
-struct odc_context {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  std::string err;
-  // scratch
-  DevBuf labels, emask, ecount, eprefix, fact, famb, fflip, pcount, pprefix, cmask, ccount,
-      cprefix, scan_tmp, counters, guard, elist, et, ecase, ntri, n3, tprefix, c3prefix, quad,
-      plist, pf, clist, cpm, cnf, npart, vbase, vloc, mlpw, table;
-  // pinned readback: [0..2] active sizes, [3] partition vertices, [4] triangles,
-  // [5] case-3, [6..8] counters
-  uint64_t* host = nullptr;
-  Job job;
-  bool pending = false;
-  int64_t cap_v = 0, cap_t = 0;
-  bool timing = false;
-  hipEvent_t ev[9] = {};
-};
-
-static int32_t fail(odc_context* ctx, int32_t code, const char* fmt, ...) {
+int32_t odc::ctx_fail(odc_context* ctx, int32_t code, const char* fmt, ...) {
   if (ctx) {
     char buf[512];
     va_list ap;
@@ -56,6 +29,7 @@ static int32_t fail(odc_context* ctx, int32_t code, const char* fmt, ...) {
   }
   return code;
 }
+#define fail odc::ctx_fail
 
 #define HIP_TRY(ctx, expr)                                                          \
   do {                                                                              \
@@ -65,10 +39,23 @@ static int32_t fail(odc_context* ctx, int32_t code, const char* fmt, ...) {
                   __FILE__, __LINE__);                                              \
   } while (0)
 
+#define TRY(expr)                \
+  do {                           \
+    int32_t r_ = (expr);         \
+    if (r_ != ODC_OK) return r_; \
+  } while (0)
+
+static void drop_graph(odc_context* ctx) {
+  if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
+  ctx->graph = nullptr;
+  ctx->graph_njobs = -1;
+}
+
 static int32_t ensure(odc_context* ctx, DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (b.bytes >= bytes) return ODC_OK;
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  drop_graph(ctx);  // a captured graph may reference the old allocation
   if (b.p) HIP_TRY(ctx, hipFree(b.p));
   b.p = nullptr;
   b.bytes = 0;
@@ -137,22 +124,29 @@ extern "C" int32_t odc_context_create(int32_t device, void* stream, odc_context*
     delete ctx;
     return ODC_ERR_HIP;
   }
+  int32_t rc = ODC_OK;
   if (stream) {
     ctx->stream = (hipStream_t)stream;
-  } else {
-    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
-      delete ctx;
-      return ODC_ERR_HIP;
-    }
+  } else if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) == hipSuccess) {
     ctx->own_stream = true;
+  } else {
+    rc = ODC_ERR_HIP;
   }
-  if (hipHostMalloc((void**)&ctx->host, 16 * sizeof(uint64_t), hipHostMallocDefault) !=
-      hipSuccess) {
-    odc_context_destroy(ctx);
-    return ODC_ERR_OUT_OF_MEMORY;
-  }
-  memset(ctx->host, 0, 16 * sizeof(uint64_t));
-  int32_t rc = ensure(ctx, ctx->table, 256 * sizeof(uint32_t));
+  if (rc == ODC_OK && hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking) !=
+                          hipSuccess)
+    rc = ODC_ERR_HIP;
+  if (rc == ODC_OK &&
+      (hipHostMalloc((void**)&ctx->hjobs, kMaxJobs * sizeof(Job), hipHostMallocDefault) !=
+           hipSuccess ||
+       hipHostMalloc((void**)&ctx->hweights, kMaxJobs * sizeof(float*), hipHostMallocDefault) !=
+           hipSuccess ||
+       hipHostMalloc((void**)&ctx->hgather, kMaxJobs * 8 * sizeof(unsigned long long),
+                     hipHostMallocDefault) != hipSuccess))
+    rc = ODC_ERR_OUT_OF_MEMORY;
+  if (rc == ODC_OK) rc = ensure(ctx, ctx->table, 256 * sizeof(uint32_t));
+  if (rc == ODC_OK) rc = ensure(ctx, ctx->djobs, kMaxJobs * sizeof(Job));
+  if (rc == ODC_OK) rc = ensure(ctx, ctx->dweights, kMaxJobs * sizeof(float*));
+  if (rc == ODC_OK) rc = ensure(ctx, ctx->dgather, kMaxJobs * 8 * sizeof(unsigned long long));
   if (rc == ODC_OK && launch_partition_table(P<uint32_t>(ctx->table), ctx->stream) != hipSuccess)
     rc = ODC_ERR_HIP;
   if (rc == ODC_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) rc = ODC_ERR_HIP;
@@ -164,27 +158,40 @@ extern "C" int32_t odc_context_create(int32_t device, void* stream, odc_context*
   return ODC_OK;
 }
 
+static void free_buf(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
 extern "C" void odc_context_destroy(odc_context* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  DevBuf* bufs[] = {&ctx->labels, &ctx->emask, &ctx->ecount, &ctx->eprefix, &ctx->fact,
-                    &ctx->famb, &ctx->fflip, &ctx->pcount, &ctx->pprefix, &ctx->cmask,
-                    &ctx->ccount, &ctx->cprefix, &ctx->scan_tmp, &ctx->counters, &ctx->guard,
-                    &ctx->elist, &ctx->et, &ctx->ecase, &ctx->ntri, &ctx->n3, &ctx->tprefix,
-                    &ctx->c3prefix, &ctx->quad, &ctx->plist, &ctx->pf, &ctx->clist, &ctx->cpm,
-                    &ctx->cnf, &ctx->npart, &ctx->vbase, &ctx->vloc, &ctx->mlpw, &ctx->table};
-  for (DevBuf* b : bufs)
-    if (b->p) (void)hipFree(b->p);
-  if (ctx->host) (void)hipHostFree(ctx->host);
+  drop_graph(ctx);
+  for (Slot& s : ctx->slots) {
+    free_buf(s.grid);
+    free_buf(s.active);
+    free_buf(s.mlpw);
+    free_buf(s.guard);
+    free_buf(s.status);
+  }
+  free_buf(ctx->djobs);
+  free_buf(ctx->dweights);
+  free_buf(ctx->dgather);
+  free_buf(ctx->table);
+  if (ctx->hjobs) (void)hipHostFree(ctx->hjobs);
+  if (ctx->hweights) (void)hipHostFree(ctx->hweights);
+  if (ctx->hgather) (void)hipHostFree(ctx->hgather);
   for (hipEvent_t& e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
+  if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
 
-static int32_t validate(odc_context* ctx, const odc_field* f, const odc_params* p,
-                        const odc_mesh_buffers* o) {
+int32_t odc::validate_job(odc_context* ctx, const odc_field* f, const odc_params* p,
+                          const odc_mesh_buffers* o) {
   if (!f || !p || !o) return fail(ctx, ODC_ERR_INVALID_ARG, "NULL field, params or buffers");
   if (p->res < 1 || p->res > kMaxRes)
     return fail(ctx, ODC_ERR_INVALID_ARG, "res %d outside 1..%d", p->res, kMaxRes);
@@ -221,314 +228,434 @@ static int32_t validate(odc_context* ctx, const odc_field* f, const odc_params* 
   return ODC_OK;
 }
 
-#define TRY(expr)                     \
-  do {                                \
-    int32_t r_ = (expr);              \
-    if (r_ != ODC_OK) return r_;      \
-  } while (0)
-
-static int32_t mark(odc_context* ctx, int i) {
-  if (!ctx->timing) return ODC_OK;
-  HIP_TRY(ctx, hipEventRecord(ctx->ev[i], ctx->stream));
-  return ODC_OK;
+// Active-set capacity for a grid of N cells per axis: crossing edges of a
+// surface scale with its area; 12 N^2 leaves a third of headroom over the
+// benchmark fields (5.5 N^2 for the MLP field, 7.3 N^2 for the CSG field),
+// and an overflow grows the scale for the rest of the context's life.
+int odc::estimate_edges(double cap_scale, int N) {
+  const double e = (12.0 * N * N + 4096.0) * cap_scale;
+  const double total = 3.0 * N * (double)(N + 1) * (N + 1);
+  return (int)(e < total ? e : total) + 64;
 }
 
-extern "C" int32_t odc_context_set_timing(odc_context* ctx, int32_t enable) {
-  if (!ctx) return ODC_ERR_INVALID_ARG;
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
-  if (enable && !ctx->ev[0])
-    for (hipEvent_t& e : ctx->ev) HIP_TRY(ctx, hipEventCreate(&e));
-  ctx->timing = enable != 0;
-  return ODC_OK;
-}
+namespace {
 
-extern "C" int32_t odc_get_stage_times(odc_context* ctx, float* ms, int32_t cap, int32_t* n) {
-  if (!ctx || !n) return ODC_ERR_INVALID_ARG;
-  *n = 8;
-  if (!ctx->timing || !ctx->pending)
-    return fail(ctx, ODC_ERR_INVALID_ARG, "stage timing is off or nothing was extracted");
-  if (cap < 8 || !ms) return fail(ctx, ODC_ERR_CAPACITY, "need room for 8 stage times");
-  HIP_TRY(ctx, hipEventSynchronize(ctx->ev[8]));
-  for (int i = 0; i < 8; ++i) HIP_TRY(ctx, hipEventElapsedTime(&ms[i], ctx->ev[i], ctx->ev[i + 1]));
-  return ODC_OK;
-}
-
-// Packs the MLP weights into the fragment orders of the matrix-core
-// evaluators (context scratch) and fills m.
-static int32_t prepare_mlp(odc_context* ctx, const odc_field* f, Mlp& m) {
-  hipStream_t s = ctx->stream;
-  const int kb1f = (f->in_dim + 1) / 2, kb1b = (f->in_dim + 15) / 16, d = f->depth;
-  const size_t n_w1f = (size_t)kb1f * 512, n_whf = (size_t)(d - 1) * kHiddenBlocksF32 * 512;
-  const size_t n_w1b = (size_t)kb1b * 512, n_whb = (size_t)(d - 1) * kHiddenBlocksBF16 * 512;
-  const size_t bytes = (n_w1f + n_whf) * 4 + (n_w1b + n_whb) * 16 + (size_t)(d + 1) * kWidth * 4;
-  TRY(ensure(ctx, ctx->mlpw, bytes));
-  char* base = P<char>(ctx->mlpw);
-  float* w1f = (float*)base;
-  float* whf = w1f + n_w1f;
-  v8bf* w1b = (v8bf*)(whf + n_whf);
-  v8bf* whb = w1b + n_w1b;
-  float* bias = (float*)(whb + n_whb);
-  float* wout = bias + (size_t)d * kWidth;
-  HIP_TRY(ctx, launch_pack_mlp(f->weights, f->in_dim, d, w1f, whf, w1b, whb, bias, wout, s));
-  m.w1f = w1f;
-  m.whf = whf;
-  m.w1b = w1b;
-  m.whb = whb;
-  m.bias = bias;
-  m.wout = wout;
-  m.spheres = f->spheres;
-  m.sdf_gain = f->sdf_gain;
-  m.out_scale = f->out_scale;
-  m.n_spheres = f->n_spheres;
-  m.depth = d;
-  m.in_dim = f->in_dim;
-  m.kb1f = kb1f;
-  m.kb1b = kb1b;
-  // b_out is read back once: the weights are caller data of fixed layout
-  const size_t bout_off = (size_t)kWidth * f->in_dim + kWidth +
-                          (size_t)(d - 1) * (kWidth * kWidth + kWidth) + kWidth;
-  float bout = 0.0f;
-  HIP_TRY(ctx, hipMemcpyAsync(&bout, f->weights + bout_off, sizeof(float),
-                              hipMemcpyDeviceToHost, s));
-  HIP_TRY(ctx, hipStreamSynchronize(s));
-  m.bout = bout;
-  return ODC_OK;
-}
-
-extern "C" int32_t odc_mesh_extract(odc_context* ctx, const odc_field* f, const odc_params* p,
-                                    const odc_mesh_buffers* o) {
-  if (!ctx) return ODC_ERR_INVALID_ARG;
-  TRY(validate(ctx, f, p, o));
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
-  hipStream_t s = ctx->stream;
-  Job& j = ctx->job;
-  j = Job();
+// Scalar fields of a job: grid, field, parameters, bit-set sizes and
+// active-set capacities for ce crossing edges.
+void job_scalars(Job& J, const odc_field* f, const odc_params* p, int ce) {
+  memset(&J, 0, sizeof(J));
   const int N = p->res;
-  j.g.N = N;
-  for (int a = 0; a < 3; ++a) j.g.lo[a] = (float)p->lo[a];
-  j.g.h = (float)(p->size / (double)N);
-  j.g.nc = (N + 1) * (N + 1) * (N + 1);
-  j.g.ea = N * (N + 1) * (N + 1);
-  j.g.fa = (N + 1) * N * N;
-  j.g.ncell = N * N * N;
-  j.kind = f->kind;
-  j.precision = p->precision;
-  j.prims = f->prims;
-  j.n_prims = f->n_prims;
-  j.iters_1d = p->iters_1d;
-  j.lin1 = p->lin1;
-  j.bin1 = p->bin1;
-  j.lin2 = p->lin2;
-  j.bin2 = p->bin2;
-  j.range1 = p->range1;
-  j.range2 = p->range2;
-  j.qef_tau = p->qef_tau;
-  j.guard_logit = p->guard_logit;
-  j.fp64_cond = p->fp64_cond;
+  J.g.N = N;
+  for (int a = 0; a < 3; ++a) J.g.lo[a] = (float)p->lo[a];
+  J.g.h = (float)(p->size / (double)N);
+  J.g.nc = (N + 1) * (N + 1) * (N + 1);
+  J.g.ea = N * (N + 1) * (N + 1);
+  J.g.fa = (N + 1) * N * N;
+  J.g.ncell = N * N * N;
+  J.kind = f->kind;
+  J.precision = f->kind == ODC_FIELD_MLP ? p->precision : 0;
+  J.prims = f->prims;
+  J.n_prims = f->n_prims;
+  J.iters_1d = p->iters_1d;
+  J.lin1 = p->lin1;
+  J.bin1 = p->bin1;
+  J.lin2 = p->lin2;
+  J.bin2 = p->bin2;
+  J.range1 = p->range1;
+  J.range2 = p->range2;
+  J.qef_tau = p->qef_tau;
+  J.guard_logit = p->guard_logit;
+  J.fp64_cond = p->fp64_cond;
+  J.nw_c = (J.g.nc + 31) / 32;
+  J.nw_e = (3 * J.g.ea + 31) / 32;
+  J.nw_f = (3 * J.g.fa + 31) / 32;
+  J.nw_cell = (J.g.ncell + 31) / 32;
+  J.cap_edges = ce;
+  J.cap_pairs = 2 * ce + 64;
+  J.cap_cells = ce + ce / 2 + 64;
+}
 
-  const int nw_c = (j.g.nc + 31) / 32;
-  const int nw_e = (3 * j.g.ea + 31) / 32;
-  const int nw_f = (3 * j.g.fa + 31) / 32;
-  const int nw_cell = (j.g.ncell + 31) / 32;
-  int nw_max = nw_e > nw_f ? nw_e : nw_f;
-  if (nw_cell > nw_max) nw_max = nw_cell;
+// Byte sizes of a job's scratch regions (each a multiple of 256).
+struct Layout {
+  size_t grid[13];
+  size_t active[16];
+  size_t grid_total = 0, active_total = 0;
+  size_t mlpw = 0, guard = 0, status = 0;
+  int guard_cap = 0;
+  size_t n_w1f = 0, n_whf = 0, n_w1b = 0, n_whb = 0;
+  size_t total() const { return grid_total + active_total + mlpw + guard + status; }
+};
 
-  TRY(ensure(ctx, ctx->labels, (size_t)nw_c * 4));
-  TRY(ensure(ctx, ctx->emask, (size_t)nw_e * 4));
-  TRY(ensure(ctx, ctx->ecount, (size_t)nw_e * 4));
-  TRY(ensure(ctx, ctx->eprefix, (size_t)(nw_e + 1) * 4));
-  TRY(ensure(ctx, ctx->fact, (size_t)nw_f * 4));
-  TRY(ensure(ctx, ctx->famb, (size_t)nw_f * 4));
-  TRY(ensure(ctx, ctx->fflip, (size_t)nw_f * 4));
-  TRY(ensure(ctx, ctx->pcount, (size_t)nw_f * 4));
-  TRY(ensure(ctx, ctx->pprefix, (size_t)(nw_f + 1) * 4));
-  TRY(ensure(ctx, ctx->cmask, (size_t)nw_cell * 4));
-  TRY(ensure(ctx, ctx->ccount, (size_t)nw_cell * 4));
-  TRY(ensure(ctx, ctx->cprefix, (size_t)(nw_cell + 1) * 4));
-  TRY(ensure(ctx, ctx->counters, 4 * sizeof(unsigned long long)));
-  j.labels = P<uint32_t>(ctx->labels);
-  j.emask = P<uint32_t>(ctx->emask);
-  j.eprefix = P<uint32_t>(ctx->eprefix);
-  j.fact = P<uint32_t>(ctx->fact);
-  j.famb = P<uint32_t>(ctx->famb);
-  j.fflip = P<uint32_t>(ctx->fflip);
-  j.pprefix = P<uint32_t>(ctx->pprefix);
-  j.cmask = P<uint32_t>(ctx->cmask);
-  j.cprefix = P<uint32_t>(ctx->cprefix);
-  j.counters = P<unsigned long long>(ctx->counters);
-
+Layout job_layout(const Job& J, const odc_field* f, bool guard_full) {
+  Layout L;
+  int nscan = J.nw_e;
+  const int others[4] = {J.nw_f, J.nw_cell, J.cap_edges + 1, J.cap_cells + 1};
+  for (int v : others) nscan = v > nscan ? v : nscan;
+  L.grid[0] = align_up((size_t)J.nw_c * 4);                 // labels
+  L.grid[1] = L.grid[2] = align_up((size_t)J.nw_e * 4);     // emask, ecount
+  L.grid[3] = align_up((size_t)(J.nw_e + 1) * 4);           // eprefix
+  L.grid[4] = L.grid[5] = L.grid[6] = L.grid[7] = align_up((size_t)J.nw_f * 4);
+  L.grid[8] = align_up((size_t)(J.nw_f + 1) * 4);
+  L.grid[9] = L.grid[10] = align_up((size_t)J.nw_cell * 4);
+  L.grid[11] = align_up((size_t)(J.nw_cell + 1) * 4);
+  L.grid[12] = align_up((size_t)((nscan + 1023) / 1024 + 2) * 4);
+  for (size_t x : L.grid) L.grid_total += x;
+  const size_t ne = (size_t)J.cap_edges, np = (size_t)J.cap_pairs, nc = (size_t)J.cap_cells;
+  const size_t asz[16] = {align_up(ne * 4),          align_up(ne * 4),
+                          align_up(ne * 4),          align_up(ne * 4),
+                          align_up(ne * 4),          align_up((ne + 1) * 4),
+                          align_up((ne + 1) * 4),    align_up(ne * sizeof(int4)),
+                          align_up(np * 4),          align_up(np * sizeof(double2)),
+                          align_up(nc * 4),          align_up(nc * 4),
+                          align_up(nc * 4),          align_up(nc * 4),
+                          align_up((nc + 1) * 4),    align_up(nc * 12 * sizeof(float))};
+  for (int i = 0; i < 16; ++i) {
+    L.active[i] = asz[i];
+    L.active_total += asz[i];
+  }
+  L.status = align_up(4 * sizeof(unsigned long long));
   if (f->kind == ODC_FIELD_MLP) {
-    TRY(prepare_mlp(ctx, f, j.mlp));
-    if (p->precision == ODC_PREC_BF16_GUARDED) {
-      TRY(ensure(ctx, ctx->guard, (size_t)j.g.nc * 4));
-      j.guard_list = P<uint32_t>(ctx->guard);
-      j.guard_cap = j.g.nc;
+    const int kb1f = (f->in_dim + 1) / 2, kb1b = (f->in_dim + 15) / 16, d = f->depth;
+    L.n_w1f = (size_t)kb1f * 512;
+    L.n_whf = ((size_t)(d - 1) * kHiddenBlocksF32 + kPrefetchF32) * 512;  // + ring overrun
+    L.n_w1b = (size_t)kb1b * 512;
+    L.n_whb = ((size_t)(d - 1) * kHiddenBlocksBF16 + kPrefetchBF16) * 512;  // + ring overrun
+    L.mlpw = align_up((L.n_w1f + L.n_whf) * 4 + (L.n_w1b + L.n_whb) * 16 +
+                      (size_t)(d + 1) * kWidth * 4);
+    if (J.precision == ODC_PREC_BF16_GUARDED) {
+      // corners in the guard band are ~1% of a grid; the queue holds 1/16 of
+      // the corners unless an earlier run of this job overflowed it
+      L.guard_cap = guard_full ? J.g.nc : (J.g.nc / 16 > 4096 ? J.g.nc / 16 : J.g.nc);
+      L.guard = align_up((size_t)L.guard_cap * 4);
     }
   }
-  HIP_TRY(ctx, hipMemsetAsync(j.counters, 0, 4 * sizeof(unsigned long long), s));
+  return L;
+}
 
-  // (a) corner labels, then classification and the three scans
-  TRY(mark(ctx, 0));
-  HIP_TRY(ctx, launch_labels(j, s));
-  TRY(mark(ctx, 1));
-  TRY(ensure(ctx, ctx->scan_tmp, scan_tmp_words(nw_max) * 4));
-  uint32_t* tmp = P<uint32_t>(ctx->scan_tmp);
-  HIP_TRY(ctx, launch_classify(j, P<uint32_t>(ctx->ecount), P<uint32_t>(ctx->pcount),
-                               P<uint32_t>(ctx->ccount), P<uint32_t>(ctx->table), s));
-  HIP_TRY(ctx, scan_exclusive(P<uint32_t>(ctx->ecount), j.eprefix, nw_e, tmp, s));
-  HIP_TRY(ctx, scan_exclusive(P<uint32_t>(ctx->pcount), j.pprefix, nw_f, tmp, s));
-  HIP_TRY(ctx, scan_exclusive(P<uint32_t>(ctx->ccount), j.cprefix, nw_cell, tmp, s));
-  TRY(mark(ctx, 2));
-  uint32_t tot[3];
-  HIP_TRY(ctx, hipMemcpyAsync(&tot[0], j.eprefix + nw_e, 4, hipMemcpyDeviceToHost, s));
-  HIP_TRY(ctx, hipMemcpyAsync(&tot[1], j.pprefix + nw_f, 4, hipMemcpyDeviceToHost, s));
-  HIP_TRY(ctx, hipMemcpyAsync(&tot[2], j.cprefix + nw_cell, 4, hipMemcpyDeviceToHost, s));
-  HIP_TRY(ctx, hipStreamSynchronize(s));
-  j.n_edges = (int)tot[0];
-  j.n_pairs = (int)tot[1];
-  j.n_cells = (int)tot[2];
+// Points the job's arrays into its scratch regions.
+void job_bind(Job& J, const Layout& L, const odc_field* f, char* grid, char* active, char* mlpw,
+              char* guard, char* status) {
+  uint32_t** gp[13] = {&J.labels, &J.emask, &J.ecount, &J.eprefix, &J.fact, &J.famb,
+                       &J.fflip, &J.pcount, &J.pprefix, &J.cmask, &J.ccount, &J.cprefix,
+                       &J.scan_tmp};
+  size_t off = 0;
+  for (int i = 0; i < 13; ++i) {
+    *gp[i] = (uint32_t*)(grid + off);
+    off += L.grid[i];
+  }
+  void** ap[16] = {(void**)&J.elist,    (void**)&J.et,    (void**)&J.ecase, (void**)&J.ntri,
+                   (void**)&J.n3,       (void**)&J.tprefix, (void**)&J.c3prefix,
+                   (void**)&J.quad,     (void**)&J.plist, (void**)&J.pf,    (void**)&J.clist,
+                   (void**)&J.cpm,      (void**)&J.cnf,   (void**)&J.npart, (void**)&J.vbase,
+                   (void**)&J.vloc};
+  off = 0;
+  for (int i = 0; i < 16; ++i) {
+    *ap[i] = active + off;
+    off += L.active[i];
+  }
+  J.status = (unsigned long long*)status;
+  if (f->kind == ODC_FIELD_MLP) {
+    const int d = f->depth;
+    float* w1f = (float*)mlpw;
+    float* whf = w1f + L.n_w1f;
+    v8bf* w1b = (v8bf*)(whf + L.n_whf);
+    v8bf* whb = w1b + L.n_w1b;
+    float* bias = (float*)(whb + L.n_whb);
+    Mlp& m = J.mlp;
+    m.w1f = w1f;
+    m.whf = whf;
+    m.w1b = w1b;
+    m.whb = whb;
+    m.bias = bias;
+    m.wout = bias + (size_t)d * kWidth;
+    m.spheres = f->spheres;
+    m.bout = f->weights + (size_t)kWidth * f->in_dim + kWidth +
+             (size_t)(d - 1) * (kWidth * kWidth + kWidth) + kWidth;
+    m.sdf_gain = f->sdf_gain;
+    m.out_scale = f->out_scale;
+    m.n_spheres = f->n_spheres;
+    m.depth = d;
+    m.in_dim = f->in_dim;
+    m.kb1f = (f->in_dim + 1) / 2;
+    m.kb1b = (f->in_dim + 15) / 16;
+    if (J.precision == ODC_PREC_BF16_GUARDED) {
+      J.guard_list = (uint32_t*)guard;
+      J.guard_cap = L.guard_cap;
+    }
+  }
+}
 
-  const size_t ne = (size_t)j.n_edges + 1, np = (size_t)j.n_pairs + 1,
-               nc = (size_t)j.n_cells + 1;
-  TRY(ensure(ctx, ctx->elist, ne * 4));
-  TRY(ensure(ctx, ctx->et, ne * 4));
-  TRY(ensure(ctx, ctx->ecase, ne * 4));
-  TRY(ensure(ctx, ctx->ntri, ne * 4));
-  TRY(ensure(ctx, ctx->n3, ne * 4));
-  TRY(ensure(ctx, ctx->tprefix, (ne + 1) * 4));
-  TRY(ensure(ctx, ctx->c3prefix, (ne + 1) * 4));
-  TRY(ensure(ctx, ctx->quad, ne * sizeof(int4)));
-  TRY(ensure(ctx, ctx->plist, np * 4));
-  TRY(ensure(ctx, ctx->pf, np * sizeof(double2)));
-  TRY(ensure(ctx, ctx->clist, nc * 4));
-  TRY(ensure(ctx, ctx->cpm, nc * 4));
-  TRY(ensure(ctx, ctx->cnf, nc * 4));
-  TRY(ensure(ctx, ctx->npart, nc * 4));
-  TRY(ensure(ctx, ctx->vbase, (nc + 1) * 4));
-  TRY(ensure(ctx, ctx->vloc, nc * 4 * 3 * sizeof(float)));
-  TRY(ensure(ctx, ctx->scan_tmp, scan_tmp_words((int)(ne > nc ? ne : nc)) * 4));
-  tmp = P<uint32_t>(ctx->scan_tmp);
-  j.elist = P<int>(ctx->elist);
-  j.et = P<float>(ctx->et);
-  j.ecase = P<uint32_t>(ctx->ecase);
-  j.tprefix = P<uint32_t>(ctx->tprefix);
-  j.c3prefix = P<uint32_t>(ctx->c3prefix);
-  j.quad = P<int4>(ctx->quad);
-  j.plist = P<int>(ctx->plist);
-  j.pf = P<double2>(ctx->pf);
-  j.clist = P<int>(ctx->clist);
-  j.cpm = P<uint32_t>(ctx->cpm);
-  j.cnf = P<uint32_t>(ctx->cnf);
-  j.vbase = P<uint32_t>(ctx->vbase);
-  j.vloc = P<float>(ctx->vloc);
-  j.out_v = o->vertices;
-  j.cap_v = o->cap_vertices;
-  j.out_t = o->triangles;
-  j.cap_t = o->cap_triangles;
-  j.out_vloc = o->vertices_local;
-  j.out_vref = o->vertex_ref;
+}  // namespace
 
-  HIP_TRY(ctx, launch_compact(j, s));
-  TRY(mark(ctx, 3));
-  // (b) 1D points, (c) 2D points
-  HIP_TRY(ctx, launch_bisect(j, s));
-  TRY(mark(ctx, 4));
-  HIP_TRY(ctx, launch_search2d(j, s));
-  TRY(mark(ctx, 5));
-  // (d) partitions, vertex numbering, QEF
-  HIP_TRY(ctx, launch_cell_count(j, P<uint32_t>(ctx->npart), P<uint32_t>(ctx->table), s));
-  HIP_TRY(ctx, scan_exclusive(P<uint32_t>(ctx->npart), j.vbase, j.n_cells, tmp, s));
-  TRY(mark(ctx, 6));
-  HIP_TRY(ctx, launch_cell_qef(j, s));
-  TRY(mark(ctx, 7));
-  // (e) emission
-  HIP_TRY(ctx, launch_emit_count(j, P<uint32_t>(ctx->ntri), P<uint32_t>(ctx->n3), s));
-  HIP_TRY(ctx, scan_exclusive(P<uint32_t>(ctx->ntri), j.tprefix, j.n_edges, tmp, s));
-  HIP_TRY(ctx, scan_exclusive(P<uint32_t>(ctx->n3), j.c3prefix, j.n_edges, tmp, s));
-  HIP_TRY(ctx, launch_emit_write(j, s));
-  TRY(mark(ctx, 8));
+size_t odc::job_scratch_bytes(const odc_field* f, const odc_params* p, int cap_edges,
+                              bool guard_full) {
+  Job J;
+  job_scalars(J, f, p, cap_edges);
+  return job_layout(J, f, guard_full).total();
+}
 
-  uint64_t* h = ctx->host;
-  memset(h, 0, 16 * sizeof(uint64_t));
-  h[0] = tot[0];
-  h[1] = tot[1];
-  h[2] = tot[2];
-  HIP_TRY(ctx, hipMemcpyAsync(&h[3], j.vbase + j.n_cells, 4, hipMemcpyDeviceToHost, s));
-  HIP_TRY(ctx, hipMemcpyAsync(&h[4], j.tprefix + j.n_edges, 4, hipMemcpyDeviceToHost, s));
-  HIP_TRY(ctx, hipMemcpyAsync(&h[5], j.c3prefix + j.n_edges, 4, hipMemcpyDeviceToHost, s));
-  HIP_TRY(ctx, hipMemcpyAsync(&h[6], j.counters, 3 * sizeof(unsigned long long),
-                              hipMemcpyDeviceToHost, s));
-  ctx->pending = true;
-  ctx->cap_v = o->cap_vertices;
-  ctx->cap_t = o->cap_triangles;
+// Fills job k (host mirror) and points it into its slot's scratch: the
+// context's own growing buffers, or the slot's block of a server arena.
+static int32_t setup_job(odc_context* ctx, int k, const odc_field* f, const odc_params* p,
+                         const odc_mesh_buffers* o, int cap_edges_min) {
+  Slot& S = ctx->slots[k];
+  Job& J = ctx->hjobs[k];
+  const int N = p->res;
+  int ce;
+  if (S.ext) {
+    ce = S.ext_cap_edges;
+  } else {
+    ce = estimate_edges(ctx->cap_scale, N);
+    if (ce < cap_edges_min) ce = cap_edges_min;
+    const int all = 3 * N * (N + 1) * (N + 1) + 64;
+    if (ce < S.cap_edges && S.cap_edges <= all) ce = S.cap_edges;
+    S.cap_edges = ce;
+  }
+  job_scalars(J, f, p, ce);
+  const Layout L = job_layout(J, f, S.guard_full);
+  if (S.ext) {
+    if (L.total() > S.ext_bytes)
+      return fail(ctx, ODC_ERR_OUT_OF_MEMORY, "job needs %zu bytes of scratch, block has %zu",
+                  L.total(), S.ext_bytes);
+    char* b = S.ext;
+    job_bind(J, L, f, b, b + L.grid_total, b + L.grid_total + L.active_total,
+             b + L.grid_total + L.active_total + L.mlpw,
+             b + L.grid_total + L.active_total + L.mlpw + L.guard);
+  } else {
+    TRY(ensure(ctx, S.grid, L.grid_total));
+    TRY(ensure(ctx, S.active, L.active_total));
+    TRY(ensure(ctx, S.status, L.status));
+    if (L.mlpw) TRY(ensure(ctx, S.mlpw, L.mlpw));
+    if (L.guard) TRY(ensure(ctx, S.guard, L.guard));
+    job_bind(J, L, f, P<char>(S.grid), P<char>(S.active), P<char>(S.mlpw), P<char>(S.guard),
+             P<char>(S.status));
+  }
+  ctx->hweights[k] = f->kind == ODC_FIELD_MLP ? f->weights : nullptr;
+  if (o) {
+    J.out_v = o->vertices;
+    J.cap_v = o->cap_vertices;
+    J.out_t = o->triangles;
+    J.cap_t = o->cap_triangles;
+    J.out_vloc = o->vertices_local;
+    J.out_vref = o->vertex_ref;
+  }
   return ODC_OK;
 }
 
-// number of set bits in the flip words (read once per sync; diagnostics only)
-static int32_t count_flips(odc_context* ctx, int64_t* out) {
-  const Job& j = ctx->job;
-  const int nw_f = (3 * j.g.fa + 31) / 32;
-  std::string tmp;
-  uint32_t* host = (uint32_t*)malloc((size_t)nw_f * 4);
-  if (!host) return fail(ctx, ODC_ERR_OUT_OF_MEMORY, "host allocation failed");
-  hipError_t e = hipMemcpy(host, j.fflip, (size_t)nw_f * 4, hipMemcpyDeviceToHost);
-  if (e != hipSuccess) {
-    free(host);
-    return fail(ctx, ODC_ERR_HIP, "flip readback: %s", hipGetErrorString(e));
+static PipelineShape shape_of(odc_context* ctx, int n) {
+  PipelineShape sh;
+  for (int k = 0; k < n; ++k) {
+    const Job& J = ctx->hjobs[k];
+    if (J.kind == 0) sh.any_csg = true;
+    if (J.kind == 1) {
+      sh.any_mlp = true;
+      if (J.precision == 0) sh.any_mlp_fp32 = true;
+      else sh.any_mlp_bf16 = true;
+    }
   }
+  return sh;
+}
+
+static bool same_shape(const PipelineShape& a, const PipelineShape& b) {
+  return a.any_csg == b.any_csg && a.any_mlp == b.any_mlp && a.any_mlp_fp32 == b.any_mlp_fp32 &&
+         a.any_mlp_bf16 == b.any_mlp_bf16;
+}
+static bool same_cfg(const LaunchCfg& a, const LaunchCfg& b) {
+  return a.grid_blocks == b.grid_blocks && a.elem_blocks == b.elem_blocks &&
+         a.mlp_blocks == b.mlp_blocks && a.scan_blocks == b.scan_blocks &&
+         a.pack_blocks == b.pack_blocks;
+}
+
+// Uploads the job array and launches the whole path for n jobs: directly, or
+// by replaying a captured graph (the kernels read everything from the job
+// array, so one graph serves every batch of the same size and kinds).
+static int32_t run_batch(odc_context* ctx, int n) {
+  hipStream_t s = ctx->stream;
+  const Job* d = P<Job>(ctx->djobs);
+  const float* const* dw = P<const float*>(ctx->dweights);
+  HIP_TRY(ctx, hipMemcpyAsync(P<Job>(ctx->djobs), ctx->hjobs, n * sizeof(Job),
+                              hipMemcpyHostToDevice, s));
+  HIP_TRY(ctx, hipMemcpyAsync(P<const float*>(ctx->dweights), ctx->hweights,
+                              n * sizeof(float*), hipMemcpyHostToDevice, s));
+  const PipelineShape sh = shape_of(ctx, n);
+  if (ctx->use_graph && !ctx->timing) {
+    const void* ptrs[3] = {ctx->djobs.p, ctx->dweights.p, ctx->table.p};
+    const bool reuse = ctx->graph && ctx->graph_njobs == n && same_shape(ctx->graph_shape, sh) &&
+                       same_cfg(ctx->graph_cfg, ctx->cfg) && ptrs[0] == ctx->graph_ptrs[0] &&
+                       ptrs[1] == ctx->graph_ptrs[1] && ptrs[2] == ctx->graph_ptrs[2];
+    if (!reuse) {
+      drop_graph(ctx);
+      hipGraph_t g = nullptr;
+      HIP_TRY(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+      hipError_t le = launch_pipeline(d, n, sh, dw, P<uint32_t>(ctx->table), ctx->cfg, nullptr,
+                                      ctx->capture_stream);
+      hipError_t ce = hipStreamEndCapture(ctx->capture_stream, &g);
+      if (le != hipSuccess || ce != hipSuccess)
+        return fail(ctx, ODC_ERR_HIP, "graph capture failed: %s / %s", hipGetErrorString(le),
+                    hipGetErrorString(ce));
+      hipError_t ie = hipGraphInstantiate(&ctx->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess) {
+        ctx->graph = nullptr;
+        return fail(ctx, ODC_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(ie));
+      }
+      ctx->graph_njobs = n;
+      ctx->graph_shape = sh;
+      ctx->graph_cfg = ctx->cfg;
+      for (int i = 0; i < 3; ++i) ctx->graph_ptrs[i] = ptrs[i];
+    }
+    HIP_TRY(ctx, hipGraphLaunch(ctx->graph, s));
+  } else {
+    HIP_TRY(ctx, launch_pipeline(d, n, sh, dw, P<uint32_t>(ctx->table), ctx->cfg,
+                                 ctx->timing ? ctx->ev : nullptr, s));
+  }
+  HIP_TRY(ctx, launch_gather(d, n, P<unsigned long long>(ctx->dgather), s));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->hgather, P<unsigned long long>(ctx->dgather),
+                              n * 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  return ODC_OK;
+}
+
+int32_t odc::enqueue_batch(odc_context* ctx, int n, const odc_field* fields,
+                           const odc_params* params, const odc_mesh_buffers* outs) {
+  if (!ctx) return ODC_ERR_INVALID_ARG;
+  if (n < 1 || n > kMaxJobs) return fail(ctx, ODC_ERR_INVALID_ARG, "batch size %d", n);
+  if (!fields || !params || !outs) return fail(ctx, ODC_ERR_INVALID_ARG, "NULL arrays");
+  for (int k = 0; k < n; ++k) TRY(validate_job(ctx, &fields[k], &params[k], &outs[k]));
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  // the host mirrors are reused: wait for the previous batch's uploads
+  if (ctx->pending) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if ((int)ctx->slots.size() < n) ctx->slots.resize(n);
+  for (int k = 0; k < n; ++k) TRY(setup_job(ctx, k, &fields[k], &params[k], &outs[k], 0));
+  TRY(run_batch(ctx, n));
+  ctx->pending = n;
+  ctx->p_fields.assign(fields, fields + n);
+  ctx->p_params.assign(params, params + n);
+  ctx->p_outs.assign(outs, outs + n);
+  return ODC_OK;
+}
+
+extern "C" int32_t odc_mesh_extract(odc_context* ctx, const odc_field* field,
+                                    const odc_params* params, const odc_mesh_buffers* out) {
+  return enqueue_batch(ctx, 1, field, params, out);
+}
+
+extern "C" int32_t odc_mesh_extract_batch(odc_context* ctx, int32_t n, const odc_field* fields,
+                                          const odc_params* params,
+                                          const odc_mesh_buffers* outs) {
+  return enqueue_batch(ctx, n, fields, params, outs);
+}
+
+bool odc::job_overflowed(const odc_context* ctx, int k) {
+  return (ctx->hgather[8 * k + 7] >> 32) != 0;
+}
+
+int odc::needed_edges(const odc_context* ctx, int k, bool* guard_over) {
+  const unsigned long long* o = ctx->hgather + 8 * k;
+  if (guard_over) *guard_over = o[6] > (unsigned long long)ctx->hjobs[k].guard_cap;
+  long long need = (long long)o[0];
+  if ((long long)((o[1] + 1) / 2) > need) need = (long long)((o[1] + 1) / 2);
+  if ((long long)(o[2] * 2 / 3) > need) need = (long long)(o[2] * 2 / 3);
+  need += need / 8 + 64;
+  const long long all = 3LL * ctx->hjobs[k].g.ea + 64;
+  return (int)(need < all ? need : all);
+}
+
+// Waits for the pending batch; a job whose active sets outgrew its scratch is
+// given room for what it needed and the batch runs again.
+static int32_t finish(odc_context* ctx) {
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  for (int attempt = 0;; ++attempt) {
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    const int n = ctx->pending;
+    bool over = false;
+    for (int k = 0; k < n; ++k) over |= job_overflowed(ctx, k);
+    if (!over) return ODC_OK;
+    if (attempt >= 2) return fail(ctx, ODC_ERR_OUT_OF_MEMORY, "scratch overflow persists");
+    for (int k = 0; k < n; ++k) {
+      bool gover = false;
+      const int need = needed_edges(ctx, k, &gover);
+      if (gover) ctx->slots[k].guard_full = true;
+      const double est = 12.0 * ctx->p_params[k].res * ctx->p_params[k].res + 4096.0;
+      if (need > est * ctx->cap_scale) ctx->cap_scale = need / est;
+      TRY(setup_job(ctx, k, &ctx->p_fields[k], &ctx->p_params[k], &ctx->p_outs[k], need));
+    }
+    TRY(run_batch(ctx, n));
+  }
+}
+
+void odc::fill_counts(const odc_context* ctx, int k, odc_mesh_counts* c) {
+  const unsigned long long* o = ctx->hgather + 8 * k;
+  const Job& J = ctx->hjobs[k];
+  memset(c, 0, sizeof(*c));
+  c->n_active_edges = (int64_t)o[0];
+  c->n_pairs = (int64_t)o[1];
+  c->n_active_cells = (int64_t)o[2];
+  c->n_case3 = (int64_t)o[5];
+  c->n_vertices = (int64_t)o[3] + c->n_case3;
+  c->n_triangles = (int64_t)o[4];
+  c->n_guard_corners = (int64_t)o[6];
+  c->n_fp64_cells = (int64_t)(o[7] & 0xFFFFFFFFull);
+  const int64_t per_pair = 1 + (J.lin1 + J.bin1) + 2 * (J.lin2 + J.bin2);
+  c->n_queries = (int64_t)J.g.nc + c->n_guard_corners + c->n_active_edges * J.iters_1d +
+                 c->n_pairs * per_pair;
+  c->n_flipped_faces = -1;
+}
+
+static int32_t count_flips(odc_context* ctx, int k, int64_t* out) {
+  const Job& J = ctx->hjobs[k];
+  std::vector<uint32_t> host((size_t)J.nw_f);
+  HIP_TRY(ctx, hipMemcpy(host.data(), J.fflip, (size_t)J.nw_f * 4, hipMemcpyDeviceToHost));
   int64_t n = 0;
-  for (int i = 0; i < nw_f; ++i) n += __builtin_popcount(host[i]);
-  free(host);
+  for (uint32_t w : host) n += __builtin_popcount(w);
   *out = n;
   return ODC_OK;
 }
 
+extern "C" int32_t odc_mesh_sync_batch(odc_context* ctx, int32_t n, odc_mesh_counts* counts) {
+  if (!ctx || !counts) return ODC_ERR_INVALID_ARG;
+  if (!ctx->pending) return fail(ctx, ODC_ERR_INVALID_ARG, "no extract to wait for");
+  if (n != ctx->pending)
+    return fail(ctx, ODC_ERR_INVALID_ARG, "pending batch has %d jobs", ctx->pending);
+  TRY(finish(ctx));
+  int32_t rc = ODC_OK;
+  for (int k = 0; k < n; ++k) {
+    fill_counts(ctx, k, &counts[k]);
+    if (counts[k].n_vertices > ctx->p_outs[k].cap_vertices ||
+        counts[k].n_triangles > ctx->p_outs[k].cap_triangles)
+      rc = fail(ctx, ODC_ERR_CAPACITY, "job %d needs %lld vertices and %lld triangles", k,
+                (long long)counts[k].n_vertices, (long long)counts[k].n_triangles);
+  }
+  return rc;
+}
+
 extern "C" int32_t odc_mesh_sync(odc_context* ctx, odc_mesh_counts* c) {
   if (!ctx || !c) return ODC_ERR_INVALID_ARG;
-  if (!ctx->pending) return fail(ctx, ODC_ERR_INVALID_ARG, "no extract to wait for");
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  const uint64_t* h = ctx->host;
-  const Job& j = ctx->job;
-  memset(c, 0, sizeof(*c));
-  c->n_active_edges = (int64_t)h[0];
-  c->n_pairs = (int64_t)h[1];
-  c->n_active_cells = (int64_t)h[2];
-  c->n_case3 = (int64_t)h[5];
-  c->n_vertices = (int64_t)h[3] + c->n_case3;
-  c->n_triangles = (int64_t)h[4];
-  c->n_guard_corners = (int64_t)h[6];
-  c->n_fp64_cells = (int64_t)h[7];
-  const int64_t per_pair = 1 + (j.lin1 + j.bin1) + 2 * (j.lin2 + j.bin2);
-  c->n_queries = (int64_t)j.g.nc + c->n_guard_corners + c->n_active_edges * j.iters_1d +
-                 c->n_pairs * per_pair;
-  TRY(count_flips(ctx, &c->n_flipped_faces));
-  if (c->n_vertices > ctx->cap_v || c->n_triangles > ctx->cap_t)
-    return fail(ctx, ODC_ERR_CAPACITY, "mesh needs %lld vertices and %lld triangles",
-                (long long)c->n_vertices, (long long)c->n_triangles);
-  return ODC_OK;
+  if (ctx->pending != 1) return fail(ctx, ODC_ERR_INVALID_ARG, "no single extract pending");
+  int32_t rc = odc_mesh_sync_batch(ctx, 1, c);
+  if (rc == ODC_OK || rc == ODC_ERR_CAPACITY) TRY(count_flips(ctx, 0, &c->n_flipped_faces));
+  return rc;
 }
 
 extern "C" int32_t odc_get_intermediate(odc_context* ctx, int32_t which, void* dst,
                                         int64_t cap_bytes, int64_t* n) {
   if (!ctx || !n) return ODC_ERR_INVALID_ARG;
   if (!ctx->pending) return fail(ctx, ODC_ERR_INVALID_ARG, "no extract yet");
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  const Job& j = ctx->job;
+  TRY(finish(ctx));
+  const Job& J = ctx->hjobs[0];
+  const unsigned long long* o = ctx->hgather;
   const void* src = nullptr;
   int64_t count = 0, elem = 4;
   switch (which) {
-    case 0: src = j.labels; count = (j.g.nc + 31) / 32; break;
-    case 1: src = j.elist; count = j.n_edges; break;
-    case 2: src = j.et; count = j.n_edges; break;
-    case 3: src = j.plist; count = j.n_pairs; break;
-    case 4: src = j.pf; count = j.n_pairs; elem = 16; break;
-    case 5: src = j.clist; count = j.n_cells; break;
-    case 6: src = j.cpm; count = j.n_cells; break;
-    case 7: src = j.cnf; count = j.n_cells; break;
-    case 8: src = j.vbase; count = j.n_cells; break;
-    case 9: src = j.ecase; count = j.n_edges; break;
+    case 0: src = J.labels; count = J.nw_c; break;
+    case 1: src = J.elist; count = (int64_t)o[0]; break;
+    case 2: src = J.et; count = (int64_t)o[0]; break;
+    case 3: src = J.plist; count = (int64_t)o[1]; break;
+    case 4: src = J.pf; count = (int64_t)o[1]; elem = 16; break;
+    case 5: src = J.clist; count = (int64_t)o[2]; break;
+    case 6: src = J.cpm; count = (int64_t)o[2]; break;
+    case 7: src = J.cnf; count = (int64_t)o[2]; break;
+    case 8: src = J.vbase; count = (int64_t)o[2]; break;
+    case 9: src = J.ecase; count = (int64_t)o[0]; break;
     default: return fail(ctx, ODC_ERR_INVALID_ARG, "unknown intermediate %d", which);
   }
   *n = count;
@@ -544,6 +671,34 @@ extern "C" int32_t odc_get_intermediate(odc_context* ctx, int32_t which, void* d
   return ODC_OK;
 }
 
+extern "C" int32_t odc_context_set_timing(odc_context* ctx, int32_t enable) {
+  if (!ctx) return ODC_ERR_INVALID_ARG;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if (enable && !ctx->ev[0])
+    for (hipEvent_t& e : ctx->ev) HIP_TRY(ctx, hipEventCreate(&e));
+  ctx->timing = enable != 0;
+  return ODC_OK;
+}
+
+extern "C" int32_t odc_context_set_graph(odc_context* ctx, int32_t enable) {
+  if (!ctx) return ODC_ERR_INVALID_ARG;
+  if (!enable) drop_graph(ctx);
+  ctx->use_graph = enable != 0;
+  return ODC_OK;
+}
+
+extern "C" int32_t odc_get_stage_times(odc_context* ctx, float* ms, int32_t cap, int32_t* n) {
+  if (!ctx || !n) return ODC_ERR_INVALID_ARG;
+  *n = 8;
+  if (!ctx->timing || !ctx->pending)
+    return fail(ctx, ODC_ERR_INVALID_ARG, "stage timing is off or nothing was extracted");
+  if (cap < 8 || !ms) return fail(ctx, ODC_ERR_CAPACITY, "need room for 8 stage times");
+  HIP_TRY(ctx, hipEventSynchronize(ctx->ev[8]));
+  for (int i = 0; i < 8; ++i)
+    HIP_TRY(ctx, hipEventElapsedTime(&ms[i], ctx->ev[i], ctx->ev[i + 1]));
+  return ODC_OK;
+}
+
 extern "C" int32_t odc_field_eval(odc_context* ctx, const odc_field* f, int32_t precision,
                                   const float* xyz, int64_t n, float* z) {
   if (!ctx) return ODC_ERR_INVALID_ARG;
@@ -555,12 +710,89 @@ extern "C" int32_t odc_field_eval(odc_context* ctx, const odc_field* f, int32_t 
   odc_params_default(&p, 1);
   odc_mesh_buffers o;
   memset(&o, 0, sizeof(o));
-  TRY(validate(ctx, f, &p, &o));
+  TRY(validate_job(ctx, f, &p, &o));
   HIP_TRY(ctx, hipSetDevice(ctx->device));
-  Mlp m = Mlp();
-  if (f->kind == ODC_FIELD_MLP) TRY(prepare_mlp(ctx, f, m));
-  HIP_TRY(ctx, launch_eval(f->kind, precision, f->prims, f->n_prims, m, xyz, (int)n, z,
-                           ctx->stream));
+  if (n == 0) return ODC_OK;
+  if (ctx->pending) TRY(finish(ctx));
+  ctx->pending = 0;
+  if (ctx->slots.empty()) ctx->slots.resize(1);
+  TRY(setup_job(ctx, 0, f, &p, &o, 0));
+  HIP_TRY(ctx, hipMemcpyAsync(P<Job>(ctx->djobs), ctx->hjobs, sizeof(Job),
+                              hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(P<const float*>(ctx->dweights), ctx->hweights, sizeof(float*),
+                              hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, launch_eval(P<Job>(ctx->djobs), ctx->hjobs[0], P<const float*>(ctx->dweights),
+                           precision, xyz, (int)n, z, ctx->cfg, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return ODC_OK;
+}
+
+// ------------------------------------------------------------- autotuner
+// Picks the persistent grid sizes for one field by timing the stages they
+// drive: grid-wide passes, thread-per-element passes and MLP passes.
+extern "C" int32_t odc_autotune(odc_context* ctx, const odc_field* f, const odc_params* p,
+                                int32_t* chosen) {
+  if (!ctx || !f || !p) return ODC_ERR_INVALID_ARG;
+  odc_mesh_buffers o;
+  memset(&o, 0, sizeof(o));
+  TRY(validate_job(ctx, f, p, &o));
+  const bool was_timing = ctx->timing;
+  TRY(odc_context_set_timing(ctx, 1));
+  auto time_stages = [&](float st[8]) -> int32_t {
+    TRY(enqueue_batch(ctx, 1, f, p, &o));
+    TRY(finish(ctx));
+    HIP_TRY(ctx, hipEventSynchronize(ctx->ev[8]));
+    for (int i = 0; i < 8; ++i) HIP_TRY(ctx, hipEventElapsedTime(&st[i], ctx->ev[i], ctx->ev[i + 1]));
+    return ODC_OK;
+  };
+  float st[8];
+  TRY(time_stages(st));  // warm-up at the current configuration
+  const int grid_c[4] = {512, 1024, 2048, 4096};
+  const int elem_c[4] = {256, 512, 1024, 2048};
+  const int mlp_c[2] = {256, 512};
+  LaunchCfg best = ctx->cfg;
+  float bt = 1e30f;
+  for (int v : grid_c) {
+    ctx->cfg.grid_blocks = v;
+    TRY(time_stages(st));
+    const float t = st[1] + st[2] + (f->kind == ODC_FIELD_CSG ? st[0] : 0.0f);
+    if (t < bt) { bt = t; best.grid_blocks = v; }
+  }
+  ctx->cfg.grid_blocks = best.grid_blocks;
+  bt = 1e30f;
+  for (int v : elem_c) {
+    ctx->cfg.elem_blocks = v;
+    TRY(time_stages(st));
+    const float t = st[5] + st[6] + st[7] + (f->kind == ODC_FIELD_CSG ? st[3] + st[4] : 0.0f);
+    if (t < bt) { bt = t; best.elem_blocks = v; }
+  }
+  ctx->cfg.elem_blocks = best.elem_blocks;
+  if (f->kind == ODC_FIELD_MLP) {
+    bt = 1e30f;
+    for (int v : mlp_c) {
+      ctx->cfg.mlp_blocks = v;
+      TRY(time_stages(st));
+      const float t = st[0] + st[3] + st[4];
+      if (t < bt) { bt = t; best.mlp_blocks = v; }
+    }
+  }
+  ctx->cfg = best;
+  if (!was_timing) ctx->timing = false;
+  if (chosen) {
+    chosen[0] = best.grid_blocks;
+    chosen[1] = best.elem_blocks;
+    chosen[2] = best.mlp_blocks;
+  }
+  return ODC_OK;
+}
+
+extern "C" int32_t odc_set_launch_config(odc_context* ctx, const int32_t* cfg3) {
+  if (!ctx || !cfg3) return ODC_ERR_INVALID_ARG;
+  if (cfg3[0] < 1 || cfg3[1] < 1 || cfg3[2] < 1 || cfg3[0] > 65536 || cfg3[1] > 65536 ||
+      cfg3[2] > 65536)
+    return fail(ctx, ODC_ERR_INVALID_ARG, "grid sizes must be in 1..65536");
+  ctx->cfg.grid_blocks = cfg3[0];
+  ctx->cfg.elem_blocks = cfg3[1];
+  ctx->cfg.mlp_blocks = cfg3[2];
   return ODC_OK;
 }

@@ -8,17 +8,23 @@
 //   cell_count/qef    (d) partitions, normals, QEF 3D points        [App. A.1.1, Sec. 5.3, Eq. 2]
 //   emit              (e) quads, intersection-free split            [Sec. 4, App. A.1.5]
 //
-// Launch shapes.  Grid-wide passes (labels of analytic fields, classification)
-// run one thread per element with wave ballots packing 64 results into two
-// 32-bit words.  Per-element passes over the compacted active sets run one
-// thread per element for analytic fields; MLP fields run one wavefront per 32
-// elements so that each occupancy query of the search is a 32-column
-// matrix-core batch (odc_mlp.h).
+// Every kernel is persistent and job-major (odc_job.h): one launch per stage
+// serves all jobs of a batch.  Grid-wide passes (labels of analytic fields,
+// classification) give each wavefront 64 consecutive elements and pack the
+// results with a ballot into two 32-bit words.  Passes over the compacted
+// active sets run one thread per element for analytic fields; MLP fields run
+// one wavefront per 32 elements so that each occupancy query of a search is a
+// 32-column matrix-core batch (odc_mlp.h).
 #include "odc_internal.h"
 
 namespace odc {
 
 constexpr int kBlock = 256;
+
+__device__ __forceinline__ int gthread() { return blockIdx.x * kBlock + threadIdx.x; }
+__device__ __forceinline__ int nthreads() { return gridDim.x * kBlock; }
+__device__ __forceinline__ int gwave() { return (blockIdx.x * kBlock + threadIdx.x) >> 6; }
+__device__ __forceinline__ int nwaves() { return gridDim.x * (kBlock / 64); }
 
 __device__ __forceinline__ void store_ballot(uint64_t b, int first_elem_of_wave, int nwords,
                                              uint32_t* __restrict__ dst) {
@@ -28,99 +34,140 @@ __device__ __forceinline__ void store_ballot(uint64_t b, int first_elem_of_wave,
   if (lane == 32 && w0 + 1 < nwords) dst[w0 + 1] = (uint32_t)(b >> 32);
 }
 
-static inline int nblocks(long long n, int per = kBlock) { return (int)((n + per - 1) / per); }
-
-// ------------------------------------------------------------------ scan
-__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ in, int n,
-                                                     uint32_t* __restrict__ bsum) {
-  __shared__ uint32_t sh[256];
-  const int base = blockIdx.x * 1024;
-  uint32_t s = 0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int i = base + threadIdx.x + k * 256;
-    if (i < n) s += in[i];
-  }
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) bsum[blockIdx.x] = sh[0];
+// ------------------------------------------------------------------ scans
+// Exclusive scans of per-job uint32 arrays, out[n] = total.  Which array:
+//   0 crossing-edge word counts, 1 pair word counts, 2 active-cell word counts,
+//   3 partitions per active cell, 4 triangles per crossing edge,
+//   5 case-3 vertices per crossing edge.
+template <int S>
+__device__ __forceinline__ void scan_arrays(const Job& J, const uint32_t*& in, uint32_t*& out,
+                                            int& n) {
+  if (S == 0) { in = J.ecount; out = J.eprefix; n = J.nw_e; }
+  if (S == 1) { in = J.pcount; out = J.pprefix; n = J.nw_f; }
+  if (S == 2) { in = J.ccount; out = J.cprefix; n = J.nw_cell; }
+  if (S == 3) { in = J.npart; out = J.vbase; n = n_cells_of(J); }
+  if (S == 4) { in = J.ntri; out = J.tprefix; n = n_edges_of(J); }
+  if (S == 5) { in = J.n3; out = J.c3prefix; n = n_edges_of(J); }
 }
 
-__global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t* __restrict__ bsum, int nb,
-                                                      uint32_t* __restrict__ total) {
+template <int S>
+__device__ __forceinline__ int scan_blocks_of(const Job& J) {
+  const uint32_t* in;
+  uint32_t* out;
+  int n;
+  scan_arrays<S>(J, in, out, n);
+  return (n + 1023) >> 10;
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_scan_reduce(const Job* __restrict__ jobs, int njobs) {
+  __shared__ uint32_t sh[256];
+  for_units(jobs, njobs, blockIdx.x, gridDim.x,
+            [](const Job& J) { return scan_blocks_of<S>(J); },
+            [&](const Job& J, int blk) {
+              const uint32_t* in;
+              uint32_t* out;
+              int n;
+              scan_arrays<S>(J, in, out, n);
+              const int base = blk * 1024;
+              uint32_t s = 0;
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                const int i = base + threadIdx.x + k * 256;
+                if (i < n) s += in[i];
+              }
+              sh[threadIdx.x] = s;
+              __syncthreads();
+              for (int off = 128; off > 0; off >>= 1) {
+                if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+                __syncthreads();
+              }
+              if (threadIdx.x == 0) J.scan_tmp[blk] = sh[0];
+              __syncthreads();
+            });
+}
+
+template <int S>
+__global__ __launch_bounds__(1024) void k_scan_blocks(const Job* __restrict__ jobs, int njobs) {
   __shared__ uint32_t sh[1024];
-  uint32_t carry = 0;
-  const int t = threadIdx.x;
-  for (int base = 0; base < nb; base += 1024) {
-    const int i = base + t;
-    const uint32_t v = i < nb ? bsum[i] : 0u;
-    sh[t] = v;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-      const uint32_t x = t >= off ? sh[t - off] : 0u;
-      __syncthreads();
-      sh[t] += x;
-      __syncthreads();
-    }
-    if (i < nb) bsum[i] = carry + sh[t] - v;
-    carry += sh[1023];
-    __syncthreads();
-  }
-  if (t == 0) *total = carry;
+  for_units(jobs, njobs, blockIdx.x, gridDim.x, [](const Job&) { return 1; },
+            [&](const Job& J, int) {
+              const uint32_t* in;
+              uint32_t* out;
+              int n;
+              scan_arrays<S>(J, in, out, n);
+              const int nb = (n + 1023) >> 10;
+              uint32_t carry = 0;
+              const int t = threadIdx.x;
+              for (int base = 0; base < nb; base += 1024) {
+                const int i = base + t;
+                const uint32_t v = i < nb ? J.scan_tmp[i] : 0u;
+                sh[t] = v;
+                __syncthreads();
+                for (int off = 1; off < 1024; off <<= 1) {
+                  const uint32_t x = t >= off ? sh[t - off] : 0u;
+                  __syncthreads();
+                  sh[t] += x;
+                  __syncthreads();
+                }
+                if (i < nb) J.scan_tmp[i] = carry + sh[t] - v;
+                carry += sh[1023];
+                __syncthreads();
+              }
+              if (t == 0) out[n] = carry;
+              __syncthreads();
+            });
 }
 
-__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ in, int n,
-                                                    const uint32_t* __restrict__ bsum,
-                                                    uint32_t* __restrict__ out) {
+template <int S>
+__global__ __launch_bounds__(256) void k_scan_apply(const Job* __restrict__ jobs, int njobs) {
   __shared__ uint32_t sh[256];
-  const int t = threadIdx.x;
-  const int base = blockIdx.x * 1024 + 4 * t;
-  uint32_t v[4], s = 0;
+  for_units(jobs, njobs, blockIdx.x, gridDim.x,
+            [](const Job& J) { return scan_blocks_of<S>(J); },
+            [&](const Job& J, int blk) {
+              const uint32_t* in;
+              uint32_t* out;
+              int n;
+              scan_arrays<S>(J, in, out, n);
+              const int t = threadIdx.x;
+              const int base = blk * 1024 + 4 * t;
+              uint32_t v[4], s = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    v[k] = (base + k < n) ? in[base + k] : 0u;
-    s += v[k];
-  }
-  sh[t] = s;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    const uint32_t x = t >= off ? sh[t - off] : 0u;
-    __syncthreads();
-    sh[t] += x;
-    __syncthreads();
-  }
-  uint32_t run = bsum[blockIdx.x] + sh[t] - s;
+              for (int k = 0; k < 4; ++k) {
+                v[k] = (base + k < n) ? in[base + k] : 0u;
+                s += v[k];
+              }
+              sh[t] = s;
+              __syncthreads();
+              for (int off = 1; off < 256; off <<= 1) {
+                const uint32_t x = t >= off ? sh[t - off] : 0u;
+                __syncthreads();
+                sh[t] += x;
+                __syncthreads();
+              }
+              uint32_t run = J.scan_tmp[blk] + sh[t] - s;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (base + k < n) out[base + k] = run;
-    run += v[k];
-  }
+              for (int k = 0; k < 4; ++k) {
+                if (base + k < n) out[base + k] = run;
+                run += v[k];
+              }
+              __syncthreads();
+            });
 }
 
-size_t scan_tmp_words(int n) { return (size_t)((n + 1023) / 1024) + 1; }
-
-hipError_t scan_exclusive(const uint32_t* in, uint32_t* out, int n, uint32_t* tmp,
-                          hipStream_t s) {
-  const int nb = (n + 1023) / 1024;
-  if (nb == 0) {
-    return hipMemsetAsync(out, 0, sizeof(uint32_t), s);
-  }
-  k_scan_reduce<<<nb, 256, 0, s>>>(in, n, tmp);
-  k_scan_blocks<<<1, 1024, 0, s>>>(tmp, nb, out + n);
-  k_scan_apply<<<nb, 256, 0, s>>>(in, n, tmp, out);
-  return hipGetLastError();
+template <int S>
+static void scan(const Job* d, int njobs, const LaunchCfg& cfg, hipStream_t s) {
+  k_scan_reduce<S><<<cfg.scan_blocks, 256, 0, s>>>(d, njobs);
+  k_scan_blocks<S><<<njobs < 64 ? njobs : 64, 1024, 0, s>>>(d, njobs);
+  k_scan_apply<S><<<cfg.scan_blocks, 256, 0, s>>>(d, njobs);
 }
 
 // ------------------------------------------------------------ MLP weights
 // Packs the binary32 weights into the fragment orders of odc_mlp.h.
-__global__ void k_pack_mlp(const float* __restrict__ w, int in_dim, int depth,
-                           float* __restrict__ w1f, float* __restrict__ whf,
-                           v8bf* __restrict__ w1b, v8bf* __restrict__ whb,
-                           float* __restrict__ bias, float* __restrict__ wout) {
+__device__ void pack_mlp(const float* __restrict__ w, int in_dim, int depth, long long id,
+                         float* __restrict__ w1f, float* __restrict__ whf,
+                         v8bf* __restrict__ w1b, v8bf* __restrict__ whb,
+                         float* __restrict__ bias, float* __restrict__ wout) {
   const int kb1f = (in_dim + 1) / 2, kb1b = (in_dim + 15) / 16;
   const size_t l1 = (size_t)kWidth * in_dim;
   const size_t hid = (size_t)kWidth * kWidth;
@@ -128,15 +175,13 @@ __global__ void k_pack_mlp(const float* __restrict__ w, int in_dim, int depth,
   const long long n_whf = (long long)(depth - 1) * kHiddenBlocksF32 * 8 * 64;
   const long long n_w1b = (long long)kb1b * 8 * 64;
   const long long n_whb = (long long)(depth - 1) * kHiddenBlocksBF16 * 8 * 64;
-  const long long total = n_w1f + n_whf + n_w1b + n_whb + depth * kWidth + kWidth;
-  for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < total;
-       id += (long long)gridDim.x * blockDim.x) {
+  {
     long long r = id;
     if (r < n_w1f) {
       const int lane = r % 64, R = (r / 64) % 8, b = (int)(r / 512);
       const int row = 32 * R + (lane & 31), k = 2 * b + (lane >> 5);
       w1f[r] = k < in_dim ? w[(size_t)row * in_dim + k] : 0.0f;
-      continue;
+      return;
     }
     r -= n_w1f;
     if (r < n_whf) {
@@ -147,7 +192,7 @@ __global__ void k_pack_mlp(const float* __restrict__ w, int in_dim, int depth,
       const int n = 32 * T + 8 * (i >> 2) + 4 * h + (i & 3);
       const float* W = w + l1 + kWidth + (size_t)l * (hid + kWidth);
       whf[r] = W[(size_t)row * kWidth + n];
-      continue;
+      return;
     }
     r -= n_whf;
     if (r < n_w1b) {
@@ -160,7 +205,7 @@ __global__ void k_pack_mlp(const float* __restrict__ w, int in_dim, int depth,
         v[j] = (__bf16)(k < in_dim ? w[(size_t)row * in_dim + k] : 0.0f);
       }
       w1b[r] = v;
-      continue;
+      return;
     }
     r -= n_w1b;
     if (r < n_whb) {
@@ -176,142 +221,182 @@ __global__ void k_pack_mlp(const float* __restrict__ w, int in_dim, int depth,
         v[j] = (__bf16)W[(size_t)row * kWidth + n];
       }
       whb[r] = v;
-      continue;
+      return;
     }
     r -= n_whb;
     if (r < (long long)depth * kWidth) {
       const int l = (int)(r / kWidth), n = (int)(r % kWidth);
       const size_t off = (l == 0) ? l1 : l1 + kWidth + (size_t)(l - 1) * (hid + kWidth) + hid;
       bias[r] = w[off + n];
-      continue;
+      return;
     }
     r -= (long long)depth * kWidth;
     wout[r] = w[l1 + kWidth + (size_t)(depth - 1) * (hid + kWidth) + r];
   }
 }
 
-hipError_t launch_pack_mlp(const float* weights, int in_dim, int depth, float* w1f, float* whf,
-                           v8bf* w1b, v8bf* whb, float* bias, float* wout, hipStream_t s) {
-  k_pack_mlp<<<1024, 256, 0, s>>>(weights, in_dim, depth, w1f, whf, w1b, whb, bias, wout);
-  return hipGetLastError();
+
+__device__ __forceinline__ long long pack_units(const Job& J) {
+  if (J.kind != 1) return 0;
+  const int d = J.mlp.depth;
+  return (long long)(J.mlp.kb1f + (d - 1) * kHiddenBlocksF32 + J.mlp.kb1b +
+                     (d - 1) * kHiddenBlocksBF16) * 512 + (long long)(d + 1) * kWidth;
+}
+
+__global__ __launch_bounds__(256) void k_pack(const Job* __restrict__ jobs, int njobs,
+                                              const float* const* __restrict__ weights) {
+  for (int k = 0; k < njobs; ++k) {
+    const Job& J = jobs[k];
+    const long long n = pack_units(J);
+    for (long long id = gthread(); id < n; id += nthreads())
+      pack_mlp(weights[k], J.mlp.in_dim, J.mlp.depth, id, const_cast<float*>(J.mlp.w1f),
+               const_cast<float*>(J.mlp.whf), const_cast<v8bf*>(J.mlp.w1b),
+               const_cast<v8bf*>(J.mlp.whb), const_cast<float*>(J.mlp.bias),
+               const_cast<float*>(J.mlp.wout));
+  }
+}
+
+// ------------------------------------------------------------------ status
+__global__ void k_clear_status(const Job* __restrict__ jobs, int njobs) {
+  for (int k = gthread(); k < njobs; k += nthreads()) {
+    jobs[k].status[0] = 0;
+    jobs[k].status[1] = 0;
+    jobs[k].status[2] = 0;
+  }
+}
+
+// per job: raw totals and status for the host (8 x uint64)
+__global__ void k_gather(const Job* __restrict__ jobs, int njobs,
+                         unsigned long long* __restrict__ out) {
+  for (int k = gthread(); k < njobs; k += nthreads()) {
+    const Job& J = jobs[k];
+    unsigned long long* o = out + 8 * k;
+    const int ne = n_edges_of(J), nc = n_cells_of(J);
+    o[0] = J.eprefix[J.nw_e];
+    o[1] = J.pprefix[J.nw_f];
+    o[2] = J.cprefix[J.nw_cell];
+    o[3] = J.vbase[nc];
+    o[4] = J.tprefix[ne];
+    o[5] = J.c3prefix[ne];
+    o[6] = J.status[0];
+    o[7] = J.status[1] | (J.status[2] << 32);
+  }
 }
 
 // ------------------------------------------------------------- (a) labels
-__global__ __launch_bounds__(256) void k_labels_csg(Grid g, const float* __restrict__ prims,
-                                                    int np, uint32_t* __restrict__ labels) {
-  const int c = blockIdx.x * kBlock + threadIdx.x;
-  int lab = 0;
-  if (c < g.nc) {
-    const int n1 = g.N + 1;
-    const float gp[3] = {(float)(c % n1), (float)((c / n1) % n1), (float)(c / (n1 * n1))};
-    float x[3];
-    grid_world(g, gp, x);
-    lab = csg_inside(prims, np, x);
-  }
-  const uint64_t b = __ballot(lab);
-  store_ballot(b, c - lane_id(), (g.nc + 31) >> 5, labels);
+__global__ __launch_bounds__(256) void k_labels_csg(const Job* __restrict__ jobs, int njobs) {
+  for_units(jobs, njobs, gwave(), nwaves(),
+            [](const Job& J) { return J.kind == 0 ? (J.g.nc + 63) >> 6 : 0; },
+            [&](const Job& J, int u) {
+              const Grid& g = J.g;
+              const int c = u * 64 + lane_id();
+              int lab = 0;
+              if (c < g.nc) {
+                const int n1 = g.N + 1;
+                const float gp[3] = {(float)(c % n1), (float)((c / n1) % n1),
+                                     (float)(c / (n1 * n1))};
+                float x[3];
+                grid_world(g, gp, x);
+                lab = csg_inside(J.prims, J.n_prims, x);
+              }
+              store_ballot(__ballot(lab), u * 64, J.nw_c, J.labels);
+            });
 }
 
+// MLP corners, 32 per wavefront: fp32, or bf16 with the guard-band corners
+// queued for fp32 re-evaluation
 template <int BF16>
-__global__ __launch_bounds__(256) void k_labels_mlp(Job j) {
+__global__ __launch_bounds__(256) void k_labels_mlp(const Job* __restrict__ jobs, int njobs) {
   __shared__ float act_lds[kBlock / 64][BF16 ? kActVecsBF16 * 4 : kActWords];
   float* act = act_lds[threadIdx.x >> 6];
-  const Grid& g = j.g;
-  const int lane = lane_id(), col = lane & 31;
-  const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
-  const int nwaves = gridDim.x * (kBlock / 64);
-  const int ntiles = (g.nc + 31) >> 5;
-  const int n1 = g.N + 1;
-  for (int t = wave; t < ntiles; t += nwaves) {
-    const int c = t * 32 + col;
-    const bool valid = c < g.nc;
-    const int cc = valid ? c : g.nc - 1;
-    const float gp[3] = {(float)(cc % n1), (float)((cc / n1) % n1), (float)(cc / (n1 * n1))};
-    float x[3];
-    grid_world(g, gp, x);
-    const float z = BF16 ? mlp_logit_bf16(j.mlp, x, reinterpret_cast<v8bf*>(act))
-                         : mlp_logit_fp32(j.mlp, x, act);
-    const uint64_t b = __ballot(valid && z > 0.0f);
-    if (lane == 0) j.labels[t] = (uint32_t)b;
-    if (BF16) {
-      const bool q = valid && lane < 32 && fabsf(z) < j.guard_logit;
-      const uint64_t qb = __ballot(q);
-      if (qb) {
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(&j.counters[0], (unsigned long long)__popcll(qb));
-        base = __shfl(base, 0);
-        if (q) {
-          const unsigned long long r = base + __popcll(qb & ((1ull << lane) - 1ull));
-          if (r < (unsigned long long)j.guard_cap) j.guard_list[r] = (uint32_t)c;
-        }
-      }
-    }
-  }
+  for_units(jobs, njobs, gwave(), nwaves(),
+            [](const Job& J) { return (J.kind == 1 && J.precision == BF16) ? J.nw_c : 0; },
+            [&](const Job& J, int t) {
+              const Grid& g = J.g;
+              const int lane = lane_id();
+              const int c = t * 32 + (lane & 31);
+              const bool valid = c < g.nc;
+              const int cc = valid ? c : g.nc - 1;
+              const int n1 = g.N + 1;
+              const float gp[3] = {(float)(cc % n1), (float)((cc / n1) % n1),
+                                   (float)(cc / (n1 * n1))};
+              float x[3];
+              grid_world(g, gp, x);
+              const float z = BF16 ? mlp_logit_bf16(J.mlp, x, reinterpret_cast<v8bf*>(act))
+                                   : mlp_logit_fp32(J.mlp, x, act);
+              const uint64_t b = __ballot(valid && z > 0.0f);
+              if (lane == 0) J.labels[t] = (uint32_t)b;
+              if (BF16) {
+                const bool q = valid && lane < 32 && fabsf(z) < J.guard_logit;
+                const uint64_t qb = __ballot(q);
+                if (qb) {
+                  unsigned long long base = 0;
+                  if (lane == 0) base = atomicAdd(&J.status[0], (unsigned long long)__popcll(qb));
+                  base = __shfl(base, 0);
+                  if (q) {
+                    const unsigned long long r = base + __popcll(qb & ((1ull << lane) - 1ull));
+                    if (r < (unsigned long long)J.guard_cap) J.guard_list[r] = (uint32_t)c;
+                    else J.status[2] = 1;  // queue full: rerun with room for every corner
+                  }
+                }
+              }
+            });
 }
 
 // fp32 re-evaluation of the corners queued by the bf16 pass
-__global__ __launch_bounds__(256) void k_relabel_fp32(Job j) {
+__global__ __launch_bounds__(256) void k_relabel_fp32(const Job* __restrict__ jobs, int njobs) {
   __shared__ float act_lds[kBlock / 64][kActWords];
   float* act = act_lds[threadIdx.x >> 6];
-  const Grid& g = j.g;
-  const int lane = lane_id(), col = lane & 31;
-  const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
-  const int nwaves = gridDim.x * (kBlock / 64);
-  const unsigned long long nq = j.counters[0];
-  const int n = (int)(nq < (unsigned long long)j.guard_cap ? nq : j.guard_cap);
-  const int n1 = g.N + 1;
-  for (int t = wave; t * 32 < n; t += nwaves) {
-    const int x_i = t * 32 + col;
-    const bool valid = x_i < n;
-    const int c = (int)j.guard_list[valid ? x_i : n - 1];
-    const float gp[3] = {(float)(c % n1), (float)((c / n1) % n1), (float)(c / (n1 * n1))};
-    float x[3];
-    grid_world(g, gp, x);
-    const float z = mlp_logit_fp32(j.mlp, x, act);
-    if (valid && lane < 32) {
-      const uint32_t bit = 1u << (c & 31);
-      if (z > 0.0f) atomicOr(&j.labels[c >> 5], bit);
-      else atomicAnd(&j.labels[c >> 5], ~bit);
-    }
-  }
-}
-
-hipError_t launch_labels(Job& j, hipStream_t s) {
-  if (j.kind == 0) {
-    k_labels_csg<<<nblocks(j.g.nc), kBlock, 0, s>>>(j.g, j.prims, j.n_prims, j.labels);
-    return hipGetLastError();
-  }
-  const int ntiles = (j.g.nc + 31) / 32;
-  const int blocks = ntiles / 4 + 1 < 4096 ? ntiles / 4 + 1 : 4096;
-  if (j.precision == 0) {
-    k_labels_mlp<0><<<blocks, kBlock, 0, s>>>(j);
-  } else {
-    k_labels_mlp<1><<<blocks, kBlock, 0, s>>>(j);
-    k_relabel_fp32<<<2048, kBlock, 0, s>>>(j);
-  }
-  return hipGetLastError();
+  for_units(jobs, njobs, gwave(), nwaves(),
+            [](const Job& J) {
+              if (J.kind != 1 || J.precision != 1) return 0;
+              const unsigned long long n = J.status[0];
+              const int m = (int)(n < (unsigned long long)J.guard_cap ? n : J.guard_cap);
+              return (m + 31) >> 5;
+            },
+            [&](const Job& J, int t) {
+              const Grid& g = J.g;
+              const unsigned long long nq = J.status[0];
+              const int n = (int)(nq < (unsigned long long)J.guard_cap ? nq : J.guard_cap);
+              const int lane = lane_id();
+              const int xi = t * 32 + (lane & 31);
+              const bool valid = xi < n;
+              const int c = (int)J.guard_list[valid ? xi : n - 1];
+              const int n1 = g.N + 1;
+              const float gp[3] = {(float)(c % n1), (float)((c / n1) % n1),
+                                   (float)(c / (n1 * n1))};
+              float x[3];
+              grid_world(g, gp, x);
+              const float z = mlp_logit_fp32(J.mlp, x, act);
+              if (valid && lane < 32) {
+                const uint32_t bit = 1u << (c & 31);
+                if (z > 0.0f) atomicOr(&J.labels[c >> 5], bit);
+                else atomicAnd(&J.labels[c >> 5], ~bit);
+              }
+            });
 }
 
 // ---------------------------------------------------------- classification
-__global__ __launch_bounds__(256) void k_classify_edges(Grid g, const uint32_t* __restrict__ L,
-                                                        uint32_t* __restrict__ emask,
-                                                        uint32_t* __restrict__ ecount) {
-  const int e = blockIdx.x * kBlock + threadIdx.x;
-  const int ne = 3 * g.ea;
-  int x = 0;
-  if (e < ne) {
-    int a, p[3];
-    edge_pos(g, e, a, p);
-    const int c0 = corner_index(g, p[0], p[1], p[2]);
-    const int step = a == 0 ? 1 : (a == 1 ? g.N + 1 : (g.N + 1) * (g.N + 1));
-    x = bit_of(L, c0) != bit_of(L, c0 + step);
-  }
-  const uint64_t b = __ballot(x);
-  const int nw = (ne + 31) >> 5;
-  store_ballot(b, e - lane_id(), nw, emask);
-  const int lane = lane_id(), w0 = (e - lane) >> 5;
-  if (lane == 0 && w0 < nw) ecount[w0] = __popc((uint32_t)b);
-  if (lane == 32 && w0 + 1 < nw) ecount[w0 + 1] = __popc((uint32_t)(b >> 32));
+__global__ __launch_bounds__(256) void k_classify_edges(const Job* __restrict__ jobs, int njobs) {
+  for_units(jobs, njobs, gwave(), nwaves(),
+            [](const Job& J) { return (3 * J.g.ea + 63) >> 6; },
+            [&](const Job& J, int u) {
+              const Grid& g = J.g;
+              const int e = u * 64 + lane_id();
+              int x = 0;
+              if (e < 3 * g.ea) {
+                int a, p[3];
+                edge_pos(g, e, a, p);
+                const int c0 = corner_index(g, p[0], p[1], p[2]);
+                const int step = a == 0 ? 1 : (a == 1 ? g.N + 1 : (g.N + 1) * (g.N + 1));
+                x = bit_of(J.labels, c0) != bit_of(J.labels, c0 + step);
+              }
+              const uint64_t b = __ballot(x);
+              store_ballot(b, u * 64, J.nw_e, J.emask);
+              const int lane = lane_id(), w0 = u * 2;
+              if (lane == 0 && w0 < J.nw_e) J.ecount[w0] = __popc((uint32_t)b);
+              if (lane == 32 && w0 + 1 < J.nw_e) J.ecount[w0 + 1] = __popc((uint32_t)(b >> 32));
+            });
 }
 
 // labels of the 8 corners of cell (i,j,k): bit lc = x + 2y + 4z
@@ -360,103 +445,106 @@ __device__ inline int face_flip(const Grid& g, const uint32_t* __restrict__ L,
   return merged;
 }
 
-__global__ __launch_bounds__(256) void k_classify_faces(Grid g, const uint32_t* __restrict__ L,
-                                                        const uint32_t* __restrict__ table,
-                                                        uint32_t* __restrict__ fact,
-                                                        uint32_t* __restrict__ famb,
-                                                        uint32_t* __restrict__ fflip,
-                                                        uint32_t* __restrict__ pcount) {
-  const int f = blockIdx.x * kBlock + threadIdx.x;
-  const int nf = 3 * g.fa;
-  int act = 0, amb = 0, flip = 0;
-  if (f < nf) {
-    int a, p[3], Lf[4];
-    face_pos(g, f, a, p);
-    face_labels(g, L, a, p, Lf);
-    const int n = __popc(face_crossing_mask(Lf));
-    act = n > 0;
-    amb = n == 4;
-    if (amb) flip = face_flip(g, L, table, a, p);
-  }
-  const uint64_t ba = __ballot(act), bb = __ballot(amb), bf = __ballot(flip);
-  const int nw = (nf + 31) >> 5;
-  const int first = f - lane_id();
-  store_ballot(ba, first, nw, fact);
-  store_ballot(bb, first, nw, famb);
-  store_ballot(bf, first, nw, fflip);
-  const int lane = lane_id(), w0 = first >> 5;
-  if (lane == 0 && w0 < nw) pcount[w0] = __popc((uint32_t)ba) + __popc((uint32_t)bb);
-  if (lane == 32 && w0 + 1 < nw)
-    pcount[w0 + 1] = __popc((uint32_t)(ba >> 32)) + __popc((uint32_t)(bb >> 32));
+__global__ __launch_bounds__(256) void k_classify_faces(const Job* __restrict__ jobs, int njobs,
+                                                        const uint32_t* __restrict__ table) {
+  for_units(jobs, njobs, gwave(), nwaves(),
+            [](const Job& J) { return (3 * J.g.fa + 63) >> 6; },
+            [&](const Job& J, int u) {
+              const Grid& g = J.g;
+              const int f = u * 64 + lane_id();
+              int act = 0, amb = 0, flip = 0;
+              if (f < 3 * g.fa) {
+                int a, p[3], Lf[4];
+                face_pos(g, f, a, p);
+                face_labels(g, J.labels, a, p, Lf);
+                const int n = __popc(face_crossing_mask(Lf));
+                act = n > 0;
+                amb = n == 4;
+                if (amb) flip = face_flip(g, J.labels, table, a, p);
+              }
+              const uint64_t ba = __ballot(act), bb = __ballot(amb), bf = __ballot(flip);
+              store_ballot(ba, u * 64, J.nw_f, J.fact);
+              store_ballot(bb, u * 64, J.nw_f, J.famb);
+              store_ballot(bf, u * 64, J.nw_f, J.fflip);
+              const int lane = lane_id(), w0 = u * 2;
+              if (lane == 0 && w0 < J.nw_f)
+                J.pcount[w0] = __popc((uint32_t)ba) + __popc((uint32_t)bb);
+              if (lane == 32 && w0 + 1 < J.nw_f)
+                J.pcount[w0 + 1] = __popc((uint32_t)(ba >> 32)) + __popc((uint32_t)(bb >> 32));
+            });
 }
 
-__global__ __launch_bounds__(256) void k_classify_cells(Grid g, const uint32_t* __restrict__ L,
-                                                        uint32_t* __restrict__ cmask,
-                                                        uint32_t* __restrict__ ccount) {
-  const int c = blockIdx.x * kBlock + threadIdx.x;
-  int x = 0;
-  if (c < g.ncell) {
-    const int N = g.N;
-    const int cfg = cell_config(g, L, c % N, (c / N) % N, c / (N * N));
-    x = cfg != 0 && cfg != 255;
-  }
-  const uint64_t b = __ballot(x);
-  const int nw = (g.ncell + 31) >> 5;
-  store_ballot(b, c - lane_id(), nw, cmask);
-  const int lane = lane_id(), w0 = (c - lane) >> 5;
-  if (lane == 0 && w0 < nw) ccount[w0] = __popc((uint32_t)b);
-  if (lane == 32 && w0 + 1 < nw) ccount[w0 + 1] = __popc((uint32_t)(b >> 32));
-}
-
-hipError_t launch_classify(Job& j, uint32_t* ecount, uint32_t* pcount, uint32_t* ccount,
-                           const uint32_t* table, hipStream_t s) {
-  k_classify_edges<<<nblocks(3LL * j.g.ea), kBlock, 0, s>>>(j.g, j.labels, j.emask, ecount);
-  k_classify_faces<<<nblocks(3LL * j.g.fa), kBlock, 0, s>>>(j.g, j.labels, table, j.fact,
-                                                             j.famb, j.fflip, pcount);
-  k_classify_cells<<<nblocks(j.g.ncell), kBlock, 0, s>>>(j.g, j.labels, j.cmask, ccount);
-  return hipGetLastError();
+__global__ __launch_bounds__(256) void k_classify_cells(const Job* __restrict__ jobs, int njobs) {
+  for_units(jobs, njobs, gwave(), nwaves(),
+            [](const Job& J) { return (J.g.ncell + 63) >> 6; },
+            [&](const Job& J, int u) {
+              const Grid& g = J.g;
+              const int c = u * 64 + lane_id();
+              int x = 0;
+              if (c < g.ncell) {
+                const int N = g.N;
+                const int cfg = cell_config(g, J.labels, c % N, (c / N) % N, c / (N * N));
+                x = cfg != 0 && cfg != 255;
+              }
+              const uint64_t b = __ballot(x);
+              store_ballot(b, u * 64, J.nw_cell, J.cmask);
+              const int lane = lane_id(), w0 = u * 2;
+              if (lane == 0 && w0 < J.nw_cell) J.ccount[w0] = __popc((uint32_t)b);
+              if (lane == 32 && w0 + 1 < J.nw_cell)
+                J.ccount[w0 + 1] = __popc((uint32_t)(b >> 32));
+            });
 }
 
 // ------------------------------------------------------------ compaction
-__global__ __launch_bounds__(256) void k_compact_bits(const uint32_t* __restrict__ mask,
-                                                      const uint32_t* __restrict__ prefix,
-                                                      int nw, int* __restrict__ list) {
-  const int w = blockIdx.x * kBlock + threadIdx.x;
-  if (w >= nw) return;
-  uint32_t m = mask[w];
-  int o = (int)prefix[w];
-  while (m) {
-    const int b = __ffs(m) - 1;
-    list[o++] = w * 32 + b;
-    m &= m - 1u;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_compact_pairs(const uint32_t* __restrict__ act,
-                                                       const uint32_t* __restrict__ amb,
-                                                       const uint32_t* __restrict__ prefix,
-                                                       int nw, int* __restrict__ list) {
-  const int w = blockIdx.x * kBlock + threadIdx.x;
-  if (w >= nw) return;
-  uint32_t m = act[w];
-  const uint32_t a2 = amb[w];
-  int o = (int)prefix[w];
-  while (m) {
-    const int b = __ffs(m) - 1;
-    const int f = w * 32 + b;
-    list[o++] = f << 1;
-    if ((a2 >> b) & 1u) list[o++] = (f << 1) | 1;
-    m &= m - 1u;
-  }
-}
-
-hipError_t launch_compact(Job& j, hipStream_t s) {
-  const int nwe = (3 * j.g.ea + 31) >> 5, nwf = (3 * j.g.fa + 31) >> 5,
-            nwc = (j.g.ncell + 31) >> 5;
-  k_compact_bits<<<nblocks(nwe), kBlock, 0, s>>>(j.emask, j.eprefix, nwe, j.elist);
-  k_compact_pairs<<<nblocks(nwf), kBlock, 0, s>>>(j.fact, j.famb, j.pprefix, nwf, j.plist);
-  k_compact_bits<<<nblocks(nwc), kBlock, 0, s>>>(j.cmask, j.cprefix, nwc, j.clist);
-  return hipGetLastError();
+// Lists in ascending id order; entries past the capacity are dropped and the
+// job is flagged for a larger scratch.
+__global__ __launch_bounds__(256) void k_compact(const Job* __restrict__ jobs, int njobs) {
+  for_units(jobs, njobs, gthread(), nthreads(),
+            [](const Job& J) { return J.nw_e + J.nw_f + J.nw_cell; },
+            [&](const Job& J, int u) {
+              if (u < J.nw_e) {
+                uint32_t m = J.emask[u];
+                int o = (int)J.eprefix[u];
+                while (m) {
+                  const int b = __ffs(m) - 1;
+                  if (o < J.cap_edges) J.elist[o] = u * 32 + b;
+                  else J.status[2] = 1;
+                  ++o;
+                  m &= m - 1u;
+                }
+                return;
+              }
+              u -= J.nw_e;
+              if (u < J.nw_f) {
+                uint32_t m = J.fact[u];
+                const uint32_t a2 = J.famb[u];
+                int o = (int)J.pprefix[u];
+                while (m) {
+                  const int b = __ffs(m) - 1;
+                  const int f = u * 32 + b;
+                  if (o < J.cap_pairs) J.plist[o] = f << 1;
+                  else J.status[2] = 1;
+                  ++o;
+                  if ((a2 >> b) & 1u) {
+                    if (o < J.cap_pairs) J.plist[o] = (f << 1) | 1;
+                    else J.status[2] = 1;
+                    ++o;
+                  }
+                  m &= m - 1u;
+                }
+                return;
+              }
+              u -= J.nw_f;
+              uint32_t m = J.cmask[u];
+              int o = (int)J.cprefix[u];
+              while (m) {
+                const int b = __ffs(m) - 1;
+                if (o < J.cap_cells) J.clist[o] = u * 32 + b;
+                else J.status[2] = 1;
+                ++o;
+                m &= m - 1u;
+              }
+            });
 }
 
 // --------------------------------------------------------- label functors
@@ -502,37 +590,29 @@ __device__ __forceinline__ float bisect_edge(const Job& j, const Lab& lab, int i
   return (lo + hi) * 0.5f;
 }
 
-__global__ __launch_bounds__(256) void k_bisect_csg(Job j) {
-  const int x = blockIdx.x * kBlock + threadIdx.x;
-  if (x >= j.n_edges) return;
-  CsgLabel lab{&j.g, j.prims, j.n_prims};
-  j.et[x] = bisect_edge(j, lab, j.elist[x]);
+__global__ __launch_bounds__(256) void k_bisect_csg(const Job* __restrict__ jobs, int njobs) {
+  for_units(jobs, njobs, gthread(), nthreads(),
+            [](const Job& J) { return J.kind == 0 ? n_edges_of(J) : 0; },
+            [&](const Job& J, int x) {
+              CsgLabel lab{&J.g, J.prims, J.n_prims};
+              J.et[x] = bisect_edge(J, lab, J.elist[x]);
+            });
 }
 
-__global__ __launch_bounds__(256) void k_bisect_mlp(Job j) {
+__global__ __launch_bounds__(256) void k_bisect_mlp(const Job* __restrict__ jobs, int njobs) {
   __shared__ float act_lds[kBlock / 64][kActWords];
-  const int lane = lane_id(), col = lane & 31;
-  const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
-  const int nwaves = gridDim.x * (kBlock / 64);
-  MlpLabel lab{&j.g, &j.mlp, act_lds[threadIdx.x >> 6]};
-  for (int t = wave; t * 32 < j.n_edges; t += nwaves) {
-    const int x = t * 32 + col;
-    const bool valid = x < j.n_edges;
-    const float tt = bisect_edge(j, lab, j.elist[valid ? x : j.n_edges - 1]);
-    if (valid && lane < 32) j.et[x] = tt;
-  }
-}
-
-hipError_t launch_bisect(Job& j, hipStream_t s) {
-  if (j.n_edges == 0) return hipSuccess;
-  if (j.kind == 0) {
-    k_bisect_csg<<<nblocks(j.n_edges), kBlock, 0, s>>>(j);
-  } else {
-    const int tiles = (j.n_edges + 31) / 32;
-    const int blocks = tiles / 4 + 1 < 2048 ? tiles / 4 + 1 : 2048;
-    k_bisect_mlp<<<blocks, kBlock, 0, s>>>(j);
-  }
-  return hipGetLastError();
+  float* act = act_lds[threadIdx.x >> 6];
+  for_units(jobs, njobs, gwave(), nwaves(),
+            [](const Job& J) { return J.kind == 1 ? (n_edges_of(J) + 31) >> 5 : 0; },
+            [&](const Job& J, int t) {
+              const int ne = n_edges_of(J);
+              const int lane = lane_id();
+              const int x = t * 32 + (lane & 31);
+              const bool valid = x < ne;
+              MlpLabel lab{&J.g, &J.mlp, act};
+              const float tt = bisect_edge(J, lab, J.elist[valid ? x : ne - 1]);
+              if (valid && lane < 32) J.et[x] = tt;
+            });
 }
 
 // ------------------------------------------------------------ (c) 2D points
@@ -619,8 +699,8 @@ __device__ double2 search_pair(const Job& j, const Lab& lab, int face, int slot)
   face_labels(g, j.labels, fr.a, fr.p, L);
   face_pairs(L, bit_of(j.fflip, face), pa, pb);
   const int fa = pa[slot], fb = pb[slot];
-  const float t1 = j.et[rank_of(j.emask, j.eprefix, face_edge_global(g, fr, fa))];
-  const float t2 = j.et[rank_of(j.emask, j.eprefix, face_edge_global(g, fr, fb))];
+  const float t1 = j.et[edge_slot(j, face_edge_global(g, fr, fa))];
+  const float t2 = j.et[edge_slot(j, face_edge_global(g, fr, fb))];
   float P1[2], P2[2];
   face_edge_point(fa, t1, P1);
   face_edge_point(fb, t2, P2);
@@ -716,39 +796,31 @@ __device__ double2 search_pair(const Job& j, const Lab& lab, int face, int slot)
   return make_double2((double)P1[0] + alpha * Au, (double)P1[1] + alpha * Av);
 }
 
-__global__ __launch_bounds__(256) void k_search2d_csg(Job j) {
-  const int x = blockIdx.x * kBlock + threadIdx.x;
-  if (x >= j.n_pairs) return;
-  CsgLabel lab{&j.g, j.prims, j.n_prims};
-  const int rec = j.plist[x];
-  j.pf[x] = search_pair(j, lab, rec >> 1, rec & 1);
+__global__ __launch_bounds__(256) void k_search2d_csg(const Job* __restrict__ jobs, int njobs) {
+  for_units(jobs, njobs, gthread(), nthreads(),
+            [](const Job& J) { return J.kind == 0 ? n_pairs_of(J) : 0; },
+            [&](const Job& J, int x) {
+              CsgLabel lab{&J.g, J.prims, J.n_prims};
+              const int rec = J.plist[x];
+              J.pf[x] = search_pair(J, lab, rec >> 1, rec & 1);
+            });
 }
 
-__global__ __launch_bounds__(256) void k_search2d_mlp(Job j) {
+__global__ __launch_bounds__(256) void k_search2d_mlp(const Job* __restrict__ jobs, int njobs) {
   __shared__ float act_lds[kBlock / 64][kActWords];
-  const int lane = lane_id(), col = lane & 31;
-  const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
-  const int nwaves = gridDim.x * (kBlock / 64);
-  MlpLabel lab{&j.g, &j.mlp, act_lds[threadIdx.x >> 6]};
-  for (int t = wave; t * 32 < j.n_pairs; t += nwaves) {
-    const int x = t * 32 + col;
-    const bool valid = x < j.n_pairs;
-    const int rec = j.plist[valid ? x : j.n_pairs - 1];
-    const double2 r = search_pair(j, lab, rec >> 1, rec & 1);
-    if (valid && lane < 32) j.pf[x] = r;
-  }
-}
-
-hipError_t launch_search2d(Job& j, hipStream_t s) {
-  if (j.n_pairs == 0) return hipSuccess;
-  if (j.kind == 0) {
-    k_search2d_csg<<<nblocks(j.n_pairs), kBlock, 0, s>>>(j);
-  } else {
-    const int tiles = (j.n_pairs + 31) / 32;
-    const int blocks = tiles / 4 + 1 < 2048 ? tiles / 4 + 1 : 2048;
-    k_search2d_mlp<<<blocks, kBlock, 0, s>>>(j);
-  }
-  return hipGetLastError();
+  float* act = act_lds[threadIdx.x >> 6];
+  for_units(jobs, njobs, gwave(), nwaves(),
+            [](const Job& J) { return J.kind == 1 ? (n_pairs_of(J) + 31) >> 5 : 0; },
+            [&](const Job& J, int t) {
+              const int np = n_pairs_of(J);
+              const int lane = lane_id();
+              const int x = t * 32 + (lane & 31);
+              const bool valid = x < np;
+              MlpLabel lab{&J.g, &J.mlp, act};
+              const int rec = J.plist[valid ? x : np - 1];
+              const double2 r = search_pair(J, lab, rec >> 1, rec & 1);
+              if (valid && lane < 32) J.pf[x] = r;
+            });
 }
 
 // ----------------------------------------------------- (d) partitions, QEF
@@ -771,30 +843,25 @@ __device__ __forceinline__ int cell_flipmask(const Grid& g, const uint32_t* __re
   return fm;
 }
 
-__global__ __launch_bounds__(256) void k_cell_count(Job j, const uint32_t* __restrict__ table,
-                                                    uint32_t* __restrict__ npart) {
-  const int x = blockIdx.x * kBlock + threadIdx.x;
-  if (x >= j.n_cells) return;
-  int c[3];
-  cell_of(j.g, j.clist[x], c);
-  const int cfg = cell_config(j.g, j.labels, c[0], c[1], c[2]);
-  const int fm = cell_flipmask(j.g, j.fflip, c);
-  int pm, np;
-  if (fm == 0) {
-    pm = (int)(table[cfg] & 0xFFFFFFu);
-    np = (int)(table[cfg] >> 24);
-  } else {
-    np = cube_partitions(cfg, fm, pm);
-  }
-  j.cpm[x] = (uint32_t)pm;
-  j.cnf[x] = (uint32_t)(np | (fm << 4));
-  npart[x] = (uint32_t)np;
-}
-
-hipError_t launch_cell_count(Job& j, uint32_t* npart, const uint32_t* table, hipStream_t s) {
-  if (j.n_cells == 0) return hipSuccess;
-  k_cell_count<<<nblocks(j.n_cells), kBlock, 0, s>>>(j, table, npart);
-  return hipGetLastError();
+__global__ __launch_bounds__(256) void k_cell_count(const Job* __restrict__ jobs, int njobs,
+                                                    const uint32_t* __restrict__ table) {
+  for_units(jobs, njobs, gthread(), nthreads(), [](const Job& J) { return n_cells_of(J); },
+            [&](const Job& J, int x) {
+              int c[3];
+              cell_of(J.g, J.clist[x], c);
+              const int cfg = cell_config(J.g, J.labels, c[0], c[1], c[2]);
+              const int fm = cell_flipmask(J.g, J.fflip, c);
+              int pm, np;
+              if (fm == 0) {
+                pm = (int)(table[cfg] & 0xFFFFFFu);
+                np = (int)(table[cfg] >> 24);
+              } else {
+                np = cube_partitions(cfg, fm, pm);
+              }
+              J.cpm[x] = (uint32_t)pm;
+              J.cnf[x] = (uint32_t)(np | (fm << 4));
+              J.npart[x] = (uint32_t)np;
+            });
 }
 
 template <typename T>
@@ -864,10 +931,7 @@ __device__ __forceinline__ void cell_face_point(const Job& j, const int c[3], in
   int slot = 0;
   for (int k = 0; k < np; ++k)
     if (pa[k] == fe || pb[k] == fe) slot = k;
-  const int w = face >> 5;
-  const uint32_t below = (1u << (face & 31)) - 1u;
-  const int base = (int)j.pprefix[w] + __popc(j.fact[w] & below) + __popc(j.famb[w] & below);
-  const double2 pf = j.pf[base + slot];
+  const double2 pf = j.pf[pair_slot(j, face) + slot];
   out[fa] = (double)side;
   out[u] = pf.x;
   out[v] = pf.y;
@@ -878,9 +942,8 @@ __device__ __forceinline__ void cell_face_point(const Job& j, const int c[3], in
 // directions from its 1D point to the 2D points on the cell's two faces that
 // hold it.  The differences are taken in binary64 from the binary64 2D points
 // and then rounded to T.  Returns false for a zero cross product.
-template <typename T>
 __device__ __forceinline__ bool edge_plane(const Job& j, const int c[3], int fm, int le,
-                                           T pe[3], T n[3]) {
+                                           double pe[3], double n[3]) {
   const int ax = le >> 2;
   int b1, b2;
   other_axes(ax, b1, b2);
@@ -888,24 +951,24 @@ __device__ __forceinline__ bool edge_plane(const Job& j, const int c[3], int fm,
   off[b1] = le & 1;
   off[b2] = (le >> 1) & 1;
   const int gid = edge_index(j.g, ax, c[0] + off[0], c[1] + off[1], c[2] + off[2]);
-  const float t = j.et[rank_of(j.emask, j.eprefix, gid)];
+  const float t = j.et[edge_slot(j, gid)];
   double ped[3] = {(double)off[0], (double)off[1], (double)off[2]};
   ped[ax] = (double)t;
   double f1[3], f2[3];
   cell_face_point(j, c, fm, b1, off[b1], le, f1);
   cell_face_point(j, c, fm, b2, off[b2], le, f2);
-  T d1[3], d2[3];
+  double d1[3], d2[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    pe[k] = (T)ped[k];
-    d1[k] = (T)(f1[k] - ped[k]);
-    d2[k] = (T)(f2[k] - ped[k]);
+    pe[k] = ped[k];
+    d1[k] = f1[k] - ped[k];
+    d2[k] = f2[k] - ped[k];
   }
   n[0] = d1[1] * d2[2] - d1[2] * d2[1];
   n[1] = d1[2] * d2[0] - d1[0] * d2[2];
   n[2] = d1[0] * d2[1] - d1[1] * d2[0];
-  const T nl = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-  if (!(nl > T(0))) return false;
+  const double nl = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  if (!(nl > 0.0)) return false;
 #pragma unroll
   for (int k = 0; k < 3; ++k) n[k] /= nl;
   return true;
@@ -914,15 +977,20 @@ __device__ __forceinline__ bool edge_plane(const Job& j, const int c[3], int fm,
 // QEF of one partition (Eq. 2 with normals from 2D points, Sec. 5.3) in
 // cell-local coordinates: mass point c of the 1D points, A = sum n n^T,
 // b = sum n n.(p_e - c), x = c + A^+_tau b with eigenvalues below
-// tau * max dropped, plus one refinement step x += A^+_tau (b - A x) that
-// recovers the accuracy the binary32 eigen-decomposition loses.  Returns
+// tau * max dropped.  The planes, A, b and the residual are binary64; T is
+// the precision of the eigen-decomposition.  With T = float the solve is
+// one pseudo-inverse application plus one refinement step on the binary64
+// residual, x += A^+_tau (b - A x): the retained eigenvalues can be as small
+// as tau * max, which would amplify the binary32 rounding of the
+// decomposition ~1/tau-fold, and the refinement removes that.  Returns
 // false when T is float and the normal matrix's condition number exceeds
-// fp64_cond (the caller redoes the solve in binary64).
+// fp64_cond (including a singular matrix); the caller then redoes the
+// decomposition in binary64.
 template <typename T>
 __device__ bool qef_partition(const Job& j, const int c[3], int cfg, int fm, uint32_t pm,
-                              int part, T x[3]) {
+                              int part, double x[3]) {
   // pass 1: mass point of the 1D points
-  T cs[3] = {0, 0, 0};
+  double cs[3] = {0, 0, 0};
   int cnt = 0;
   for (int le = 0; le < 12; ++le) {
     if (!cube_edge_crosses(cfg, le) || (int)((pm >> (2 * le)) & 3u) != part) continue;
@@ -933,26 +1001,26 @@ __device__ bool qef_partition(const Job& j, const int c[3], int cfg, int fm, uin
     off[b1] = le & 1;
     off[b2] = (le >> 1) & 1;
     const int gid = edge_index(j.g, ax, c[0] + off[0], c[1] + off[1], c[2] + off[2]);
-    T pe[3] = {(T)off[0], (T)off[1], (T)off[2]};
-    pe[ax] = (T)j.et[rank_of(j.emask, j.eprefix, gid)];
+    double pe[3] = {(double)off[0], (double)off[1], (double)off[2]};
+    pe[ax] = (double)j.et[edge_slot(j, gid)];
 #pragma unroll
     for (int k = 0; k < 3; ++k) cs[k] += pe[k];
     ++cnt;
   }
-  T cm[3];
+  double cm[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    cm[k] = cs[k] / (T)(cnt > 0 ? cnt : 1);
+    cm[k] = cs[k] / (double)(cnt > 0 ? cnt : 1);
     x[k] = cm[k];
   }
   // pass 2: planes
-  T A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, b[3] = {0, 0, 0};
+  double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, b[3] = {0, 0, 0};
   int used = 0;
   for (int le = 0; le < 12; ++le) {
     if (!cube_edge_crosses(cfg, le) || (int)((pm >> (2 * le)) & 3u) != part) continue;
-    T pe[3], n[3];
-    if (!edge_plane<T>(j, c, fm, le, pe, n)) continue;
-    const T dd = n[0] * (pe[0] - cm[0]) + n[1] * (pe[1] - cm[1]) + n[2] * (pe[2] - cm[2]);
+    double pe[3], n[3];
+    if (!edge_plane(j, c, fm, le, pe, n)) continue;
+    const double dd = n[0] * (pe[0] - cm[0]) + n[1] * (pe[1] - cm[1]) + n[2] * (pe[2] - cm[2]);
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
       b[r] += n[r] * dd;
@@ -966,24 +1034,24 @@ __device__ bool qef_partition(const Job& j, const int c[3], int cfg, int fm, uin
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) M[r][k] = A[r][k];
+    for (int k = 0; k < 3; ++k) M[r][k] = (T)A[r][k];
   T V[3][3], ev[3];
   jacobi3<T>(M, V, ev);
   const T lmax = fmax(ev[0], fmax(ev[1], ev[2]));
   const T lmin = fmin(ev[0], fmin(ev[1], ev[2]));
   if (sizeof(T) == 4 && (lmin <= T(0) || (double)lmax > j.fp64_cond * (double)lmin)) return false;
   const T thr = (T)j.qef_tau * lmax;
-  T y[3] = {0, 0, 0};
+  double y[3] = {0, 0, 0};
   for (int pass = 0; pass < 2; ++pass) {
-    T r[3];
+    double r[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) r[q] = b[q] - (A[q][0] * y[0] + A[q][1] * y[1] + A[q][2] * y[2]);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       if (!(ev[k] >= thr) || ev[k] <= T(0)) continue;
-      const T vr = V[0][k] * r[0] + V[1][k] * r[1] + V[2][k] * r[2];
+      const double vr = (double)V[0][k] * r[0] + (double)V[1][k] * r[1] + (double)V[2][k] * r[2];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) y[a] += V[a][k] * vr / ev[k];
+      for (int a = 0; a < 3; ++a) y[a] += (double)V[a][k] * vr / (double)ev[k];
     }
   }
 #pragma unroll
@@ -991,61 +1059,45 @@ __device__ bool qef_partition(const Job& j, const int c[3], int cfg, int fm, uin
   return true;
 }
 
-__global__ __launch_bounds__(256) void k_cell_qef(Job j) {
-  const int x = blockIdx.x * kBlock + threadIdx.x;
-  int fp64 = 0;
-  if (x < j.n_cells) {
-    const int cid = j.clist[x];
-    int c[3];
-    cell_of(j.g, cid, c);
-    const int cfg = cell_config(j.g, j.labels, c[0], c[1], c[2]);
-    const uint32_t pm = j.cpm[x];
-    const int np = (int)(j.cnf[x] & 15u), fm = (int)(j.cnf[x] >> 4);
-    const int vb = (int)j.vbase[x];
-    for (int part = 0; part < np; ++part) {
-      float v[3];
-      float xf[3];
-      if (qef_partition<float>(j, c, cfg, fm, pm, part, xf)) {
-        v[0] = xf[0]; v[1] = xf[1]; v[2] = xf[2];
-      } else {
-        double xd[3];
-        qef_partition<double>(j, c, cfg, fm, pm, part, xd);
-        v[0] = (float)xd[0]; v[1] = (float)xd[1]; v[2] = (float)xd[2];
-        ++fp64;
-      }
-      const int vid = vb + part;
-      j.vloc[3 * vid] = v[0];
-      j.vloc[3 * vid + 1] = v[1];
-      j.vloc[3 * vid + 2] = v[2];
-      if (vid < j.cap_v) {
-        const float gp[3] = {(float)c[0] + v[0], (float)c[1] + v[1], (float)c[2] + v[2]};
-        float w[3];
-        grid_world(j.g, gp, w);
-        j.out_v[3 * vid] = w[0];
-        j.out_v[3 * vid + 1] = w[1];
-        j.out_v[3 * vid + 2] = w[2];
-        if (j.out_vloc) {
-          j.out_vloc[3 * vid] = v[0];
-          j.out_vloc[3 * vid + 1] = v[1];
-          j.out_vloc[3 * vid + 2] = v[2];
-        }
-        if (j.out_vref) j.out_vref[vid] = corner_index(j.g, c[0], c[1], c[2]);
-      }
-    }
-  }
-  // one atomic per wave
-  const uint64_t any = __ballot(fp64 != 0);
-  if (any) {
-    int tot = fp64;
-    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
-    if (lane_id() == 0) atomicAdd(&j.counters[1], (unsigned long long)tot);
-  }
-}
-
-hipError_t launch_cell_qef(Job& j, hipStream_t s) {
-  if (j.n_cells == 0) return hipSuccess;
-  k_cell_qef<<<nblocks(j.n_cells), kBlock, 0, s>>>(j);
-  return hipGetLastError();
+__global__ __launch_bounds__(256) void k_cell_qef(const Job* __restrict__ jobs, int njobs) {
+  for_units(jobs, njobs, gthread(), nthreads(), [](const Job& J) { return n_cells_of(J); },
+            [&](const Job& J, int x) {
+              const int cid = J.clist[x];
+              int c[3];
+              cell_of(J.g, cid, c);
+              const int cfg = cell_config(J.g, J.labels, c[0], c[1], c[2]);
+              const uint32_t pm = J.cpm[x];
+              const int np = (int)(J.cnf[x] & 15u), fm = (int)(J.cnf[x] >> 4);
+              const int vb = (int)J.vbase[x];
+              int fp64 = 0;
+              for (int part = 0; part < np; ++part) {
+                double xd[3];
+                if (!qef_partition<float>(J, c, cfg, fm, pm, part, xd)) {
+                  qef_partition<double>(J, c, cfg, fm, pm, part, xd);
+                  ++fp64;
+                }
+                const float v[3] = {(float)xd[0], (float)xd[1], (float)xd[2]};
+                const int vid = vb + part;
+                J.vloc[3 * vid] = v[0];
+                J.vloc[3 * vid + 1] = v[1];
+                J.vloc[3 * vid + 2] = v[2];
+                if (vid < J.cap_v) {
+                  const float gp[3] = {(float)c[0] + v[0], (float)c[1] + v[1], (float)c[2] + v[2]};
+                  float w[3];
+                  grid_world(J.g, gp, w);
+                  J.out_v[3 * vid] = w[0];
+                  J.out_v[3 * vid + 1] = w[1];
+                  J.out_v[3 * vid + 2] = w[2];
+                  if (J.out_vloc) {
+                    J.out_vloc[3 * vid] = v[0];
+                    J.out_vloc[3 * vid + 1] = v[1];
+                    J.out_vloc[3 * vid + 2] = v[2];
+                  }
+                  if (J.out_vref) J.out_vref[vid] = corner_index(J.g, c[0], c[1], c[2]);
+                }
+              }
+              if (fp64) atomicAdd(&J.status[1], (unsigned long long)fp64);
+            });
 }
 
 // --------------------------------------------------------------- (e) emit
@@ -1056,133 +1108,174 @@ __device__ __forceinline__ float triple3(const float a[3], const float b[3], con
   return a[0] * x + a[1] * y + a[2] * z;
 }
 
-__global__ __launch_bounds__(256) void k_emit_count(Job j, uint32_t* __restrict__ ntri,
-                                                    uint32_t* __restrict__ n3) {
-  const int x = blockIdx.x * kBlock + threadIdx.x;
-  if (x >= j.n_edges) return;
-  const Grid& g = j.g;
-  int a, p[3];
-  edge_pos(g, j.elist[x], a, p);
-  const int b = (a + 1) % 3, cc = (a + 2) % 3;
-  const int OFFB[4] = {0, -1, -1, 0}, OFFC[4] = {0, 0, -1, -1};
-  int vid[4];
-  float P[4][3];
-  for (int q = 0; q < 4; ++q) {
-    int c[3] = {p[0], p[1], p[2]};
-    c[b] += OFFB[q];
-    c[cc] += OFFC[q];
-    if (c[0] < 0 || c[1] < 0 || c[2] < 0 || c[0] >= g.N || c[1] >= g.N || c[2] >= g.N) {
-      j.ecase[x] = 0;
-      ntri[x] = 0;
-      n3[x] = 0;
-      return;
-    }
-    const int ci = rank_of(j.cmask, j.cprefix, c[0] + g.N * (c[1] + g.N * c[2]));
-    int off[3] = {p[0] - c[0], p[1] - c[1], p[2] - c[2]};
-    const int le = cell_edge(a, off);
-    const int part = (int)((j.cpm[ci] >> (2 * le)) & 3u);
-    vid[q] = (int)j.vbase[ci] + part;
+__global__ __launch_bounds__(256) void k_emit_count(const Job* __restrict__ jobs, int njobs) {
+  for_units(jobs, njobs, gthread(), nthreads(), [](const Job& J) { return n_edges_of(J); },
+            [&](const Job& J, int x) {
+              const Grid& g = J.g;
+              int a, p[3];
+              edge_pos(g, J.elist[x], a, p);
+              const int b = (a + 1) % 3, cc = (a + 2) % 3;
+              const int OFFB[4] = {0, -1, -1, 0}, OFFC[4] = {0, 0, -1, -1};
+              int vid[4];
+              float P[4][3];
+              for (int q = 0; q < 4; ++q) {
+                int c[3] = {p[0], p[1], p[2]};
+                c[b] += OFFB[q];
+                c[cc] += OFFC[q];
+                if (c[0] < 0 || c[1] < 0 || c[2] < 0 || c[0] >= g.N || c[1] >= g.N || c[2] >= g.N) {
+                  J.ecase[x] = 0;
+                  J.ntri[x] = 0;
+                  J.n3[x] = 0;
+                  return;
+                }
+                const int ci = cell_slot(J, c[0] + g.N * (c[1] + g.N * c[2]));
+                int off[3] = {p[0] - c[0], p[1] - c[1], p[2] - c[2]};
+                const int le = cell_edge(a, off);
+                const int part = (int)((J.cpm[ci] >> (2 * le)) & 3u);
+                vid[q] = (int)J.vbase[ci] + part;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) P[q][k] = (float)(c[k] - p[k]) + j.vloc[3 * vid[q] + k];
-  }
-  const int lower_in = bit_of(j.labels, corner_index(g, p[0], p[1], p[2]));
-  // c1..c4 counter-clockwise about +a; reversed when the inside end is the upper one
-  const int ord[4] = {0, lower_in ? 1 : 3, 2, lower_in ? 3 : 1};
-  float Q[4][3], pin[3] = {0, 0, 0}, pout[3] = {0, 0, 0};
-  (lower_in ? pout : pin)[a] = 1.0f;
-  int4 qd;
-  int* qv = &qd.x;
-  for (int q = 0; q < 4; ++q) {
-    qv[q] = vid[ord[q]];
+                for (int k = 0; k < 3; ++k) P[q][k] = (float)(c[k] - p[k]) + J.vloc[3 * vid[q] + k];
+              }
+              const int lower_in = bit_of(J.labels, corner_index(g, p[0], p[1], p[2]));
+              // c1..c4 counter-clockwise about +a; reversed when the inside end is the upper one
+              const int ord[4] = {0, lower_in ? 1 : 3, 2, lower_in ? 3 : 1};
+              float Q[4][3], pin[3] = {0, 0, 0}, pout[3] = {0, 0, 0};
+              (lower_in ? pout : pin)[a] = 1.0f;
+              int4 qd;
+              int* qv = &qd.x;
+              for (int q = 0; q < 4; ++q) {
+                qv[q] = vid[ord[q]];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) Q[q][k] = P[ord[q]][k];
-  }
-  // App. A.1.5: vertex k concave against v_out (Eq. A1) or v_in (Eq. A2)
-  int concave[4];
-  for (int k = 0; k < 4; ++k) {
-    const int kp = (k + 3) & 3, kn = (k + 1) & 3;
-    float u0[3], u1[3], u2[3], w0[3], w1[3], w2[3];
+                for (int k = 0; k < 3; ++k) Q[q][k] = P[ord[q]][k];
+              }
+              // App. A.1.5: vertex k concave against v_out (Eq. A1) or v_in (Eq. A2)
+              int concave[4];
+              for (int k = 0; k < 4; ++k) {
+                const int kp = (k + 3) & 3, kn = (k + 1) & 3;
+                float u0[3], u1[3], u2[3], w0[3], w1[3], w2[3];
 #pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      u0[t] = Q[k][t] - pout[t];
-      u1[t] = Q[kp][t] - pout[t];
-      u2[t] = Q[kn][t] - pout[t];
-      w0[t] = Q[k][t] - pin[t];
-      w1[t] = Q[kp][t] - pin[t];
-      w2[t] = Q[kn][t] - pin[t];
-    }
-    concave[k] = (triple3(u0, u1, u2) < 0.0f) || (triple3(w0, w1, w2) > 0.0f);
-  }
-  int cs = 3;
-  if (!concave[1] && !concave[3]) cs = 1;
-  else if (!concave[0] && !concave[2]) cs = 2;
-  j.ecase[x] = (uint32_t)cs;
-  j.quad[x] = qd;
-  ntri[x] = cs == 3 ? 4u : 2u;
-  n3[x] = cs == 3 ? 1u : 0u;
+                for (int t = 0; t < 3; ++t) {
+                  u0[t] = Q[k][t] - pout[t];
+                  u1[t] = Q[kp][t] - pout[t];
+                  u2[t] = Q[kn][t] - pout[t];
+                  w0[t] = Q[k][t] - pin[t];
+                  w1[t] = Q[kp][t] - pin[t];
+                  w2[t] = Q[kn][t] - pin[t];
+                }
+                concave[k] = (triple3(u0, u1, u2) < 0.0f) || (triple3(w0, w1, w2) > 0.0f);
+              }
+              int cs = 3;
+              if (!concave[1] && !concave[3]) cs = 1;
+              else if (!concave[0] && !concave[2]) cs = 2;
+              J.ecase[x] = (uint32_t)cs;
+              J.quad[x] = qd;
+              J.ntri[x] = cs == 3 ? 4u : 2u;
+              J.n3[x] = cs == 3 ? 1u : 0u;
+            });
 }
 
-hipError_t launch_emit_count(Job& j, uint32_t* ntri, uint32_t* n3, hipStream_t s) {
-  if (j.n_edges == 0) return hipSuccess;
-  k_emit_count<<<nblocks(j.n_edges), kBlock, 0, s>>>(j, ntri, n3);
+__global__ __launch_bounds__(256) void k_emit_write(const Job* __restrict__ jobs, int njobs) {
+  for_units(jobs, njobs, gthread(), nthreads(), [](const Job& J) { return n_edges_of(J); },
+            [&](const Job& J, int x) {
+              const int cs = (int)J.ecase[x];
+              if (cs == 0) return;
+              const int4 qd = J.quad[x];
+              const int t0 = (int)J.tprefix[x];
+              int tri[4][3];
+              int nt = 2;
+              if (cs == 1) {
+                tri[0][0] = qd.x; tri[0][1] = qd.y; tri[0][2] = qd.z;
+                tri[1][0] = qd.x; tri[1][1] = qd.z; tri[1][2] = qd.w;
+              } else if (cs == 2) {
+                tri[0][0] = qd.x; tri[0][1] = qd.y; tri[0][2] = qd.w;
+                tri[1][0] = qd.y; tri[1][1] = qd.z; tri[1][2] = qd.w;
+              } else {
+                const int nvp = (int)J.vbase[n_cells_of(J)];
+                const int ve = nvp + (int)J.c3prefix[x];
+                const int qv[4] = {qd.x, qd.y, qd.z, qd.w};
+                for (int k = 0; k < 4; ++k) {
+                  tri[k][0] = ve;
+                  tri[k][1] = qv[k];
+                  tri[k][2] = qv[(k + 1) & 3];
+                }
+                nt = 4;
+                if (ve < J.cap_v) {
+                  int a, p[3];
+                  edge_pos(J.g, J.elist[x], a, p);
+                  const float t = J.et[x];
+                  float gp[3] = {(float)p[0], (float)p[1], (float)p[2]};
+                  gp[a] = (float)p[a] + t;
+                  float w[3];
+                  grid_world(J.g, gp, w);
+                  J.out_v[3 * ve] = w[0];
+                  J.out_v[3 * ve + 1] = w[1];
+                  J.out_v[3 * ve + 2] = w[2];
+                  if (J.out_vloc) {
+                    J.out_vloc[3 * ve] = a == 0 ? t : 0.0f;
+                    J.out_vloc[3 * ve + 1] = a == 1 ? t : 0.0f;
+                    J.out_vloc[3 * ve + 2] = a == 2 ? t : 0.0f;
+                  }
+                  if (J.out_vref) J.out_vref[ve] = corner_index(J.g, p[0], p[1], p[2]);
+                }
+              }
+              for (int k = 0; k < nt; ++k) {
+                if (t0 + k >= J.cap_t) break;
+                J.out_t[3 * (t0 + k)] = tri[k][0];
+                J.out_t[3 * (t0 + k) + 1] = tri[k][1];
+                J.out_t[3 * (t0 + k) + 2] = tri[k][2];
+              }
+            });
+}
+
+// ------------------------------------------------------------ pipeline
+// The whole path for njobs jobs (device array d): one launch per stage and
+// no host synchronisation, so a stream capture of it replays as one graph.
+hipError_t launch_pipeline(const Job* d, int njobs, const PipelineShape& sh,
+                           const float* const* d_weights, const uint32_t* table,
+                           const LaunchCfg& cfg, hipEvent_t* ev, hipStream_t s) {
+  auto mark = [&](int i) {
+    if (ev) (void)hipEventRecord(ev[i], s);
+  };
+  k_clear_status<<<4, kBlock, 0, s>>>(d, njobs);
+  if (sh.any_mlp) k_pack<<<cfg.pack_blocks, kBlock, 0, s>>>(d, njobs, d_weights);
+  mark(0);
+  if (sh.any_csg) k_labels_csg<<<cfg.grid_blocks, kBlock, 0, s>>>(d, njobs);
+  if (sh.any_mlp_fp32) k_labels_mlp<0><<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
+  if (sh.any_mlp_bf16) {
+    k_labels_mlp<1><<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
+    k_relabel_fp32<<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
+  }
+  mark(1);
+  k_classify_edges<<<cfg.grid_blocks, kBlock, 0, s>>>(d, njobs);
+  k_classify_faces<<<cfg.grid_blocks, kBlock, 0, s>>>(d, njobs, table);
+  k_classify_cells<<<cfg.grid_blocks, kBlock, 0, s>>>(d, njobs);
+  scan<0>(d, njobs, cfg, s);
+  scan<1>(d, njobs, cfg, s);
+  scan<2>(d, njobs, cfg, s);
+  mark(2);
+  k_compact<<<cfg.grid_blocks, kBlock, 0, s>>>(d, njobs);
+  mark(3);
+  if (sh.any_csg) k_bisect_csg<<<cfg.elem_blocks, kBlock, 0, s>>>(d, njobs);
+  if (sh.any_mlp) k_bisect_mlp<<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
+  mark(4);
+  if (sh.any_csg) k_search2d_csg<<<cfg.elem_blocks, kBlock, 0, s>>>(d, njobs);
+  if (sh.any_mlp) k_search2d_mlp<<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
+  mark(5);
+  k_cell_count<<<cfg.elem_blocks, kBlock, 0, s>>>(d, njobs, table);
+  scan<3>(d, njobs, cfg, s);
+  mark(6);
+  k_cell_qef<<<cfg.elem_blocks, kBlock, 0, s>>>(d, njobs);
+  mark(7);
+  k_emit_count<<<cfg.elem_blocks, kBlock, 0, s>>>(d, njobs);
+  scan<4>(d, njobs, cfg, s);
+  scan<5>(d, njobs, cfg, s);
+  k_emit_write<<<cfg.elem_blocks, kBlock, 0, s>>>(d, njobs);
+  mark(8);
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_emit_write(Job j) {
-  const int x = blockIdx.x * kBlock + threadIdx.x;
-  if (x >= j.n_edges) return;
-  const int cs = (int)j.ecase[x];
-  if (cs == 0) return;
-  const int4 qd = j.quad[x];
-  const int t0 = (int)j.tprefix[x];
-  int tri[4][3];
-  int nt = 2;
-  if (cs == 1) {
-    tri[0][0] = qd.x; tri[0][1] = qd.y; tri[0][2] = qd.z;
-    tri[1][0] = qd.x; tri[1][1] = qd.z; tri[1][2] = qd.w;
-  } else if (cs == 2) {
-    tri[0][0] = qd.x; tri[0][1] = qd.y; tri[0][2] = qd.w;
-    tri[1][0] = qd.y; tri[1][1] = qd.z; tri[1][2] = qd.w;
-  } else {
-    const int nvp = (int)j.vbase[j.n_cells];
-    const int ve = nvp + (int)j.c3prefix[x];
-    const int qv[4] = {qd.x, qd.y, qd.z, qd.w};
-    for (int k = 0; k < 4; ++k) {
-      tri[k][0] = ve;
-      tri[k][1] = qv[k];
-      tri[k][2] = qv[(k + 1) & 3];
-    }
-    nt = 4;
-    if (ve < j.cap_v) {
-      int a, p[3];
-      edge_pos(j.g, j.elist[x], a, p);
-      const float t = j.et[x];
-      float gp[3] = {(float)p[0], (float)p[1], (float)p[2]};
-      gp[a] = (float)p[a] + t;
-      float w[3];
-      grid_world(j.g, gp, w);
-      j.out_v[3 * ve] = w[0];
-      j.out_v[3 * ve + 1] = w[1];
-      j.out_v[3 * ve + 2] = w[2];
-      if (j.out_vloc) {
-        j.out_vloc[3 * ve] = a == 0 ? t : 0.0f;
-        j.out_vloc[3 * ve + 1] = a == 1 ? t : 0.0f;
-        j.out_vloc[3 * ve + 2] = a == 2 ? t : 0.0f;
-      }
-      if (j.out_vref) j.out_vref[ve] = corner_index(j.g, p[0], p[1], p[2]);
-    }
-  }
-  for (int k = 0; k < nt; ++k) {
-    if (t0 + k >= j.cap_t) break;
-    j.out_t[3 * (t0 + k)] = tri[k][0];
-    j.out_t[3 * (t0 + k) + 1] = tri[k][1];
-    j.out_t[3 * (t0 + k) + 2] = tri[k][2];
-  }
-}
-
-hipError_t launch_emit_write(Job& j, hipStream_t s) {
-  if (j.n_edges == 0) return hipSuccess;
-  k_emit_write<<<nblocks(j.n_edges), kBlock, 0, s>>>(j);
+hipError_t launch_gather(const Job* d, int njobs, unsigned long long* out, hipStream_t s) {
+  k_gather<<<4, kBlock, 0, s>>>(d, njobs, out);
   return hipGetLastError();
 }
 
@@ -1190,22 +1283,22 @@ hipError_t launch_emit_write(Job& j, hipStream_t s) {
 __global__ __launch_bounds__(256) void k_eval_csg(const float* __restrict__ prims, int np,
                                                   const float* __restrict__ xyz, int n,
                                                   float* __restrict__ z) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const float x[3] = {xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]};
-  z[i] = csg_inside(prims, np, x) ? 1.0f : -1.0f;
+  for (int i = gthread(); i < n; i += nthreads()) {
+    const float x[3] = {xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]};
+    z[i] = csg_inside(prims, np, x) ? 1.0f : -1.0f;
+  }
 }
 
 template <int BF16>
-__global__ __launch_bounds__(256) void k_eval_mlp(Mlp m, const float* __restrict__ xyz, int n,
+__global__ __launch_bounds__(256) void k_eval_mlp(const Job* __restrict__ job,
+                                                  const float* __restrict__ xyz, int n,
                                                   float* __restrict__ z) {
   __shared__ float act_lds[kBlock / 64][BF16 ? kActVecsBF16 * 4 : kActWords];
   float* act = act_lds[threadIdx.x >> 6];
-  const int lane = lane_id(), col = lane & 31;
-  const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
-  const int nwaves = gridDim.x * (kBlock / 64);
-  for (int t = wave; t * 32 < n; t += nwaves) {
-    const int i = t * 32 + col;
+  const Mlp& m = job->mlp;
+  const int lane = lane_id();
+  for (int t = gwave(); t * 32 < n; t += nwaves()) {
+    const int i = t * 32 + (lane & 31);
     const int k = i < n ? i : n - 1;
     const float x[3] = {xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2]};
     const float v = BF16 ? mlp_logit_bf16(m, x, reinterpret_cast<v8bf*>(act))
@@ -1214,16 +1307,15 @@ __global__ __launch_bounds__(256) void k_eval_mlp(Mlp m, const float* __restrict
   }
 }
 
-hipError_t launch_eval(int kind, int precision, const float* prims, int np, const Mlp& m,
-                       const float* xyz, int n, float* z, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  if (kind == 0) {
-    k_eval_csg<<<nblocks(n), kBlock, 0, s>>>(prims, np, xyz, n, z);
+hipError_t launch_eval(const Job* d_job, const Job& h_job, const float* const* d_weights,
+                       int precision, const float* xyz, int n, float* z, const LaunchCfg& cfg,
+                       hipStream_t s) {
+  if (h_job.kind == 0) {
+    k_eval_csg<<<cfg.elem_blocks, kBlock, 0, s>>>(h_job.prims, h_job.n_prims, xyz, n, z);
   } else {
-    const int tiles = (n + 31) / 32;
-    const int blocks = tiles / 4 + 1 < 2048 ? tiles / 4 + 1 : 2048;
-    if (precision == 0) k_eval_mlp<0><<<blocks, kBlock, 0, s>>>(m, xyz, n, z);
-    else k_eval_mlp<1><<<blocks, kBlock, 0, s>>>(m, xyz, n, z);
+    k_pack<<<cfg.pack_blocks, kBlock, 0, s>>>(d_job, 1, d_weights);
+    if (precision == 0) k_eval_mlp<0><<<cfg.mlp_blocks, kBlock, 0, s>>>(d_job, xyz, n, z);
+    else k_eval_mlp<1><<<cfg.mlp_blocks, kBlock, 0, s>>>(d_job, xyz, n, z);
   }
   return hipGetLastError();
 }

@@ -8,7 +8,8 @@
 // tile holds, in lane l and register r, output row 8(r/4) + 4(l/32) + r%4 of
 // column l%32; the next layer consumes exactly those registers as its B
 // operand, which fixes a permutation of the K index that the packed weights
-// absorb.  Activations therefore never leave registers.
+// absorb.  Between layers the activations are parked in LDS (see
+// mlp_logit_fp32), which frees registers for the weight prefetch.
 //
 //  fp32 path  v_mfma_f32_32x32x2_f32: K block b (2 rows), lane half h gives
 //             row 2b+h.  Hidden-layer virtual K row (b = 16T + i, h) is
@@ -37,6 +38,25 @@ constexpr int kMaxInDim = 45;
 constexpr int kHiddenBlocksF32 = kWidth / 2;    // 128 K blocks of 2
 constexpr int kHiddenBlocksBF16 = kWidth / 16;  // 16 K blocks of 16
 
+// Pointers that are known to address device global memory.  The kernels
+// read the job records from memory, so the pointers inside are generic; a
+// load through a generic pointer is a flat load, which also counts against
+// the LDS wait counter and stalls the LDS/matrix-core pipeline.  Weight
+// reads therefore go through global-qualified copies.
+#define ODC_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const ODC_GLOBAL T* gmem(const T* p) {
+  return (const ODC_GLOBAL T*)p;
+}
+// Read-only for the whole launch (biases, output weights, sdf spheres: the
+// packing runs in an earlier kernel): wave-uniform reads through the
+// constant address space become scalar loads.
+#define ODC_CONST __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ const ODC_CONST T* cmem(const T* p) {
+  return (const ODC_CONST T*)p;
+}
+
 struct Mlp {
   const float* w1f;  // [kb1f][8][64]            layer 1, fp32 fragments
   const float* whf;  // [depth-1][128][8][64]    hidden layers, fp32 fragments
@@ -45,12 +65,21 @@ struct Mlp {
   const float* bias; // [depth][256]
   const float* wout; // [256]
   const float* spheres;
-  float bout;
+  const float* bout;  // the output bias, read in place from the caller's weights
   float sdf_gain, out_scale;
   int n_spheres, depth, in_dim, kb1f, kb1b;
 };
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Entry of a per-neuron vector (bias, output weights) for accumulator
+// register i of tile T in lane half h: neuron 32 T + 8 (i/4) + 4 h + i%4.
+// Both candidates are wave-uniform (scalar loads); the lane half selects.
+__device__ __forceinline__ float bias_of(const ODC_CONST float* v, int T, int i, int h) {
+  const int n0 = 32 * T + 8 * (i >> 2) + (i & 3);
+  const float lo = v[n0], hi = v[n0 + 4];
+  return h ? hi : lo;
+}
 
 // Feature k of gamma(x): (x, y, z), then per band j: sin(2^j pi x_a), a < 3,
 // then cos(2^j pi x_a); 0 past in_dim.  The argument 2^j x is exact.
@@ -70,10 +99,10 @@ __device__ __forceinline__ float mlp_feature(int k, const float x[3], int in_dim
 __device__ __forceinline__ float mlp_finish(const Mlp& M, float part, const float x[3]) {
   const float other = __shfl_xor(part, 32);
   const float y0 = (lane_id() < 32) ? (part + other) : (other + part);
-  const float y = y0 + M.bout;
+  const float y = y0 + *cmem(M.bout);
   float sdf = INFINITY;
   for (int s = 0; s < M.n_spheres; ++s) {
-    const float* sp = M.spheres + 4 * s;
+    const ODC_CONST float* sp = cmem(M.spheres) + 4 * s;
     const float dx = x[0] - sp[0], dy = x[1] - sp[1], dz = x[2] - sp[2];
     const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
     const float d = sqrtf((xx + yy) + zz) - sp[3];
@@ -92,6 +121,14 @@ __device__ __forceinline__ float mlp_finish(const Mlp& M, float part, const floa
 // is to free 128 registers per lane for the weight-fragment prefetch.
 constexpr int kActWords = kHiddenBlocksF32 * 64;
 
+// Weight fragments of the hidden layers are streamed through a ring of
+// kPrefetchF32 K blocks held in registers: the load of block b + kPrefetchF32
+// is issued as block b is consumed, so each load has about kPrefetchF32 x 8
+// matrix-core instructions (~2000 cycles) to arrive.  The hidden layers are
+// contiguous in memory and the ring runs across layer boundaries; the packed
+// buffer carries kPrefetchF32 K blocks of padding after the last layer.
+constexpr int kPrefetchF32 = 4;
+
 __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
                                                 float* __restrict__ act) {
   const int lane = lane_id();
@@ -100,44 +137,76 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
 #pragma unroll
   for (int R = 0; R < 8; ++R) acc[R] = (v16f){};
   for (int b = 0; b < M.kb1f; ++b) {
+    const ODC_GLOBAL float* wp = gmem(M.w1f) + (size_t)b * 8 * 64 + lane;
+    float w[8];
+#pragma unroll
+    for (int R = 0; R < 8; ++R) w[R] = wp[R * 64];
     const float bv = mlp_feature(2 * b + h, x, M.in_dim);
-    const float* wp = M.w1f + (size_t)b * 8 * 64 + lane;
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int R = 0; R < 8; ++R)
-      acc[R] = __builtin_amdgcn_mfma_f32_32x32x2f32(wp[R * 64], bv, acc[R], 0, 0, 0);
+      acc[R] = __builtin_amdgcn_mfma_f32_32x32x2f32(w[R], bv, acc[R], 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
   }
+  // the ring's first blocks load while the first transition runs.  The
+  // offset is an opaque zero so that these loads stay here: hoisted out of a
+  // caller's query loop they would pin 32 registers for its whole length.
+  int zero = 0;
+  asm volatile("" : "+v"(zero));
+  const ODC_GLOBAL float* Wh = gmem(M.whf) + lane + zero;
+  float wr[kPrefetchF32][8];
+#pragma unroll
+  for (int d = 0; d < kPrefetchF32; ++d)
+#pragma unroll
+    for (int R = 0; R < 8; ++R) wr[d][R] = Wh[(d * 8 + R) * 64];
   for (int l = 1; l < M.depth; ++l) {
-    const float* bl = M.bias + (l - 1) * kWidth;
+    const ODC_CONST float* bl = cmem(M.bias) + (l - 1) * kWidth;
+    // bias, ReLU and park, one 32-row tile at a time (bounds the live range)
 #pragma unroll
-    for (int T = 0; T < 8; ++T)
+    for (int T = 0; T < 8; ++T) {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int n = 32 * T + 8 * (i >> 2) + 4 * h + (i & 3);
-        act[(16 * T + i) * 64 + lane] = fmaxf(acc[T][i] + bl[n], 0.0f);
+      for (int i = 0; i < 16; ++i)
+        act[(16 * T + i) * 64 + lane] = fmaxf(acc[T][i] + bias_of(bl, T, i, h), 0.0f);
+      acc[T] = (v16f){};
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // block b of this layer is block (l-1)*128 + b of the stream
+    const ODC_GLOBAL float* Wn =
+        Wh + ((size_t)(l - 1) * kHiddenBlocksF32 + kPrefetchF32) * 8 * 64;
+    float bvn = act[lane];
+    // fully unrolled: a loop back-edge here makes the wait-count insertion
+    // drain every load in flight at the top of each trip
+#pragma unroll
+    for (int b0 = 0; b0 < kHiddenBlocksF32; b0 += kPrefetchF32) {
+#pragma unroll
+      for (int d = 0; d < kPrefetchF32; ++d) {
+        const int b = b0 + d;
+        const float bv = bvn;
+        bvn = act[((b + 1) & (kHiddenBlocksF32 - 1)) * 64 + lane];
+#pragma unroll
+        for (int R = 0; R < 8; ++R)
+          acc[R] = __builtin_amdgcn_mfma_f32_32x32x2f32(wr[d][R], bv, acc[R], 0, 0, 0);
+        // refill the slot just consumed (same registers: no copies)
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int R = 0; R < 8; ++R) wr[d][R] = Wn[((size_t)b * 8 + R) * 64];
+        __builtin_amdgcn_sched_barrier(0);
       }
-#pragma unroll
-    for (int R = 0; R < 8; ++R) acc[R] = (v16f){};
-    const float* W = M.whf + (size_t)(l - 1) * kHiddenBlocksF32 * 8 * 64 + lane;
-#pragma unroll 8
-    for (int b = 0; b < kHiddenBlocksF32; ++b) {
-      const float* wp = W + (size_t)b * 8 * 64;
-      const float bv = act[b * 64 + lane];
-#pragma unroll
-      for (int R = 0; R < 8; ++R)
-        acc[R] = __builtin_amdgcn_mfma_f32_32x32x2f32(wp[R * 64], bv, acc[R], 0, 0, 0);
     }
   }
-  const float* bl = M.bias + (M.depth - 1) * kWidth;
+  const ODC_CONST float* bl = cmem(M.bias) + (M.depth - 1) * kWidth;
+  const ODC_CONST float* wo = cmem(M.wout);
   float part = 0.0f;
 #pragma unroll
-  for (int T = 0; T < 8; ++T)
+  for (int T = 0; T < 8; ++T) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      const int n = 32 * T + 8 * (i >> 2) + 4 * h + (i & 3);
-      const float a = fmaxf(acc[T][i] + bl[n], 0.0f);
-      const float p = M.wout[n] * a;
+      const float a = fmaxf(acc[T][i] + bias_of(bl, T, i, h), 0.0f);
+      const float p = bias_of(wo, T, i, h) * a;
       part = part + p;
     }
+    __builtin_amdgcn_sched_barrier(0);
+  }
   return mlp_finish(M, part, x);
 }
 
@@ -145,6 +214,9 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
 // is this wavefront's LDS region of kActBlocksBF16 * 64 eight-element bf16
 // vectors, used as in the fp32 path.
 constexpr int kActVecsBF16 = kHiddenBlocksBF16 * 64;
+// Ring depth of the bf16 hidden-layer weight stream (K blocks of 16 rows;
+// 32 registers per block), as in the fp32 path.
+constexpr int kPrefetchBF16 = 4;
 
 __device__ __forceinline__ float mlp_logit_bf16(const Mlp& M, const float x[3],
                                                 v8bf* __restrict__ act) {
@@ -154,52 +226,77 @@ __device__ __forceinline__ float mlp_logit_bf16(const Mlp& M, const float x[3],
 #pragma unroll
   for (int R = 0; R < 8; ++R) acc[R] = (v16f){};
   for (int b = 0; b < M.kb1b; ++b) {
+    const ODC_GLOBAL v8bf* wp = gmem(M.w1b) + (size_t)b * 8 * 64 + lane;
+    v8bf w[8];
+#pragma unroll
+    for (int R = 0; R < 8; ++R) w[R] = wp[R * 64];
     v8bf bv;
 #pragma unroll
     for (int j = 0; j < 8; ++j) bv[j] = (__bf16)mlp_feature(16 * b + 8 * h + j, x, M.in_dim);
-    const v8bf* wp = M.w1b + (size_t)b * 8 * 64 + lane;
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int R = 0; R < 8; ++R)
-      acc[R] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wp[R * 64], bv, acc[R], 0, 0, 0);
+      acc[R] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[R], bv, acc[R], 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
   }
-  for (int l = 1; l < M.depth; ++l) {
-    const float* bl = M.bias + (l - 1) * kWidth;
+  int zero = 0;  // keeps the ring prologue here (see mlp_logit_fp32)
+  asm volatile("" : "+v"(zero));
+  const ODC_GLOBAL v8bf* Wh = gmem(M.whb) + lane + zero;
+  v8bf wr[kPrefetchBF16][8];
 #pragma unroll
-    for (int T = 0; T < 8; ++T)
+  for (int d = 0; d < kPrefetchBF16; ++d)
+#pragma unroll
+    for (int R = 0; R < 8; ++R) wr[d][R] = Wh[(d * 8 + R) * 64];
+  for (int l = 1; l < M.depth; ++l) {
+    // scalar bias reads: vector loads here would queue behind the ring's
+    // refills and wait for all of them
+    const ODC_CONST float* bl = cmem(M.bias) + (l - 1) * kWidth;
+#pragma unroll
+    for (int T = 0; T < 8; ++T) {
 #pragma unroll
       for (int beta = 0; beta < 2; ++beta) {
         v8bf v;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const int i = 8 * beta + j;
-          const int n = 32 * T + 8 * (i >> 2) + 4 * h + (i & 3);
-          v[j] = (__bf16)fmaxf(acc[T][i] + bl[n], 0.0f);
+          v[j] = (__bf16)fmaxf(acc[T][i] + bias_of(bl, T, i, h), 0.0f);
         }
         act[(2 * T + beta) * 64 + lane] = v;
       }
+      acc[T] = (v16f){};
+    }
+    const ODC_GLOBAL v8bf* Wn =
+        Wh + ((size_t)(l - 1) * kHiddenBlocksBF16 + kPrefetchBF16) * 8 * 64;
+    v8bf bvn = act[lane];
 #pragma unroll
-    for (int R = 0; R < 8; ++R) acc[R] = (v16f){};
-    const v8bf* W = M.whb + (size_t)(l - 1) * kHiddenBlocksBF16 * 8 * 64 + lane;
-#pragma unroll 4
-    for (int b = 0; b < kHiddenBlocksBF16; ++b) {
-      const v8bf* wp = W + (size_t)b * 8 * 64;
-      const v8bf bv = act[b * 64 + lane];
+    for (int b0 = 0; b0 < kHiddenBlocksBF16; b0 += kPrefetchBF16) {
 #pragma unroll
-      for (int R = 0; R < 8; ++R)
-        acc[R] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wp[R * 64], bv, acc[R], 0, 0, 0);
+      for (int d = 0; d < kPrefetchBF16; ++d) {
+        const int b = b0 + d;
+        const v8bf bv = bvn;
+        bvn = act[((b + 1) & (kHiddenBlocksBF16 - 1)) * 64 + lane];
+#pragma unroll
+        for (int R = 0; R < 8; ++R)
+          acc[R] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[d][R], bv, acc[R], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int R = 0; R < 8; ++R) wr[d][R] = Wn[((size_t)b * 8 + R) * 64];
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
   }
-  const float* bl = M.bias + (M.depth - 1) * kWidth;
+  const ODC_GLOBAL float* bl = gmem(M.bias) + (M.depth - 1) * kWidth;
   float part = 0.0f;
 #pragma unroll
-  for (int T = 0; T < 8; ++T)
+  for (int T = 0; T < 8; ++T) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int n = 32 * T + 8 * (i >> 2) + 4 * h + (i & 3);
       const float a = fmaxf(acc[T][i] + bl[n], 0.0f);
-      const float p = M.wout[n] * a;
+      const float p = gmem(M.wout)[n] * a;
       part = part + p;
     }
+  }
   return mlp_finish(M, part, x);
 }
 

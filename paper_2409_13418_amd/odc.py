@@ -60,9 +60,35 @@ class MeshCounts(C.Structure):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("n_lanes", C.c_int32), ("max_batch", C.c_int32),
+                ("max_batch_corners", C.c_int64)]
+
+
+class RequestResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("attempts", C.c_int32), ("counts", MeshCounts),
+                ("submit_ms", C.c_double), ("admit_ms", C.c_double), ("done_ms", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("submitted", "completed", "failed", "queued",
+                                          "in_flight", "batches", "active_cells")] + \
+               [(n, C.c_double) for n in ("p50_ms", "p99_ms", "mean_ms", "max_ms", "window_s",
+                                           "cells_per_s")] + \
+               [("arena_bytes", C.c_int64), ("arena_peak_bytes", C.c_int64)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 EXPORTS = ("odc_status_string", "odc_last_error", "odc_context_create", "odc_context_destroy",
            "odc_params_default", "odc_mesh_extract", "odc_mesh_sync", "odc_get_intermediate",
-           "odc_context_set_timing", "odc_get_stage_times", "odc_field_eval")
+           "odc_context_set_timing", "odc_get_stage_times", "odc_field_eval",
+           "odc_mesh_extract_batch", "odc_mesh_sync_batch", "odc_context_set_graph",
+           "odc_autotune", "odc_set_launch_config", "odc_server_create", "odc_server_destroy",
+           "odc_server_last_error", "odc_server_footprint", "odc_server_submit",
+           "odc_server_poll", "odc_server_wait", "odc_server_get_stats",
+           "odc_server_reset_stats")
 STAGES = ("labels", "classify", "compact", "bisect", "search2d", "cell_count", "cell_qef", "emit")
 
 _lib = None
@@ -102,6 +128,38 @@ def load(path: str = LIB_PATH):
     L.odc_field_eval.argtypes = [C.c_void_p, C.POINTER(Field), C.c_int32, C.c_void_p, C.c_int64,
                                  C.c_void_p]
     L.odc_field_eval.restype = C.c_int32
+    L.odc_mesh_extract_batch.argtypes = [C.c_void_p, C.c_int32, C.POINTER(Field),
+                                         C.POINTER(Params), C.POINTER(MeshBuffers)]
+    L.odc_mesh_extract_batch.restype = C.c_int32
+    L.odc_mesh_sync_batch.argtypes = [C.c_void_p, C.c_int32, C.POINTER(MeshCounts)]
+    L.odc_mesh_sync_batch.restype = C.c_int32
+    L.odc_context_set_graph.argtypes = [C.c_void_p, C.c_int32]
+    L.odc_context_set_graph.restype = C.c_int32
+    L.odc_autotune.argtypes = [C.c_void_p, C.POINTER(Field), C.POINTER(Params),
+                               C.POINTER(C.c_int32)]
+    L.odc_autotune.restype = C.c_int32
+    L.odc_set_launch_config.argtypes = [C.c_void_p, C.POINTER(C.c_int32)]
+    L.odc_set_launch_config.restype = C.c_int32
+    L.odc_server_create.argtypes = [C.c_void_p, C.POINTER(ServerConfig), C.POINTER(C.c_void_p)]
+    L.odc_server_create.restype = C.c_int32
+    L.odc_server_destroy.argtypes = [C.c_void_p]
+    L.odc_server_destroy.restype = None
+    L.odc_server_last_error.argtypes = [C.c_void_p]
+    L.odc_server_last_error.restype = C.c_char_p
+    L.odc_server_footprint.argtypes = [C.c_void_p, C.POINTER(Field), C.POINTER(Params),
+                                       C.POINTER(C.c_int64)]
+    L.odc_server_footprint.restype = C.c_int32
+    L.odc_server_submit.argtypes = [C.c_void_p, C.POINTER(Field), C.POINTER(Params),
+                                    C.POINTER(MeshBuffers), C.POINTER(C.c_uint64)]
+    L.odc_server_submit.restype = C.c_int32
+    L.odc_server_poll.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32)]
+    L.odc_server_poll.restype = C.c_int32
+    L.odc_server_wait.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(RequestResult)]
+    L.odc_server_wait.restype = C.c_int32
+    L.odc_server_get_stats.argtypes = [C.c_void_p, C.POINTER(ServerStats)]
+    L.odc_server_get_stats.restype = C.c_int32
+    L.odc_server_reset_stats.argtypes = [C.c_void_p]
+    L.odc_server_reset_stats.restype = C.c_int32
     _lib = L
     return L
 
@@ -263,6 +321,69 @@ class Context:
         self._check(rc, "odc_field_eval")
         return z.cpu().numpy()
 
+    def set_graph(self, enable: bool):
+        self._check(load().odc_context_set_graph(self.h, 1 if enable else 0), "set_graph")
+
+    def autotune(self, dfield: DeviceField, params: Params):
+        """Times candidate launch shapes on this field; returns the chosen
+        (grid, element, matrix-core) block counts, kept for this context."""
+        ch = (C.c_int32 * 3)()
+        self._check(load().odc_autotune(self.h, C.byref(dfield.c), C.byref(params), ch),
+                    "autotune")
+        return tuple(ch)
+
+    def set_launch_config(self, grid_blocks: int, elem_blocks: int, mlp_blocks: int):
+        v = (C.c_int32 * 3)(grid_blocks, elem_blocks, mlp_blocks)
+        self._check(load().odc_set_launch_config(self.h, v), "set_launch_config")
+
+    def extract_batch(self, dfields, params_list, caps=None, want_local=False):
+        """Meshes several fields in one launch per stage.  Returns a list of
+        dicts like extract(); outputs live in per-job device tensors."""
+        torch = self.torch
+        n = len(dfields)
+        if caps is None:
+            caps = [(max(4096, 8 * p.res * p.res), max(8192, 16 * p.res * p.res))
+                    for p in params_list]
+        for attempt in range(2):
+            fa = (Field * n)(*[d.c for d in dfields])
+            pa = (Params * n)(*params_list)
+            bufs = (MeshBuffers * n)()
+            keep = []
+            for k in range(n):
+                nv, nt = caps[k]
+                v = torch.empty(3 * nv, dtype=torch.float32, device=self.device)
+                t = torch.empty(3 * nt, dtype=torch.int32, device=self.device)
+                vl = torch.empty(3 * nv, dtype=torch.float32, device=self.device) if want_local else None
+                vr = torch.empty(nv, dtype=torch.int32, device=self.device) if want_local else None
+                keep.append((v, t, vl, vr))
+                bufs[k].vertices = v.data_ptr()
+                bufs[k].cap_vertices = nv
+                bufs[k].triangles = t.data_ptr()
+                bufs[k].cap_triangles = nt
+                bufs[k].vertices_local = vl.data_ptr() if vl is not None else None
+                bufs[k].vertex_ref = vr.data_ptr() if vr is not None else None
+            L = load()
+            self._check(L.odc_mesh_extract_batch(self.h, n, fa, pa, bufs), "extract_batch")
+            counts = (MeshCounts * n)()
+            rc = L.odc_mesh_sync_batch(self.h, n, counts)
+            if rc == ERR_CAPACITY and attempt == 0:
+                caps = [(max(caps[k][0], counts[k].n_vertices + 16),
+                         max(caps[k][1], counts[k].n_triangles + 16)) for k in range(n)]
+                continue
+            self._check(rc, "sync_batch")
+            break
+        out = []
+        for k in range(n):
+            c = counts[k].as_dict()
+            v, t, vl, vr = keep[k]
+            c["vertices"] = v[:3 * c["n_vertices"]].view(-1, 3)
+            c["triangles"] = t[:3 * c["n_triangles"]].view(-1, 3)
+            if want_local:
+                c["vertices_local"] = vl[:3 * c["n_vertices"]].view(-1, 3)
+                c["vertex_ref"] = vr[:c["n_vertices"]]
+            out.append(c)
+        return out
+
     def set_timing(self, enable: bool):
         self._check(load().odc_context_set_timing(self.h, 1 if enable else 0), "set_timing")
 
@@ -289,3 +410,110 @@ class Context:
         self._check(rc, "odc_get_intermediate")
         a = t[:count * elem].cpu().numpy().view(dt)
         return a.reshape(count, 2) if name == "pair_pf" else a
+
+
+class OutputBuffers:
+    """Device output tensors of one job (vertices, triangles and optionally
+    the grid-local vertex form) and the odc_mesh_buffers that point at them."""
+
+    def __init__(self, n_vertices: int, n_triangles: int, device="cuda", want_local=False):
+        import torch
+        self.v = torch.empty(3 * n_vertices, dtype=torch.float32, device=device)
+        self.t = torch.empty(3 * n_triangles, dtype=torch.int32, device=device)
+        self.vl = torch.empty(3 * n_vertices, dtype=torch.float32, device=device) \
+            if want_local else None
+        self.vr = torch.empty(n_vertices, dtype=torch.int32, device=device) if want_local else None
+        b = MeshBuffers()
+        b.vertices = self.v.data_ptr()
+        b.cap_vertices = n_vertices
+        b.triangles = self.t.data_ptr()
+        b.cap_triangles = n_triangles
+        b.vertices_local = self.vl.data_ptr() if want_local else None
+        b.vertex_ref = self.vr.data_ptr() if want_local else None
+        self.c = b
+
+    def views(self, counts: dict) -> dict:
+        nv, nt = counts["n_vertices"], counts["n_triangles"]
+        out = {"vertices": self.v[:3 * nv].view(-1, 3), "triangles": self.t[:3 * nt].view(-1, 3)}
+        if self.vl is not None:
+            out["vertices_local"] = self.vl[:3 * nv].view(-1, 3)
+            out["vertex_ref"] = self.vr[:nv]
+        return out
+
+
+class Server:
+    """Continuous-batching request loop of libodc (odc_server_*) on the
+    context's GPU.  Field tensors and output buffers of a submitted job must
+    stay alive until wait() returns for its ticket; submit() keeps references
+    to the objects it is given until then."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, lanes: int = 2, max_batch: int = 16,
+                 max_batch_corners: int = 0):
+        L = load()
+        self.ctx = ctx
+        cfg = ServerConfig(int(hbm_budget_bytes), int(lanes), int(max_batch),
+                           int(max_batch_corners))
+        h = C.c_void_p()
+        rc = L.odc_server_create(ctx.h, C.byref(cfg), C.byref(h))
+        if rc != OK:
+            raise OdcError(rc, f"odc_server_create: {L.odc_status_string(rc).decode()}: "
+                               f"{L.odc_last_error(ctx.h).decode()}")
+        self.h = h
+        self._held = {}
+
+    def close(self):
+        if self.h:
+            load().odc_server_destroy(self.h)
+            self.h = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != OK:
+            L = load()
+            raise OdcError(rc, f"{what}: {L.odc_status_string(rc).decode()}: "
+                               f"{L.odc_server_last_error(self.h).decode()}")
+
+    def footprint(self, dfield: DeviceField, params: Params) -> int:
+        b = C.c_int64()
+        self._check(load().odc_server_footprint(self.h, C.byref(dfield.c), C.byref(params),
+                                                C.byref(b)), "footprint")
+        return int(b.value)
+
+    def submit(self, dfield: DeviceField, params: Params, out: OutputBuffers) -> int:
+        """Queues one job; returns its ticket at once."""
+        t = C.c_uint64()
+        self._check(load().odc_server_submit(self.h, C.byref(dfield.c), C.byref(params),
+                                             C.byref(out.c), C.byref(t)), "submit")
+        self._held[t.value] = (dfield, params, out)
+        return int(t.value)
+
+    def poll(self, ticket: int) -> bool:
+        d = C.c_int32()
+        self._check(load().odc_server_poll(self.h, ticket, C.byref(d)), "poll")
+        return bool(d.value)
+
+    def wait(self, ticket: int) -> dict:
+        """Blocks until the job is done; returns its status, counts and
+        host timestamps (ms since the server started) and releases it."""
+        r = RequestResult()
+        self._check(load().odc_server_wait(self.h, ticket, C.byref(r)), "wait")
+        self._held.pop(ticket, None)
+        out = r.counts.as_dict()
+        out.update(status=int(r.status), attempts=int(r.attempts), submit_ms=r.submit_ms,
+                   admit_ms=r.admit_ms, done_ms=r.done_ms,
+                   latency_ms=r.done_ms - r.submit_ms)
+        return out
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        self._check(load().odc_server_get_stats(self.h, C.byref(st)), "stats")
+        return st.as_dict()
+
+    def reset_stats(self):
+        self._check(load().odc_server_reset_stats(self.h), "reset_stats")

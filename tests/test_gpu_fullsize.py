@@ -1,0 +1,178 @@
+"""Parity at the workloads' full sizes, in the benchmark's launch shape.
+
+* CSG field at 128^3 (48 boxes + 16 spheres - 8 boxes, seed 2): the oracle
+  finishes the whole grid in about a second, so everything is compared
+  element by element, exactly as in the small parity tests.
+* MLP field at 256^3, bf16-guarded, default context (the configuration the
+  benchmark times): the oracle evaluates the network in binary64, which is
+  too slow for the whole grid, so seeded samples of corners, crossing edges,
+  face pairs and active cells are recomputed one by one and compared, and
+  the properties that hold at any size are checked on the whole mesh.  The
+  fp32 path on the same grid must give the same mesh bit for bit.
+"""
+import numpy as np
+import pytest
+
+import odc_inputs as I
+import meshcheck as M
+from gpu_common import compare_discrete, gpu_run, vertex_grid_coords
+
+pytestmark = pytest.mark.gpu
+
+VERT_TOL = 1e-5   # cell widths
+MLP_TIE = 1e-5    # binary64 logit band treated as a near-tie (fp32 error < 2e-6)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2409_13418_amd import odc
+    c = odc.Context(0)
+    yield c
+    c.close()
+
+
+def test_csg128_full_parity(ctx, oracle_mod):
+    f = I.csg_random_field(2)
+    g = I.unit_grid(128, 15)
+    r, _ = gpu_run(f, g, ctx=ctx)
+    m = oracle_mod.Oracle(f, g).mesh()
+    assert compare_discrete(r, m) == []
+    assert np.array_equal(r["edge_t"].astype(np.float64), m["edge_t"])
+    pf = r["pair_pf"].astype(np.float64)
+    d = np.linalg.norm(pf - m["pair_pf"], axis=1)
+    tol = 1e-5 * (1 + np.linalg.norm(m["pair_pf"], axis=1)) / np.maximum(m["pair_sin"], 1e-3)
+    assert np.all(d <= tol), float(d.max())
+    nvp = int(m["cell_npart"].sum())
+    dv = np.max(np.abs(vertex_grid_coords(r, 128)[:nvp] - m["vert"][:nvp]), axis=1)
+    assert np.all((dv <= VERT_TOL) | (m["vert_tie"][:nvp] != 0)), float(dv.max())
+    tie = m["edge_case_tie"] != 0
+    assert np.all((r["edge_case"] == m["edge_case"]) | tie)
+    if np.all(r["edge_case"] == m["edge_case"]):
+        assert np.array_equal(r["triangles"], m["tris"])
+    ok, why = M.is_closed_oriented_manifold(r["triangles"], r["n_vertices"])
+    assert ok, why
+    print(f"csg128: {len(m['cell_id'])} cells, {len(m['tris'])} triangles, "
+          f"max vertex error {dv.max():.2e} cells")
+
+
+@pytest.fixture(scope="module")
+def mlp256(ctx):
+    f = I.mlp_field(3)
+    g = I.unit_grid(256, 15)
+    r, _ = gpu_run(f, g, precision=1, ctx=ctx)
+    return f, g, r
+
+
+def _corner_ijk(c, n1):
+    return c % n1, (c // n1) % n1, c // (n1 * n1)
+
+
+def test_mlp256_sampled_labels(mlp256, oracle_mod):
+    f, g, r = mlp256
+    o = oracle_mod.Oracle(f, g, mlp_tie_eps=MLP_TIE)
+    n1 = g.res + 1
+    rng = np.random.default_rng(11)
+    # uniform corners, and corners at the ends of crossing edges (next to the surface)
+    cs = list(rng.integers(0, n1 ** 3, 1500))
+    eids = r["edge_ids"][rng.integers(0, len(r["edge_ids"]), 1500)]
+    ea = g.res * n1 * n1
+    for e in eids:
+        a, loc = int(e) // ea, int(e) % ea
+        dims = [n1, n1, n1]
+        dims[a] = g.res
+        i = loc % dims[0]
+        j = (loc // dims[0]) % dims[1]
+        k = loc // (dims[0] * dims[1])
+        p = [i, j, k]
+        cs.append(p[0] + n1 * (p[1] + n1 * p[2]))
+        p[a] += 1
+        cs.append(p[0] + n1 * (p[1] + n1 * p[2]))
+    ties = 0
+    for c in cs:
+        lab, tie = o.corner_label(*_corner_ijk(int(c), n1))
+        if tie:
+            ties += 1
+            continue
+        assert r["corner_label"][c] == lab, int(c)
+    print(f"mlp256 labels: {len(cs)} sampled corners, {ties} near-ties")
+
+
+def test_mlp256_sampled_edges_pairs_cells(mlp256, oracle_mod):
+    f, g, r = mlp256
+    o = oracle_mod.Oracle(f, g, mlp_tie_eps=MLP_TIE)
+    rng = np.random.default_rng(12)
+    # 1D points: equal when the oracle's bisection met no near-tie, otherwise
+    # inside the bracket reached before the first near-tie step
+    ne = len(r["edge_ids"])
+    for x in rng.integers(0, ne, 150):
+        t, ts = o.edge_point(int(r["edge_ids"][x]))
+        d = abs(float(r["edge_t"][x]) - t)
+        assert d <= (0.0 if ts == 0 else 2.0 ** -(ts - 1)), (int(x), t, ts)
+    # 2D points: within the stated tolerance without a near-tie in the cone,
+    # within a quarter cell otherwise
+    npairs = len(r["pairs"])
+    clean = 0
+    for x in rng.integers(0, npairs, 60):
+        rec = int(r["pairs"][x])
+        n, pf, info, tie = o.pair_point(rec >> 1, rec & 1)
+        assert n >= 1
+        d = float(np.linalg.norm(r["pair_pf"][x] - pf))
+        if tie == 0:
+            clean += 1
+            # the binary32 bound of the small parity tests at the smallest
+            # admitted line angle (sin 1e-3)
+            assert d <= 1e-5 * (1 + np.linalg.norm(pf)) / 1e-3, (int(x), d)
+        assert d <= 0.25, (int(x), d)
+    # cells: partition structure exact; vertices within tolerance
+    nc = len(r["cell_ids"])
+    vg = vertex_grid_coords(r, g.res)
+    for x in rng.integers(0, nc, 40):
+        cid = int(r["cell_ids"][x])
+        n, verts, pm, tie = o.cell_vertices(cid)
+        assert n == int(r["cell_nf"][x] & 15), cid
+        assert pm == int(r["cell_partmap"][x]), cid
+        base = int(r["vertex_base"][x])
+        dv = np.max(np.abs(vg[base:base + n] - verts))
+        assert dv <= (VERT_TOL if tie == 0 else 0.25), (cid, dv, tie)
+    print(f"mlp256: 150 edges, 60 pairs ({clean} without near-tie), 40 cells checked")
+
+
+def test_mlp256_mesh_properties(mlp256):
+    f, g, r = mlp256
+    tris = r["triangles"]
+    ok, why = M.is_closed_oriented_manifold(tris, r["n_vertices"])
+    assert ok, why
+    npart = int(np.sum(r["cell_nf"] & 15))
+    assert r["n_vertices"] == npart + r["n_case3"]
+    # one quad per crossing edge with four in-grid cells, split into two
+    # triangles, or four around the edge's 1D point (case 3)
+    N, n1 = g.res, g.res + 1
+    e = r["edge_ids"].astype(np.int64)
+    ea = N * n1 * n1
+    a, loc = e // ea, e % ea
+    interior = np.ones(len(e), bool)
+    for ax in range(3):
+        sel = a == ax
+        dims = [n1, n1, n1]
+        dims[ax] = N
+        ijk = [loc[sel] % dims[0], (loc[sel] // dims[0]) % dims[1], loc[sel] // (dims[0] * dims[1])]
+        inner = np.ones(int(sel.sum()), bool)
+        for o in range(3):
+            if o != ax:
+                inner &= (ijk[o] > 0) & (ijk[o] < N)
+        interior[sel] = inner
+    assert len(tris) == 2 * int(interior.sum()) + 2 * r["n_case3"]
+    # no clamp to the cell (unclamped QEF points); report how many leave it
+    vl = r["vertices_local"][:npart]
+    assert np.all(np.isfinite(vl))
+    outside = int(np.sum(np.any((vl < 0) | (vl > 1), axis=1)))
+    print(f"mlp256: {npart} partition vertices, {outside} outside their cell")
+
+
+def test_mlp256_bf16_equals_fp32(ctx, mlp256):
+    f, g, rb = mlp256
+    ra, _ = gpu_run(f, g, precision=0, ctx=ctx, want_local=False)
+    assert np.array_equal(ra["corner_label"], rb["corner_label"])
+    assert np.array_equal(ra["triangles"], rb["triangles"])
+    assert np.array_equal(ra["vertices"], rb["vertices"])
+    assert rb["n_guard_corners"] > 0

@@ -1,0 +1,142 @@
+"""Serving loop (odc_server_*): continuous batching with admission by device
+scratch footprint.  Every job must give the mesh it gives when extracted
+alone, bit for bit, whatever it was batched with, and jobs that arrive while
+others run must be admitted while those are still on the device."""
+import time
+
+import numpy as np
+import pytest
+
+import odc_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def odc():
+    from paper_2409_13418_amd import odc as m
+    return m
+
+
+def _jobs():
+    out = []
+    for k, res in enumerate((24, 40, 32, 48)):
+        out.append((I.csg_random_field(5000 + k), I.unit_grid(res, 15), 0))
+    for k, (res, prec) in enumerate(((16, 0), (24, 1), (32, 1), (20, 0))):
+        out.append((I.mlp_field(5100 + k), I.unit_grid(res, 15), prec))
+    f, g = I.sphere_case(32, 10)
+    out.append((f, g, 0))
+    return out
+
+
+def _alone(odc, jobs):
+    ctx = odc.Context(0)
+    ref = []
+    for f, g, prec in jobs:
+        r = ctx.extract(odc.DeviceField(f), odc.default_params(g, prec))
+        ref.append((r["vertices"].cpu().numpy().copy(), r["triangles"].cpu().numpy().copy(),
+                    r["n_active_cells"]))
+    ctx.close()
+    return ref
+
+
+def _lattice_field():
+    recs = []
+    for i in range(8):
+        for j in range(8):
+            for k in range(8):
+                c = (-0.4375 + 0.125 * i, -0.4375 + 0.125 * j, -0.4375 + 0.125 * k)
+                recs.append(I.sphere_record(c, 0.047))
+    return I.csg_field(recs)
+
+
+def test_mix_equals_alone(odc):
+    jobs = _jobs()
+    ref = _alone(odc, jobs)
+    ctx = odc.Context(0)
+    dfs = [odc.DeviceField(f) for f, _, _ in jobs]
+    ps = [odc.default_params(g, prec) for _, g, prec in jobs]
+    outs = [odc.OutputBuffers(len(v) + 16, len(t) + 16) for v, t, _ in ref]
+    tmp = odc.Server(ctx, 1 << 30)
+    fp = [tmp.footprint(d, p) for d, p in zip(dfs, ps)]
+    tmp.close()
+    # room for about three jobs at a time: later jobs wait for memory
+    budget = 3 * max(fp)
+    srv = odc.Server(ctx, budget, lanes=2, max_batch=2)
+    tickets = [srv.submit(dfs[k], ps[k], outs[k]) for k in range(4)]
+    time.sleep(0.002)
+    tickets += [srv.submit(dfs[k], ps[k], outs[k]) for k in range(4, len(jobs))]
+    res = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    for k, r in enumerate(res):
+        assert r["status"] == odc.OK, (k, r)
+        v, t, nc = ref[k]
+        assert r["n_active_cells"] == nc, k
+        got = outs[k].views(r)
+        assert np.array_equal(got["vertices"].cpu().numpy(), v), k
+        assert np.array_equal(got["triangles"].cpu().numpy(), t), k
+        assert r["submit_ms"] <= r["admit_ms"] <= r["done_ms"]
+    assert st["completed"] == len(jobs) and st["failed"] == 0
+    assert st["batches"] >= len(jobs) // 2
+    assert st["arena_peak_bytes"] <= budget
+    assert st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+    # continuous batching: some job was admitted while another batch was
+    # still on the device
+    spans = sorted((r["admit_ms"], r["done_ms"]) for r in res)
+    overlap = any(spans[i + 1][0] < spans[i][1] and spans[i + 1][0] != spans[i][0]
+                  for i in range(len(spans) - 1))
+    print(f"serve mix: {st['batches']} batches, p50 {st['p50_ms']:.2f} ms, "
+          f"p99 {st['p99_ms']:.2f} ms, peak arena {st['arena_peak_bytes']} of {budget}")
+    assert overlap
+    ctx.close()
+
+
+def test_overflow_is_requeued(odc):
+    """A job whose active sets outgrow their planned capacity goes back to
+    the queue with the capacity it needed and completes on the next try."""
+    f = _lattice_field()
+    g = I.unit_grid(64, 12)
+    ctx = odc.Context(0)
+    df = odc.DeviceField(f)
+    p = odc.default_params(g)
+    alone = ctx.extract(df, p)
+    v0 = alone["vertices"].cpu().numpy().copy()
+    t0 = alone["triangles"].cpu().numpy().copy()
+    srv = odc.Server(ctx, 1 << 30, lanes=1)
+    out = odc.OutputBuffers(len(v0) + 16, len(t0) + 16)
+    r = srv.wait(srv.submit(df, p, out))
+    srv.close()
+    assert r["status"] == odc.OK and r["attempts"] == 2
+    got = out.views(r)
+    assert np.array_equal(got["vertices"].cpu().numpy(), v0)
+    assert np.array_equal(got["triangles"].cpu().numpy(), t0)
+    ctx.close()
+
+
+def test_admission_limits_and_errors(odc):
+    ctx = odc.Context(0)
+    f, g = I.sphere_case(32, 10)
+    df = odc.DeviceField(f)
+    p = odc.default_params(g)
+    srv = odc.Server(ctx, 1 << 20)
+    assert srv.footprint(df, p) > (1 << 20)
+    with pytest.raises(odc.OdcError) as e:
+        srv.submit(df, p, odc.OutputBuffers(4096, 8192))
+    assert e.value.status == odc.ERR_OUT_OF_MEMORY
+    srv.close()
+    srv = odc.Server(ctx, 1 << 28)
+    bad = odc.default_params(g)
+    bad.res = 0
+    with pytest.raises(odc.OdcError) as e:
+        srv.submit(df, bad, odc.OutputBuffers(16, 16))
+    assert e.value.status == odc.ERR_INVALID_ARG
+    # too little output room: the job reports CAPACITY with the sizes needed
+    small = odc.OutputBuffers(16, 16)
+    r = srv.wait(srv.submit(df, p, small))
+    assert r["status"] == odc.ERR_CAPACITY
+    assert r["n_vertices"] > 16 and r["n_triangles"] > 16
+    with pytest.raises(odc.OdcError):
+        srv.poll(123456789)
+    srv.close()
+    ctx.close()
