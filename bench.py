@@ -43,10 +43,40 @@ PEAK_FP32_MFMA = 157.3e12
 PEAK_BF16_MFMA = 2.5e15
 
 
-def cpu_baseline(field, grid, seconds: float, sub: int = 16, seed: int = 0) -> dict:
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_2409_13418_amd", "csrc")
+    for fn in ("odc_kernels.hip", "odc_mlp.h", "odc_job.h", "odc_device.h", "odc_internal.h"):
+        with open(os.path.join(src, fn), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE runs scaled by a plain copy), or None when
+    the kernel sources changed after the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "search2d_mlp256_bf16.md")
+    if not os.path.exists(path):
+        return None
+    value, sha = None, None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith(f"traffic_bytes_per_launch k_{kernel}_mlp:"):
+                value = float(line.split(":")[1])
+            if line.startswith("kernel_sources_sha256:"):
+                sha = line.split(":", 1)[1].strip()
+    return value if sha == kernel_sources_sha256() else None
+
+
+def cpu_baseline(field, grid, seconds: float, sub: int = 16, seed: int = 0, chamfer=None) -> dict:
     """The oracle, untuned, on sub-boxes of the same grid (same h, same field)
     centred on seeded points of the sdf spheres' surfaces, until `seconds` of
-    CPU time have been spent.  Returns active cells per second."""
+    CPU time have been spent.  Returns active cells per second.  With
+    `chamfer` = (context, device field, precision), the first sub-boxes are
+    also meshed on the GPU and the Chamfer distance to the oracle's mesh is
+    reported (outside the timed part)."""
     from oracle import oracle as O
     O.build()
     rng = np.random.default_rng(seed)
@@ -54,6 +84,7 @@ def cpu_baseline(field, grid, seconds: float, sub: int = 16, seed: int = 0) -> d
     cells = 0
     spent = 0.0
     boxes = 0
+    cham = []
     while spent < seconds:
         s = field.spheres[rng.integers(len(field.spheres))].astype(np.float64)
         d = rng.standard_normal(3)
@@ -68,10 +99,25 @@ def cpu_baseline(field, grid, seconds: float, sub: int = 16, seed: int = 0) -> d
         spent += time.perf_counter() - t0
         cells += len(m["cell_id"])
         boxes += 1
+        if chamfer is not None and len(cham) < 4 and len(m["tris"]):
+            from paper_2409_13418_amd import odc
+            sys.path.insert(0, os.path.join(ROOT, "tests"))
+            from meshcheck import chamfer_h2
+            ctx, df, prec = chamfer
+            r = ctx.extract(df, odc.default_params(g2, prec))
+            vo = np.asarray(g2.lo) + m["vert"] * h
+            cham.append(chamfer_h2(r["vertices"].cpu().numpy(), r["triangles"].cpu().numpy(),
+                                   vo, m["tris"], h, n=20000, seed=boxes))
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    return {"value": cells / spent, "unit": "cells/s", "cores": threads, "kind": "oracle",
-            "sample": f"{boxes} sub-boxes of {sub}^3 cells at the benchmark's h around seeded "
-                      f"sphere-surface points, {cells} active cells in {spent:.1f} s"}
+    out = {"value": cells / spent, "unit": "cells/s", "cores": threads, "kind": "oracle",
+           "sample": f"{boxes} sub-boxes of {sub}^3 cells at the benchmark's h around seeded "
+                     f"sphere-surface points, {cells} active cells in {spent:.1f} s"}
+    if cham:
+        out["chamfer_vs_oracle"] = {
+            "value": max(cham), "unit": "h^2", "boxes": len(cham),
+            "method": "symmetric mean squared point-to-surface distance, 20k area samples per "
+                      "mesh, GPU mesh of the same sub-box at the benchmark's precision; max over boxes"}
+    return out
 
 
 def _batch_mode(args):
@@ -326,7 +372,8 @@ def main():
         peak = PEAK_BF16_MFMA if prec == odc.PREC_BF16_GUARDED else PEAK_FP32_MFMA
     achieved = flop / (stages[dom] / 1e3) / 1e12
     roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak / 1e12,
-                "unit": "TFLOP/s", "frac": achieved * 1e12 / peak, "traffic": None}
+                "unit": "TFLOP/s", "frac": achieved * 1e12 / peak,
+                "traffic": measured_traffic(dom) if prec == odc.PREC_BF16_GUARDED else None}
     out = {
         "metric": "active cells meshed/sec at 256^3 MLP occupancy",
         "value": value, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
@@ -346,7 +393,11 @@ def main():
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(field, grid, args.cpu_seconds)
+        cb = cpu_baseline(field, grid, args.cpu_seconds, chamfer=(ctx, df, prec))
+        cham = cb.pop("chamfer_vs_oracle", None)
+        out["cpu_baseline"] = cb
+        if cham is not None:
+            out["chamfer_vs_oracle"] = cham
     print(json.dumps(out), flush=True)
 
 

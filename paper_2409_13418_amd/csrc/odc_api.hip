@@ -315,7 +315,7 @@ Layout job_layout(const Job& J, const odc_field* f, bool guard_full) {
   }
   L.status = align_up(4 * sizeof(unsigned long long));
   if (f->kind == ODC_FIELD_MLP) {
-    const int kb1f = (f->in_dim + 1) / 2, kb1b = (f->in_dim + 15) / 16, d = f->depth;
+    const int kb1f = kb1_fp32(f->in_dim), kb1b = kb1_bf16(f->in_dim), d = f->depth;
     L.n_w1f = (size_t)kb1f * 512;
     L.n_whf = ((size_t)(d - 1) * kHiddenBlocksF32 + kPrefetchF32) * 512;  // + ring overrun
     L.n_w1b = (size_t)kb1b * 512;
@@ -376,8 +376,8 @@ void job_bind(Job& J, const Layout& L, const odc_field* f, char* grid, char* act
     m.n_spheres = f->n_spheres;
     m.depth = d;
     m.in_dim = f->in_dim;
-    m.kb1f = (f->in_dim + 1) / 2;
-    m.kb1b = (f->in_dim + 15) / 16;
+    m.kb1f = kb1_fp32(f->in_dim);
+    m.kb1b = kb1_bf16(f->in_dim);
     if (J.precision == ODC_PREC_BF16_GUARDED) {
       J.guard_list = (uint32_t*)guard;
       J.guard_cap = L.guard_cap;

@@ -168,7 +168,7 @@ __device__ void pack_mlp(const float* __restrict__ w, int in_dim, int depth, lon
                          float* __restrict__ w1f, float* __restrict__ whf,
                          v8bf* __restrict__ w1b, v8bf* __restrict__ whb,
                          float* __restrict__ bias, float* __restrict__ wout) {
-  const int kb1f = (in_dim + 1) / 2, kb1b = (in_dim + 15) / 16;
+  const int kb1f = kb1_fp32(in_dim), kb1b = kb1_bf16(in_dim);
   const size_t l1 = (size_t)kWidth * in_dim;
   const size_t hid = (size_t)kWidth * kWidth;
   const long long n_w1f = (long long)kb1f * 8 * 64;

@@ -37,6 +37,13 @@ constexpr int kMaxDepth = 8;
 constexpr int kMaxInDim = 45;
 constexpr int kHiddenBlocksF32 = kWidth / 2;    // 128 K blocks of 2
 constexpr int kHiddenBlocksBF16 = kWidth / 16;  // 16 K blocks of 16
+// Layer-1 K blocks, padded with zero weights to whole groups of 4 so that one
+// register ring streams layer 1 and the hidden layers alike (they are
+// contiguous in memory); at most 6 (fp32) and 1 (bf16) groups.
+__host__ __device__ constexpr int kb1_fp32(int in_dim) { return ((in_dim + 1) / 2 + 3) / 4 * 4; }
+__host__ __device__ constexpr int kb1_bf16(int in_dim) { return ((in_dim + 15) / 16 + 3) / 4 * 4; }
+constexpr int kMaxGroups1F32 = kb1_fp32(45) / 4;
+constexpr int kMaxGroups1BF16 = kb1_bf16(45) / 4;
 
 // Pointers that are known to address device global memory.  The kernels
 // read the job records from memory, so the pointers inside are generic; a
@@ -121,44 +128,52 @@ __device__ __forceinline__ float mlp_finish(const Mlp& M, float part, const floa
 // is to free 128 registers per lane for the weight-fragment prefetch.
 constexpr int kActWords = kHiddenBlocksF32 * 64;
 
-// Weight fragments of the hidden layers are streamed through a ring of
-// kPrefetchF32 K blocks held in registers: the load of block b + kPrefetchF32
-// is issued as block b is consumed, so each load has about kPrefetchF32 x 8
-// matrix-core instructions (~2000 cycles) to arrive.  The hidden layers are
-// contiguous in memory and the ring runs across layer boundaries; the packed
-// buffer carries kPrefetchF32 K blocks of padding after the last layer.
+// Weight fragments stream through a ring of kPrefetchF32 K blocks held in
+// registers: the load of block b + kPrefetchF32 is issued as block b is
+// consumed, so each load has about kPrefetchF32 x 8 matrix-core
+// instructions (~2000 cycles) to arrive.  Layer 1 (padded to whole groups
+// of kPrefetchF32 blocks) and the hidden layers are contiguous in memory and
+// the ring runs straight through them; the packed buffer carries
+// kPrefetchF32 blocks of padding after the last layer for the overrun.
 constexpr int kPrefetchF32 = 4;
 
 __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
                                                 float* __restrict__ act) {
   const int lane = lane_id();
   const int h = lane >> 5;
-  v16f acc[8];
-#pragma unroll
-  for (int R = 0; R < 8; ++R) acc[R] = (v16f){};
-  for (int b = 0; b < M.kb1f; ++b) {
-    const ODC_GLOBAL float* wp = gmem(M.w1f) + (size_t)b * 8 * 64 + lane;
-    float w[8];
-#pragma unroll
-    for (int R = 0; R < 8; ++R) w[R] = wp[R * 64];
-    const float bv = mlp_feature(2 * b + h, x, M.in_dim);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int R = 0; R < 8; ++R)
-      acc[R] = __builtin_amdgcn_mfma_f32_32x32x2f32(w[R], bv, acc[R], 0, 0, 0);
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  // the ring's first blocks load while the first transition runs.  The
-  // offset is an opaque zero so that these loads stay here: hoisted out of a
-  // caller's query loop they would pin 32 registers for its whole length.
+  // The offset is an opaque zero so that the ring's first loads stay here:
+  // hoisted out of a caller's query loop they would pin 32 registers for its
+  // whole length.
   int zero = 0;
   asm volatile("" : "+v"(zero));
-  const ODC_GLOBAL float* Wh = gmem(M.whf) + lane + zero;
+  const ODC_GLOBAL float* S = gmem(M.w1f) + lane + zero;  // layer 1, then the hidden layers
   float wr[kPrefetchF32][8];
 #pragma unroll
   for (int d = 0; d < kPrefetchF32; ++d)
 #pragma unroll
-    for (int R = 0; R < 8; ++R) wr[d][R] = Wh[(d * 8 + R) * 64];
+    for (int R = 0; R < 8; ++R) wr[d][R] = S[(d * 8 + R) * 64];
+  v16f acc[8];
+#pragma unroll
+  for (int R = 0; R < 8; ++R) acc[R] = (v16f){};
+  // layer 1: B operand = Fourier features computed in registers
+  const int ng = M.kb1f / kPrefetchF32;
+#pragma unroll
+  for (int gi = 0; gi < kMaxGroups1F32; ++gi) {
+    if (gi < ng) {
+#pragma unroll
+      for (int d = 0; d < kPrefetchF32; ++d) {
+        const int b = gi * kPrefetchF32 + d;
+        const float bv = mlp_feature(2 * b + h, x, M.in_dim);
+#pragma unroll
+        for (int R = 0; R < 8; ++R)
+          acc[R] = __builtin_amdgcn_mfma_f32_32x32x2f32(wr[d][R], bv, acc[R], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int R = 0; R < 8; ++R) wr[d][R] = S[((size_t)(b + kPrefetchF32) * 8 + R) * 64];
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
   for (int l = 1; l < M.depth; ++l) {
     const ODC_CONST float* bl = cmem(M.bias) + (l - 1) * kWidth;
     // bias, ReLU and park, one 32-row tile at a time (bounds the live range)
@@ -170,9 +185,9 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
       acc[T] = (v16f){};
       __builtin_amdgcn_sched_barrier(0);
     }
-    // block b of this layer is block (l-1)*128 + b of the stream
+    // block b of this layer is block kb1f + (l-1)*128 + b of the stream
     const ODC_GLOBAL float* Wn =
-        Wh + ((size_t)(l - 1) * kHiddenBlocksF32 + kPrefetchF32) * 8 * 64;
+        S + ((size_t)M.kb1f + (size_t)(l - 1) * kHiddenBlocksF32 + kPrefetchF32) * 8 * 64;
     float bvn = act[lane];
     // fully unrolled: a loop back-edge here makes the wait-count insertion
     // drain every load in flight at the top of each trip
@@ -222,31 +237,38 @@ __device__ __forceinline__ float mlp_logit_bf16(const Mlp& M, const float x[3],
                                                 v8bf* __restrict__ act) {
   const int lane = lane_id();
   const int h = lane >> 5;
-  v16f acc[8];
-#pragma unroll
-  for (int R = 0; R < 8; ++R) acc[R] = (v16f){};
-  for (int b = 0; b < M.kb1b; ++b) {
-    const ODC_GLOBAL v8bf* wp = gmem(M.w1b) + (size_t)b * 8 * 64 + lane;
-    v8bf w[8];
-#pragma unroll
-    for (int R = 0; R < 8; ++R) w[R] = wp[R * 64];
-    v8bf bv;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) bv[j] = (__bf16)mlp_feature(16 * b + 8 * h + j, x, M.in_dim);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int R = 0; R < 8; ++R)
-      acc[R] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[R], bv, acc[R], 0, 0, 0);
-    __builtin_amdgcn_sched_barrier(0);
-  }
   int zero = 0;  // keeps the ring prologue here (see mlp_logit_fp32)
   asm volatile("" : "+v"(zero));
-  const ODC_GLOBAL v8bf* Wh = gmem(M.whb) + lane + zero;
+  const ODC_GLOBAL v8bf* S = gmem(M.w1b) + lane + zero;  // layer 1, then the hidden layers
   v8bf wr[kPrefetchBF16][8];
 #pragma unroll
   for (int d = 0; d < kPrefetchBF16; ++d)
 #pragma unroll
-    for (int R = 0; R < 8; ++R) wr[d][R] = Wh[(d * 8 + R) * 64];
+    for (int R = 0; R < 8; ++R) wr[d][R] = S[(d * 8 + R) * 64];
+  v16f acc[8];
+#pragma unroll
+  for (int R = 0; R < 8; ++R) acc[R] = (v16f){};
+  const int ng = M.kb1b / kPrefetchBF16;
+#pragma unroll
+  for (int gi = 0; gi < kMaxGroups1BF16; ++gi) {
+    if (gi < ng) {
+#pragma unroll
+      for (int d = 0; d < kPrefetchBF16; ++d) {
+        const int b = gi * kPrefetchBF16 + d;
+        v8bf bv;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          bv[j] = (__bf16)mlp_feature(16 * b + 8 * h + j, x, M.in_dim);
+#pragma unroll
+        for (int R = 0; R < 8; ++R)
+          acc[R] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[d][R], bv, acc[R], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int R = 0; R < 8; ++R) wr[d][R] = S[((size_t)(b + kPrefetchBF16) * 8 + R) * 64];
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
   for (int l = 1; l < M.depth; ++l) {
     // scalar bias reads: vector loads here would queue behind the ring's
     // refills and wait for all of them
@@ -266,7 +288,7 @@ __device__ __forceinline__ float mlp_logit_bf16(const Mlp& M, const float x[3],
       acc[T] = (v16f){};
     }
     const ODC_GLOBAL v8bf* Wn =
-        Wh + ((size_t)(l - 1) * kHiddenBlocksBF16 + kPrefetchBF16) * 8 * 64;
+        S + ((size_t)M.kb1b + (size_t)(l - 1) * kHiddenBlocksBF16 + kPrefetchBF16) * 8 * 64;
     v8bf bvn = act[lane];
 #pragma unroll
     for (int b0 = 0; b0 < kHiddenBlocksBF16; b0 += kPrefetchBF16) {
@@ -285,17 +307,18 @@ __device__ __forceinline__ float mlp_logit_bf16(const Mlp& M, const float x[3],
       }
     }
   }
-  const ODC_GLOBAL float* bl = gmem(M.bias) + (M.depth - 1) * kWidth;
+  const ODC_CONST float* bl = cmem(M.bias) + (M.depth - 1) * kWidth;
+  const ODC_CONST float* wo = cmem(M.wout);
   float part = 0.0f;
 #pragma unroll
   for (int T = 0; T < 8; ++T) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      const int n = 32 * T + 8 * (i >> 2) + 4 * h + (i & 3);
-      const float a = fmaxf(acc[T][i] + bl[n], 0.0f);
-      const float p = gmem(M.wout)[n] * a;
+      const float a = fmaxf(acc[T][i] + bias_of(bl, T, i, h), 0.0f);
+      const float p = bias_of(wo, T, i, h) * a;
       part = part + p;
     }
+    __builtin_amdgcn_sched_barrier(0);
   }
   return mlp_finish(M, part, x);
 }

@@ -51,8 +51,12 @@ def test_csg128_full_parity(ctx, oracle_mod):
         assert np.array_equal(r["triangles"], m["tris"])
     ok, why = M.is_closed_oriented_manifold(r["triangles"], r["n_vertices"])
     assert ok, why
+    # Chamfer distance to the oracle's mesh: vertices within 1e-5 h bound it by 1e-10 h^2
+    vo = np.asarray(g.lo) + m["vert"] * g.h
+    ch = M.chamfer_h2(r["vertices"], r["triangles"], vo, m["tris"], g.h, n=20000)
+    assert ch <= 1e-10, ch
     print(f"csg128: {len(m['cell_id'])} cells, {len(m['tris'])} triangles, "
-          f"max vertex error {dv.max():.2e} cells")
+          f"max vertex error {dv.max():.2e} cells, Chamfer vs oracle {ch:.2e} h^2")
 
 
 @pytest.fixture(scope="module")
