@@ -25,6 +25,25 @@ struct Grid {
 };
 
 // ---------------------------------------------------------------- indexing
+// Element i of a 3-vector, and updates of it, written as selects: a small
+// array indexed at run time would otherwise be placed in scratch or LDS.
+template <class T>
+__device__ __forceinline__ T at3(const T v[3], int i) {
+  return i == 0 ? v[0] : (i == 1 ? v[1] : v[2]);
+}
+template <class T>
+__device__ __forceinline__ void add_at3(T v[3], int i, T x) {
+  v[0] = i == 0 ? v[0] + x : v[0];
+  v[1] = i == 1 ? v[1] + x : v[1];
+  v[2] = i == 2 ? v[2] + x : v[2];
+}
+template <class T>
+__device__ __forceinline__ void set_at3(T v[3], int i, T x) {
+  v[0] = i == 0 ? x : v[0];
+  v[1] = i == 1 ? x : v[1];
+  v[2] = i == 2 ? x : v[2];
+}
+
 __device__ __forceinline__ void other_axes(int a, int& b1, int& b2) {
   b1 = (a == 0) ? 1 : 0;
   b2 = (a == 2) ? 1 : 2;

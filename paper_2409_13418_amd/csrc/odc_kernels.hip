@@ -177,15 +177,20 @@ __device__ void pack_mlp(const float* __restrict__ w, int in_dim, int depth, lon
   const long long n_whb = (long long)(depth - 1) * kHiddenBlocksBF16 * 8 * 64;
   {
     long long r = id;
+    // fp32 fragments: for K block b, lane l holds the values of tiles
+    // R = 4q + c (c < 4) as one 16-byte vector at float offset
+    // ((2b + q) * 64 + l) * 4 + c, so a lane loads its 8 tiles with 2 loads
     if (r < n_w1f) {
-      const int lane = r % 64, R = (r / 64) % 8, b = (int)(r / 512);
+      const int c = r % 4, lane = (r / 4) % 64, q = (r / 256) % 2, b = (int)(r / 512);
+      const int R = 4 * q + c;
       const int row = 32 * R + (lane & 31), k = 2 * b + (lane >> 5);
       w1f[r] = k < in_dim ? w[(size_t)row * in_dim + k] : 0.0f;
       return;
     }
     r -= n_w1f;
     if (r < n_whf) {
-      const int lane = r % 64, R = (r / 64) % 8, b = (int)((r / 512) % kHiddenBlocksF32);
+      const int c = r % 4, lane = (r / 4) % 64, q = (r / 256) % 2;
+      const int R = 4 * q + c, b = (int)((r / 512) % kHiddenBlocksF32);
       const int l = (int)(r / (512LL * kHiddenBlocksF32));
       const int row = 32 * R + (lane & 31), h = lane >> 5;
       const int T = b >> 4, i = b & 15;
@@ -416,8 +421,8 @@ __device__ __forceinline__ void face_labels(const Grid& g, const uint32_t* __res
 #pragma unroll
   for (int lc = 0; lc < 4; ++lc) {
     int q[3] = {p[0], p[1], p[2]};
-    q[u] += lc & 1;
-    q[v] += lc >> 1;
+    add_at3(q, u, lc & 1);
+    add_at3(q, v, lc >> 1);
     out[lc] = bit_of(L, corner_index(g, q[0], q[1], q[2]));
   }
 }
@@ -631,10 +636,10 @@ __device__ __forceinline__ int face_edge_global(const Grid& g, const FaceFrame& 
   int axis;
   if (fe < 2) {
     axis = fr.u;
-    q[fr.v] += fe;
+    add_at3(q, fr.v, fe);
   } else {
     axis = fr.v;
-    q[fr.u] += fe - 2;
+    add_at3(q, fr.u, fe - 2);
   }
   return edge_index(g, axis, q[0], q[1], q[2]);
 }
@@ -698,7 +703,7 @@ __device__ double2 search_pair(const Job& j, const Lab& lab, int face, int slot)
   int L[4], pa[2], pb[2];
   face_labels(g, j.labels, fr.a, fr.p, L);
   face_pairs(L, bit_of(j.fflip, face), pa, pb);
-  const int fa = pa[slot], fb = pb[slot];
+  const int fa = slot ? pa[1] : pa[0], fb = slot ? pb[1] : pb[0];
   const float t1 = j.et[edge_slot(j, face_edge_global(g, fr, fa))];
   const float t2 = j.et[edge_slot(j, face_edge_global(g, fr, fb))];
   float P1[2], P2[2];
@@ -725,10 +730,9 @@ __device__ double2 search_pair(const Job& j, const Lab& lab, int face, int slot)
       s = lb.param(k);
       lb.point(s, P);
     }
-    float gp[3];
-    gp[fr.a] = (float)fr.p[fr.a];
-    gp[fr.u] = (float)fr.p[fr.u] + P[0];
-    gp[fr.v] = (float)fr.p[fr.v] + P[1];
+    float gp[3] = {(float)fr.p[0], (float)fr.p[1], (float)fr.p[2]};
+    add_at3(gp, fr.u, P[0]);
+    add_at3(gp, fr.v, P[1]);
     const int l = lab(gp);
     if (step == 0) {
       // step 1: the ray from m orthogonal to l, towards a corner whose label

@@ -30,6 +30,7 @@
 namespace odc {
 
 typedef float v16f __attribute__((ext_vector_type(16)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 constexpr int kWidth = 256;
@@ -131,7 +132,10 @@ constexpr int kActWords = kHiddenBlocksF32 * 64;
 // Weight fragments stream through a ring of kPrefetchF32 K blocks held in
 // registers: the load of block b + kPrefetchF32 is issued as block b is
 // consumed, so each load has about kPrefetchF32 x 8 matrix-core
-// instructions (~2000 cycles) to arrive.  Layer 1 (padded to whole groups
+// instructions (~2000 cycles) to arrive.  A lane's eight fp32 fragments of a
+// K block are packed as two 16-byte vectors: two load instructions per
+// block instead of eight (fewer issue slots between the matrix-core
+// instructions, which the fp32 matrix instructions share with the VALU).  Layer 1 (padded to whole groups
 // of kPrefetchF32 blocks) and the hidden layers are contiguous in memory and
 // the ring runs straight through them; the packed buffer carries
 // kPrefetchF32 blocks of padding after the last layer for the overrun.
@@ -146,12 +150,14 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
   // whole length.
   int zero = 0;
   asm volatile("" : "+v"(zero));
-  const ODC_GLOBAL float* S = gmem(M.w1f) + lane + zero;  // layer 1, then the hidden layers
-  float wr[kPrefetchF32][8];
+  // layer 1, then the hidden layers: lane l's fragments of K block b are two
+  // 16-byte vectors (tiles 0-3 and 4-7) at vector index (2b + q) * 64 + l
+  const ODC_GLOBAL v4f* S = (const ODC_GLOBAL v4f*)gmem(M.w1f) + lane + zero;
+  v4f wr[kPrefetchF32][2];
 #pragma unroll
   for (int d = 0; d < kPrefetchF32; ++d)
 #pragma unroll
-    for (int R = 0; R < 8; ++R) wr[d][R] = S[(d * 8 + R) * 64];
+    for (int q = 0; q < 2; ++q) wr[d][q] = S[(2 * d + q) * 64];
   v16f acc[8];
 #pragma unroll
   for (int R = 0; R < 8; ++R) acc[R] = (v16f){};
@@ -166,10 +172,10 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
         const float bv = mlp_feature(2 * b + h, x, M.in_dim);
 #pragma unroll
         for (int R = 0; R < 8; ++R)
-          acc[R] = __builtin_amdgcn_mfma_f32_32x32x2f32(wr[d][R], bv, acc[R], 0, 0, 0);
+          acc[R] = __builtin_amdgcn_mfma_f32_32x32x2f32(wr[d][R >> 2][R & 3], bv, acc[R], 0, 0, 0);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int R = 0; R < 8; ++R) wr[d][R] = S[((size_t)(b + kPrefetchF32) * 8 + R) * 64];
+        for (int q = 0; q < 2; ++q) wr[d][q] = S[((size_t)(b + kPrefetchF32) * 2 + q) * 64];
         __builtin_amdgcn_sched_barrier(0);
       }
     }
@@ -186,8 +192,8 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
       __builtin_amdgcn_sched_barrier(0);
     }
     // block b of this layer is block kb1f + (l-1)*128 + b of the stream
-    const ODC_GLOBAL float* Wn =
-        S + ((size_t)M.kb1f + (size_t)(l - 1) * kHiddenBlocksF32 + kPrefetchF32) * 8 * 64;
+    const ODC_GLOBAL v4f* Wn =
+        S + ((size_t)M.kb1f + (size_t)(l - 1) * kHiddenBlocksF32 + kPrefetchF32) * 128;
     float bvn = act[lane];
     // fully unrolled: a loop back-edge here makes the wait-count insertion
     // drain every load in flight at the top of each trip
@@ -200,11 +206,11 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
         bvn = act[((b + 1) & (kHiddenBlocksF32 - 1)) * 64 + lane];
 #pragma unroll
         for (int R = 0; R < 8; ++R)
-          acc[R] = __builtin_amdgcn_mfma_f32_32x32x2f32(wr[d][R], bv, acc[R], 0, 0, 0);
+          acc[R] = __builtin_amdgcn_mfma_f32_32x32x2f32(wr[d][R >> 2][R & 3], bv, acc[R], 0, 0, 0);
         // refill the slot just consumed (same registers: no copies)
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int R = 0; R < 8; ++R) wr[d][R] = Wn[((size_t)b * 8 + R) * 64];
+        for (int q = 0; q < 2; ++q) wr[d][q] = Wn[((size_t)b * 2 + q) * 64];
         __builtin_amdgcn_sched_barrier(0);
       }
     }

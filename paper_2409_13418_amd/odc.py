@@ -101,6 +101,9 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise OdcError(-1, f"{path} is missing: build it with paper_2409_13418_amd/build.py")
+    # PyTorch ships its own HIP runtime; importing it first makes the library
+    # bind to that same runtime (one runtime per process, one device view)
+    import torch  # noqa: F401
     L = C.CDLL(path)
     L.odc_status_string.argtypes = [C.c_int32]
     L.odc_status_string.restype = C.c_char_p
