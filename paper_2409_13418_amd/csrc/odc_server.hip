@@ -91,6 +91,7 @@ class Arena {
 
 struct Request {
   uint64_t ticket = 0;
+  double cost = 0.0;  // estimated work, for the SHORTEST policy
   odc_field field;
   odc_params params;
   odc_mesh_buffers out;
@@ -206,22 +207,58 @@ static void collect(odc_server* s, Lane& L, hipError_t ev) {
   s->cv_done.notify_all();
 }
 
-// Admits jobs from the head of the queue into an idle lane (lock held).
+// Estimated work of a job in arbitrary units: grid corners plus the queries
+// of the searches on the ~6 N^2 crossing edges of a typical surface (61 per
+// edge), an MLP query costing ~100 analytic ones.
+static double job_cost(const odc_field& f, const odc_params& p) {
+  const double n = p.res, n1 = n + 1.0;
+  const double queries = n1 * n1 * n1 + 61.0 * 6.0 * n * n;
+  return f.kind == ODC_FIELD_MLP ? 100.0 * queries : queries;
+}
+
+// Admits queued jobs into an idle lane (lock held): in arrival order
+// (FIFO), or cheapest first with aged jobs ahead of all (SHORTEST).
 // Returns true when a batch was launched.
 static bool admit(odc_server* s, Lane& L) {
   std::vector<Request*> batch;
   int64_t corners = 0;
-  while (!s->queue.empty() && (int)batch.size() < s->conf.max_batch) {
-    Request* r = s->queue.front();
+  std::vector<size_t> order(s->queue.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  if (s->conf.policy == ODC_SERVE_SHORTEST) {
+    const double now = ms_since(s->t0);
+    auto aged = [&](const Request* r) { return now - r->res.submit_ms > s->conf.age_ms; };
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+      const Request* ra = s->queue[a];
+      const Request* rb = s->queue[b];
+      const bool ga = aged(ra), gb = aged(rb);
+      if (ga != gb) return ga;       // aged jobs first, in arrival order
+      if (ga) return a < b;
+      return ra->cost < rb->cost;    // then the cheapest
+    });
+  }
+  std::vector<size_t> taken;
+  for (size_t i : order) {
+    if ((int)batch.size() >= s->conf.max_batch) break;
+    Request* r = s->queue[i];
     const int64_t n1 = r->params.res + 1;
     const int64_t c = n1 * n1 * n1;
-    if (!batch.empty() && corners + c > s->conf.max_batch_corners) break;
-    if (!s->arena.alloc(r->bytes, &r->off)) break;  // in order: wait for memory
+    const bool fifo = s->conf.policy == ODC_SERVE_FIFO;
+    const bool must = fifo || ms_since(s->t0) - r->res.submit_ms > s->conf.age_ms;
+    if (!batch.empty() && corners + c > s->conf.max_batch_corners) {
+      if (must) break;
+      continue;
+    }
+    if (!s->arena.alloc(r->bytes, &r->off)) {
+      if (must) break;  // wait for memory rather than pass this job
+      continue;
+    }
     corners += c;
     batch.push_back(r);
-    s->queue.pop_front();
+    taken.push_back(i);
   }
   if (batch.empty()) return false;
+  std::sort(taken.begin(), taken.end());
+  for (auto it = taken.rbegin(); it != taken.rend(); ++it) s->queue.erase(s->queue.begin() + *it);
   const int n = (int)batch.size();
   if ((int)L.ctx->slots.size() < n) L.ctx->slots.resize(n);
   std::vector<odc_field> f(n);
@@ -324,10 +361,13 @@ extern "C" int32_t odc_server_create(odc_context* ctx, const odc_server_config* 
   if (c.n_lanes == 0) c.n_lanes = 2;
   if (c.max_batch == 0) c.max_batch = 16;
   if (c.max_batch_corners == 0) c.max_batch_corners = (int64_t)1 << 25;
+  if (c.age_ms == 0.0f) c.age_ms = 1000.0f;
   if (c.hbm_budget_bytes < (1 << 20) || c.n_lanes < 1 || c.n_lanes > 8 || c.max_batch < 1 ||
-      c.max_batch > kMaxJobs || c.max_batch_corners < 1)
+      c.max_batch > kMaxJobs || c.max_batch_corners < 1 ||
+      (c.policy != ODC_SERVE_FIFO && c.policy != ODC_SERVE_SHORTEST) || !(c.age_ms > 0.0f))
     return ctx_fail(ctx, ODC_ERR_INVALID_ARG,
-                    "server needs a budget >= 1 MiB, 1..8 lanes and 1..%d jobs per batch",
+                    "server needs a budget >= 1 MiB, 1..8 lanes, 1..%d jobs per batch, "
+                    "a known policy and age_ms > 0",
                     kMaxJobs);
   odc_server* s = new odc_server();
   s->device = ctx->device;
@@ -395,6 +435,7 @@ extern "C" int32_t odc_server_submit(odc_server* s, const odc_field* f, const od
     std::lock_guard<std::mutex> lk(s->mu);
     r->cap_edges = estimate_edges(s->cap_scale, p->res);
     r->bytes = job_scratch_bytes(f, p, r->cap_edges, false);
+    r->cost = job_cost(*f, *p);
     if (r->bytes > s->arena.capacity()) {
       const size_t need = r->bytes;
       delete r;

@@ -140,3 +140,44 @@ def test_admission_limits_and_errors(odc):
         srv.poll(123456789)
     srv.close()
     ctx.close()
+
+
+def test_shortest_first_and_aging(odc):
+    """SHORTEST admits the cheaper of two queued jobs first; with a tiny age
+    bound every queued job is aged and the order is arrival order again.
+    Each job's mesh is the one it gives alone."""
+    ctx = odc.Context(0)
+    fb = I.mlp_field(5200)
+    blocker = (odc.DeviceField(fb), odc.default_params(I.unit_grid(160, 15), 0))
+    big = (odc.DeviceField(I.mlp_field(5201)), odc.default_params(I.unit_grid(96, 15), 0))
+    small = (odc.DeviceField(I.csg_random_field(5202)), odc.default_params(I.unit_grid(24, 15), 0))
+    ref = {}
+    for name, (df, p) in (("big", big), ("small", small)):
+        r = ctx.extract(df, p)
+        ref[name] = (r["vertices"].cpu().numpy().copy(), r["triangles"].cpu().numpy().copy())
+    orders = {}
+    for policy, age in ((odc.SERVE_FIFO, 0.0), (odc.SERVE_SHORTEST, 60000.0),
+                        (odc.SERVE_SHORTEST, 1e-3)):
+        srv = odc.Server(ctx, 1 << 31, lanes=1, max_batch=1, policy=policy, age_ms=age)
+        ob = odc.OutputBuffers(1 << 20, 1 << 21)
+        tb = srv.submit(blocker[0], blocker[1], ob)
+        outs = {n: odc.OutputBuffers(len(ref[n][0]) + 16, len(ref[n][1]) + 16) for n in ref}
+        tg = srv.submit(big[0], big[1], outs["big"])
+        ts = srv.submit(small[0], small[1], outs["small"])
+        rb, rg, rs = srv.wait(tb), srv.wait(tg), srv.wait(ts)
+        srv.close()
+        assert rb["status"] == rg["status"] == rs["status"] == odc.OK
+        # both later jobs were still queued when the blocker finished
+        assert rb["done_ms"] >= max(rg["submit_ms"], rs["submit_ms"])
+        for n, r in (("big", rg), ("small", rs)):
+            got = outs[n].views(r)
+            assert np.array_equal(got["vertices"].cpu().numpy(), ref[n][0]), (policy, n)
+            assert np.array_equal(got["triangles"].cpu().numpy(), ref[n][1]), (policy, n)
+        orders[(policy, age)] = "small" if rs["admit_ms"] < rg["admit_ms"] else "big"
+    assert orders[(odc.SERVE_FIFO, 0.0)] == "big"
+    assert orders[(odc.SERVE_SHORTEST, 60000.0)] == "small"
+    assert orders[(odc.SERVE_SHORTEST, 1e-3)] == "big"
+    with pytest.raises(odc.OdcError) as e:
+        odc.Server(ctx, 1 << 28, policy=7)
+    assert e.value.status == odc.ERR_INVALID_ARG
+    ctx.close()
