@@ -312,7 +312,7 @@ __global__ __launch_bounds__(256) void k_labels_csg(const Job* __restrict__ jobs
 // queued for fp32 re-evaluation
 template <int BF16>
 __global__ __launch_bounds__(256) void k_labels_mlp(const Job* __restrict__ jobs, int njobs) {
-  __shared__ float act_lds[kBlock / 64][BF16 ? kActVecsBF16 * 4 : kActWords];
+  __shared__ __align__(16) float act_lds[kBlock / 64][BF16 ? kActVecsBF16 * 4 : kActWords];
   float* act = act_lds[threadIdx.x >> 6];
   for_units(jobs, njobs, gwave(), nwaves(),
             [](const Job& J) { return (J.kind == 1 && J.precision == BF16) ? J.nw_c : 0; },
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(256) void k_labels_mlp(const Job* __restrict__ jobs
 
 // fp32 re-evaluation of the corners queued by the bf16 pass
 __global__ __launch_bounds__(256) void k_relabel_fp32(const Job* __restrict__ jobs, int njobs) {
-  __shared__ float act_lds[kBlock / 64][kActWords];
+  __shared__ __align__(16) float act_lds[kBlock / 64][kActWords];
   float* act = act_lds[threadIdx.x >> 6];
   for_units(jobs, njobs, gwave(), nwaves(),
             [](const Job& J) {
@@ -605,7 +605,7 @@ __global__ __launch_bounds__(256) void k_bisect_csg(const Job* __restrict__ jobs
 }
 
 __global__ __launch_bounds__(256) void k_bisect_mlp(const Job* __restrict__ jobs, int njobs) {
-  __shared__ float act_lds[kBlock / 64][kActWords];
+  __shared__ __align__(16) float act_lds[kBlock / 64][kActWords];
   float* act = act_lds[threadIdx.x >> 6];
   for_units(jobs, njobs, gwave(), nwaves(),
             [](const Job& J) { return J.kind == 1 ? (n_edges_of(J) + 31) >> 5 : 0; },
@@ -811,7 +811,7 @@ __global__ __launch_bounds__(256) void k_search2d_csg(const Job* __restrict__ jo
 }
 
 __global__ __launch_bounds__(256) void k_search2d_mlp(const Job* __restrict__ jobs, int njobs) {
-  __shared__ float act_lds[kBlock / 64][kActWords];
+  __shared__ __align__(16) float act_lds[kBlock / 64][kActWords];
   float* act = act_lds[threadIdx.x >> 6];
   for_units(jobs, njobs, gwave(), nwaves(),
             [](const Job& J) { return J.kind == 1 ? (n_pairs_of(J) + 31) >> 5 : 0; },
@@ -1297,7 +1297,7 @@ template <int BF16>
 __global__ __launch_bounds__(256) void k_eval_mlp(const Job* __restrict__ job,
                                                   const float* __restrict__ xyz, int n,
                                                   float* __restrict__ z) {
-  __shared__ float act_lds[kBlock / 64][BF16 ? kActVecsBF16 * 4 : kActWords];
+  __shared__ __align__(16) float act_lds[kBlock / 64][BF16 ? kActVecsBF16 * 4 : kActWords];
   float* act = act_lds[threadIdx.x >> 6];
   const Mlp& m = job->mlp;
   const int lane = lane_id();
