@@ -183,8 +183,8 @@ __device__ void pack_mlp(const float* __restrict__ w, int in_dim, int depth, lon
     if (r < n_w1f) {
       const int c = r % 4, lane = (r / 4) % 64, q = (r / 256) % 2, b = (int)(r / 512);
       const int R = 4 * q + c;
-      const int row = 32 * R + (lane & 31), k = 2 * b + (lane >> 5);
-      w1f[r] = k < in_dim ? w[(size_t)row * in_dim + k] : 0.0f;
+      const int row = 32 * R + (lane & 31), k = feature_of_pair(b, lane >> 5);
+      w1f[r] = k >= 0 && k < in_dim ? w[(size_t)row * in_dim + k] : 0.0f;
       return;
     }
     r -= n_w1f;
@@ -206,8 +206,8 @@ __device__ void pack_mlp(const float* __restrict__ w, int in_dim, int depth, lon
       v8bf v;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const int k = 16 * b + 8 * h + j;
-        v[j] = (__bf16)(k < in_dim ? w[(size_t)row * in_dim + k] : 0.0f);
+        const int k = feature_of_pair(8 * b + j, h);
+        v[j] = (__bf16)(k >= 0 && k < in_dim ? w[(size_t)row * in_dim + k] : 0.0f);
       }
       w1b[r] = v;
       return;
@@ -312,7 +312,7 @@ __global__ __launch_bounds__(256) void k_labels_csg(const Job* __restrict__ jobs
 // queued for fp32 re-evaluation
 template <int BF16>
 __global__ __launch_bounds__(256) void k_labels_mlp(const Job* __restrict__ jobs, int njobs) {
-  __shared__ __align__(16) float act_lds[kBlock / 64][BF16 ? kActVecsBF16 * 4 : kActWords];
+  __shared__ __align__(16) float act_lds[kBlock / 64][BF16 ? kActWordsBF16 : kActWords];
   float* act = act_lds[threadIdx.x >> 6];
   for_units(jobs, njobs, gwave(), nwaves(),
             [](const Job& J) { return (J.kind == 1 && J.precision == BF16) ? J.nw_c : 0; },
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(256) void k_labels_mlp(const Job* __restrict__ jobs
                                    (float)(cc / (n1 * n1))};
               float x[3];
               grid_world(g, gp, x);
-              const float z = BF16 ? mlp_logit_bf16(J.mlp, x, reinterpret_cast<v8bf*>(act))
+              const float z = BF16 ? mlp_logit_bf16(J.mlp, x, act)
                                    : mlp_logit_fp32(J.mlp, x, act);
               const uint64_t b = __ballot(valid && z > 0.0f);
               if (lane == 0) J.labels[t] = (uint32_t)b;
@@ -1297,7 +1297,7 @@ template <int BF16>
 __global__ __launch_bounds__(256) void k_eval_mlp(const Job* __restrict__ job,
                                                   const float* __restrict__ xyz, int n,
                                                   float* __restrict__ z) {
-  __shared__ __align__(16) float act_lds[kBlock / 64][BF16 ? kActVecsBF16 * 4 : kActWords];
+  __shared__ __align__(16) float act_lds[kBlock / 64][BF16 ? kActWordsBF16 : kActWords];
   float* act = act_lds[threadIdx.x >> 6];
   const Mlp& m = job->mlp;
   const int lane = lane_id();
@@ -1305,7 +1305,7 @@ __global__ __launch_bounds__(256) void k_eval_mlp(const Job* __restrict__ job,
     const int i = t * 32 + (lane & 31);
     const int k = i < n ? i : n - 1;
     const float x[3] = {xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2]};
-    const float v = BF16 ? mlp_logit_bf16(m, x, reinterpret_cast<v8bf*>(act))
+    const float v = BF16 ? mlp_logit_bf16(m, x, act)
                          : mlp_logit_fp32(m, x, act);
     if (i < n && lane < 32) z[i] = v;
   }

@@ -12,10 +12,12 @@
 // mlp_logit_fp32), which frees registers for the weight prefetch.
 //
 //  fp32 path  v_mfma_f32_32x32x2_f32: K block b (2 rows), lane half h gives
-//             row 2b+h.  Hidden-layer virtual K row (b = 16T + i, h) is
-//             physical neuron 32T + 8(i/4) + 4h + i%4.
+//             row 2b+h.  Layer-1 block b is input pair b (below); hidden-layer
+//             virtual K row (b = 16T + i, h) is physical neuron
+//             32T + 8(i/4) + 4h + i%4.
 //  bf16 path  v_mfma_f32_32x32x16_bf16: K block b (16 rows), lane half h
-//             gives rows 16b + 8h + j, j < 8.  Hidden-layer virtual row
+//             gives rows 16b + 8h + j, j < 8.  Layer-1 row (b, h, j) is member
+//             h of input pair 8b + j; hidden-layer virtual row
 //             (b = 2T + beta, h, j) is physical neuron 32T + 16 beta +
 //             8(j/4) + 4h + j%4, taken from accumulator register 8 beta + j.
 //
@@ -38,11 +40,36 @@ constexpr int kMaxDepth = 8;
 constexpr int kMaxInDim = 45;
 constexpr int kHiddenBlocksF32 = kWidth / 2;    // 128 K blocks of 2
 constexpr int kHiddenBlocksBF16 = kWidth / 16;  // 16 K blocks of 16
+// Layer-1 inputs gamma(x): (x, y, z), then per band j: sin(2^j pi x_a),
+// a < 3, then cos(2^j pi x_a).  The matrix cores consume them in pairs, lane
+// half h taking member h: pair 0 = (x, y), pair 1 = (z, none), pair
+// 2 + 3j + a = (sin, cos)(2^j pi x_a).  The packed layer-1 weights follow
+// this order (feature_of_pair), so both halves run the same instructions.
+__host__ __device__ constexpr int feature_of_pair(int p, int h) {
+  return p == 0 ? h : (p == 1 ? (h ? -1 : 2) : 3 + 6 * ((p - 2) / 3) + 3 * h + (p - 2) % 3);
+}
+__host__ __device__ constexpr int n_pairs(int in_dim) { return (in_dim + 1) / 2; }
+// every input of gamma is a member of exactly one of the first n_pairs pairs
+constexpr bool pairs_cover(int in_dim) {
+  for (int k = 0; k < in_dim; ++k) {
+    int n = 0;
+    for (int p = 0; p < n_pairs(in_dim); ++p)
+      for (int h = 0; h < 2; ++h) n += feature_of_pair(p, h) == k;
+    if (n != 1) return false;
+  }
+  for (int p = 0; p < n_pairs(in_dim); ++p)
+    for (int h = 0; h < 2; ++h)
+      if (feature_of_pair(p, h) >= in_dim) return false;
+  return true;
+}
+static_assert(pairs_cover(3) && pairs_cover(9) && pairs_cover(39) && pairs_cover(45),
+              "input pairs must cover gamma exactly");
+
 // Layer-1 K blocks, padded with zero weights to whole groups of 4 so that one
 // register ring streams layer 1 and the hidden layers alike (they are
 // contiguous in memory); at most 6 (fp32) and 1 (bf16) groups.
-__host__ __device__ constexpr int kb1_fp32(int in_dim) { return ((in_dim + 1) / 2 + 3) / 4 * 4; }
-__host__ __device__ constexpr int kb1_bf16(int in_dim) { return ((in_dim + 15) / 16 + 3) / 4 * 4; }
+__host__ __device__ constexpr int kb1_fp32(int in_dim) { return (n_pairs(in_dim) + 3) / 4 * 4; }
+__host__ __device__ constexpr int kb1_bf16(int in_dim) { return ((n_pairs(in_dim) + 7) / 8 + 3) / 4 * 4; }
 constexpr int kMaxGroups1F32 = kb1_fp32(45) / 4;
 constexpr int kMaxGroups1BF16 = kb1_bf16(45) / 4;
 
@@ -97,31 +124,41 @@ __device__ __forceinline__ float bias_of(const ODC_CONST float* v, int T, int i,
   return h ? hi : lo;
 }
 
-// Feature k of gamma(x): (x, y, z), then per band j: sin(2^j pi x_a), a < 3,
-// then cos(2^j pi x_a); 0 past in_dim.  The argument is taken in
-// revolutions, a = 2^(j-1) x_a (exact), reduced exactly to [-1/2, 1/2] by
-// subtracting the nearest integer, and handed to the hardware sine and
-// cosine (absolute error ~1.2e-7 against the correctly rounded sin(pi t)
-// on this range: about two binary32 ulps of a value near 1).
-__device__ __forceinline__ float mlp_feature(int k, const float x[3], int in_dim) {
-  if (k >= in_dim) return 0.0f;
-  if (k < 3) return k == 0 ? x[0] : (k == 1 ? x[1] : x[2]);
-  const int r = k - 3;
-  const int band = r / 6;
-  const int w = r - 6 * band;
-  const int axis = w % 3;
-  const float xa = axis == 0 ? x[0] : (axis == 1 ? x[1] : x[2]);
-  const float a = xa * (float)(1 << band) * 0.5f;  // sin(pi t) = sin(2 pi (t / 2))
-  const float rev = a - __builtin_rintf(a);
-  return w >= 3 ? __builtin_amdgcn_cosf(rev) : __builtin_amdgcn_sinf(rev);
+// The phase in revolutions, 2^(j-1) x_a (exact), reduced exactly to
+// [-1/2, 1/2] by subtracting the nearest integer.
+__device__ __forceinline__ float pair_phase(int p, const float x[3]) {
+  const int q = p - 2, j = q / 3, a = q % 3;
+  const float t = x[a] * (j == 0 ? 0.5f : (float)(1 << (j - 1)));
+  return t - __builtin_rintf(t);
+}
+
+// binary32 member h of pair p: the hardware sine or cosine of the reduced
+// phase (absolute error ~1.2e-7 against the correctly rounded value on this
+// range: about two binary32 ulps of a value near 1).
+__device__ __forceinline__ float pair_feature(int p, int h, const float x[3]) {
+  if (p == 0) return h ? x[1] : x[0];
+  if (p == 1) return h ? 0.0f : x[2];
+  const float r = pair_phase(p, x);
+  return h ? __builtin_amdgcn_cosf(r) : __builtin_amdgcn_sinf(r);
+}
+
+// The same for the bf16 path (inputs rounded to bf16, relative error 2^-9):
+// cos(2 pi r) = sin(2 pi (r + 1/4)), one transcendental for either half;
+// the added quarter rounds by at most 2^-25 revolutions.
+__device__ __forceinline__ float pair_feature_fast(int p, float quarter_h, int h,
+                                                   const float x[3]) {
+  if (p == 0) return h ? x[1] : x[0];
+  if (p == 1) return h ? 0.0f : x[2];
+  return __builtin_amdgcn_sinf(pair_phase(p, x) + quarter_h);
 }
 
 // |x - c| - r of one sphere (c, r): squared distance by fused multiply-adds,
 // hardware square root (within 1 ulp).
-__device__ __forceinline__ float sphere_term(const ODC_CONST float* sp, const float x[3]) {
-  const float dx = x[0] - sp[0], dy = x[1] - sp[1], dz = x[2] - sp[2];
+__device__ __forceinline__ float sphere_term(float cx, float cy, float cz, float r,
+                                             const float x[3]) {
+  const float dx = x[0] - cx, dy = x[1] - cy, dz = x[2] - cz;
   const float q = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-  return __builtin_amdgcn_sqrtf(q) - sp[3];
+  return __builtin_amdgcn_sqrtf(q) - r;
 }
 
 // z = out_scale * y - sdf_gain * sdf, from the two half-wave partial sums
@@ -129,15 +166,29 @@ __device__ __forceinline__ float mlp_finish(const Mlp& M, float part, const floa
   const float other = __shfl_xor(part, 32);
   const float y0 = (lane_id() < 32) ? (part + other) : (other + part);
   const float y = y0 + *cmem(M.bout);
-  // spheres four at a time (one 16-dword scalar load each), then the rest
+  // spheres four at a time (one 16-dword scalar load each, issued one group
+  // ahead of its use), then the rest
   const ODC_CONST float* sp = cmem(M.spheres);
+  const int n4 = M.n_spheres & ~3;
   float sdf = INFINITY;
-  int s = 0;
-  for (; s + 4 <= M.n_spheres; s += 4) {
+  if (n4 > 0) {
+    float c[16];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) sdf = fminf(sdf, sphere_term(sp + 4 * (s + u), x));
+    for (int j = 0; j < 16; ++j) c[j] = sp[j];
+    for (int s = 0; s < n4; s += 4) {
+      const int sn = s + 4 < n4 ? s + 4 : s;
+      float nx[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) nx[j] = sp[4 * sn + j];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        sdf = fminf(sdf, sphere_term(c[4 * u], c[4 * u + 1], c[4 * u + 2], c[4 * u + 3], x));
+#pragma unroll
+      for (int j = 0; j < 16; ++j) c[j] = nx[j];
+    }
   }
-  for (; s < M.n_spheres; ++s) sdf = fminf(sdf, sphere_term(sp + 4 * s, x));
+  for (int s = n4; s < M.n_spheres; ++s)
+    sdf = fminf(sdf, sphere_term(sp[4 * s], sp[4 * s + 1], sp[4 * s + 2], sp[4 * s + 3], x));
   const float mt = M.out_scale * y;
   const float st = M.sdf_gain * sdf;
   return mt - st;
@@ -157,6 +208,35 @@ __device__ __forceinline__ float mlp_finish(const Mlp& M, float part, const floa
 // frees 128 registers per lane for the weight prefetch.
 constexpr int kActWords = kHiddenBlocksF32 * 64;
 constexpr int kGroupsF32 = kHiddenBlocksF32 / 4;  // 32 groups of 4 K blocks
+
+// Output layer of either path from the last layer's pre-activations in the
+// accumulators: y = sum_n wout[n] relu(pre_n + bias_n), lane half h taking
+// neurons 8G + 4h + d in the order (G, d), then the sdf term.
+__device__ __forceinline__ float mlp_output(const Mlp& M, const v16f (&acc)[8], int h, int zero,
+                                            const float x[3]) {
+  const ODC_GLOBAL v4f* Bl = (const ODC_GLOBAL v4f*)gmem(M.bias) + (size_t)(M.depth - 1) * 64 + h + zero;
+  const ODC_GLOBAL v4f* Wo = (const ODC_GLOBAL v4f*)gmem(M.wout) + h + zero;
+  float part = 0.0f;
+#pragma unroll
+  for (int G0 = 0; G0 < kGroupsF32; G0 += 8) {
+    v4f bb[8], wo[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      bb[u] = Bl[2 * (G0 + u)];
+      wo[u] = Wo[2 * (G0 + u)];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int G = G0 + u, T = G >> 2, g = G & 3;
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const float a = fmaxf(acc[T][4 * g + d] + bb[u][d], 0.0f);
+        part = __builtin_fmaf(wo[u][d], a, part);
+      }
+    }
+  }
+  return mlp_finish(M, part, x);
+}
 
 // Weight fragments stream through a ring of kPrefetchF32 K blocks held in
 // registers: the load of block b + kPrefetchF32 is issued as block b is
@@ -191,6 +271,10 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
   // bias of layer l, group G, this lane half: vector (l * 64 + 2G + h)
   const ODC_GLOBAL v4f* Bv = (const ODC_GLOBAL v4f*)gmem(M.bias) + h + zero;
   v4f* act4 = reinterpret_cast<v4f*>(act);
+  // layer 1's bias, group 0, fetched ahead of the ring so that waiting for
+  // it at the first hidden layer does not drain the ring
+  v4f bq[2];
+  bq[0] = Bv[0];
   v4f wr[kPrefetchF32][2];
 #pragma unroll
   for (int d = 0; d < kPrefetchF32; ++d)
@@ -203,7 +287,7 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
   // Each block's B operand is formed while the previous block's matrix
   // instructions run (no VALU-to-MFMA dependency at the block boundary).
   const int ng = M.kb1f / kPrefetchF32;
-  float bv = mlp_feature(h, x, M.in_dim);
+  float bv = pair_feature(0, h, x);
 #pragma unroll
   for (int gi = 0; gi < kMaxGroups1F32; ++gi) {
     if (gi == 0 || gi < ng) {
@@ -214,7 +298,7 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
         for (int R = 0; R < 8; ++R)
           acc[R] = __builtin_amdgcn_mfma_f32_32x32x2f32(wr[d][R >> 2][R & 3], bv,
                                                         b == 0 ? zacc : acc[R], 0, 0, 0);
-        bv = mlp_feature(2 * (b + 1) + h, x, M.in_dim);
+        bv = pair_feature(b + 1, h, x);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int q = 0; q < 2; ++q) wr[d][q] = S((b + kPrefetchF32) * 2 + q);
@@ -222,8 +306,6 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
       }
     }
   }
-  v4f bq[2];
-  bq[0] = Bv[0];  // layer 1's bias, group 0
   for (int l = 1; l < M.depth; ++l) {
     // park the pre-activations of layer l
 #pragma unroll
@@ -264,46 +346,59 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
       }
     }
   }
-  // output layer: y = sum_n wout[n] relu(pre_n + bias_n), lane half h taking
-  // neurons 8G + 4h + d, in the order (G, d)
-  const ODC_GLOBAL v4f* Bl = Bv + (size_t)(M.depth - 1) * 64;
-  const ODC_GLOBAL v4f* Wo = (const ODC_GLOBAL v4f*)gmem(M.wout) + h + zero;
-  float part = 0.0f;
-#pragma unroll
-  for (int G0 = 0; G0 < kGroupsF32; G0 += 8) {
-    v4f bb[8], wo[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      bb[u] = Bl[2 * (G0 + u)];
-      wo[u] = Wo[2 * (G0 + u)];
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int G = G0 + u, T = G >> 2, g = G & 3;
-#pragma unroll
-      for (int d = 0; d < 4; ++d) {
-        const float a = fmaxf(acc[T][4 * g + d] + bb[u][d], 0.0f);
-        part = __builtin_fmaf(wo[u][d], a, part);
-      }
-    }
-  }
-  return mlp_finish(M, part, x);
+  return mlp_output(M, acc, h, zero, x);
 }
 
 // bf16 operands, fp32 accumulation (all 64 lanes must be active).  `act`
-// is this wavefront's LDS region of kActBlocksBF16 * 64 eight-element bf16
-// vectors, used as in the fp32 path.
-constexpr int kActVecsBF16 = kHiddenBlocksBF16 * 64;
-// Ring depth of the bf16 hidden-layer weight stream (K blocks of 16 rows;
-// 32 registers per block), as in the fp32 path.
+// is this wavefront's LDS region of kActWordsBF16 floats: the parked
+// pre-activations of the last layer, laid out as in the fp32 path, then the
+// 256 biases of that layer.  A K block b of a hidden layer takes, in lane
+// half h, neurons 16b + 4h + (0..3) and 16b + 8 + 4h + (0..3): parked
+// vectors 2b and 2b + 1 of the lane and bias vectors 4b + h and 4b + 2 + h.
+// Its B operand bf16(relu(pre + bias)) is formed while the previous block's
+// matrix instructions run (bf16 matrix instructions co-issue with a few VALU
+// instructions each; a serial transition between layers would not).
+constexpr int kActWordsBF16 = kActWords + kWidth;
+// Ring depth of the bf16 weight stream (K blocks of 16 rows; 32 registers
+// per block), as in the fp32 path.
 constexpr int kPrefetchBF16 = 4;
 
+// ReLU of two packed bf16 values: a bf16 is below zero exactly when its bits
+// read as a negative 16-bit integer, so a packed signed max against 0 maps
+// negatives (and -0) to +0 and keeps the rest.  Rounding to bf16 is
+// monotonic and keeps 0, so this equals rounding relu(v).
+__device__ __forceinline__ v8bf relu_bf16(v8bf v) {
+  typedef short v8s __attribute__((ext_vector_type(8)));
+  const v8s z = {};
+  return __builtin_bit_cast(v8bf, __builtin_elementwise_max(__builtin_bit_cast(v8s, v), z));
+}
+
+// Two floats to a packed bf16 pair in one instruction (round to nearest even).
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+  typedef float v2f __attribute__((ext_vector_type(2)));
+  typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f){a, b}, v2bf));
+}
+
+__device__ __forceinline__ v8bf bf16_operand(v4f a0, v4f a1, v4f t0, v4f t1) {
+  typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+  const v4f s0 = a0 + t0, s1 = a1 + t1;
+  const v4u p = {pack_bf16(s0[0], s0[1]), pack_bf16(s0[2], s0[3]), pack_bf16(s1[0], s1[1]),
+                 pack_bf16(s1[2], s1[3])};
+  return relu_bf16(__builtin_bit_cast(v8bf, p));
+}
+
 __device__ __forceinline__ float mlp_logit_bf16(const Mlp& M, const float x[3],
-                                                v8bf* __restrict__ act) {
+                                                float* __restrict__ act) {
   const int lane = lane_id();
   const int h = lane >> 5;
   int zero = 0;  // keeps the ring prologue here (see mlp_logit_fp32)
   asm volatile("" : "+v"(zero));
+  v4f* act4 = reinterpret_cast<v4f*>(act);
+  v4f* tab4 = act4 + kGroupsF32 * 64;
+  // this lane's four biases of each layer, fetched one layer ahead
+  const ODC_GLOBAL v4f* Bg = (const ODC_GLOBAL v4f*)gmem(M.bias) + lane + zero;
+  v4f tb = Bg[0];
   // layer 1, then the hidden layers, through a buffer resource as in the
   // fp32 path: vector (8b + R) of the stream holds tile R of K block b
   const __amdgpu_buffer_rsrc_t ws = weight_stream(
@@ -317,23 +412,31 @@ __device__ __forceinline__ float mlp_logit_bf16(const Mlp& M, const float x[3],
   for (int d = 0; d < kPrefetchBF16; ++d)
 #pragma unroll
     for (int R = 0; R < 8; ++R) wr[d][R] = S(d * 8 + R);
+  const v16f zacc = {};
   v16f acc[8];
+  const float quarter_h = h ? 0.25f : 0.0f;
+  auto features = [&](int b) {
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    v4u p;
 #pragma unroll
-  for (int R = 0; R < 8; ++R) acc[R] = (v16f){};
+    for (int j = 0; j < 4; ++j)
+      p[j] = pack_bf16(pair_feature_fast(8 * b + 2 * j, quarter_h, h, x),
+                       pair_feature_fast(8 * b + 2 * j + 1, quarter_h, h, x));
+    return __builtin_bit_cast(v8bf, p);
+  };
   const int ng = M.kb1b / kPrefetchBF16;
+  v8bf bv = features(0);
 #pragma unroll
   for (int gi = 0; gi < kMaxGroups1BF16; ++gi) {
-    if (gi < ng) {
+    if (gi == 0 || gi < ng) {
 #pragma unroll
       for (int d = 0; d < kPrefetchBF16; ++d) {
         const int b = gi * kPrefetchBF16 + d;
-        v8bf bv;
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-          bv[j] = (__bf16)mlp_feature(16 * b + 8 * h + j, x, M.in_dim);
 #pragma unroll
         for (int R = 0; R < 8; ++R)
-          acc[R] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[d][R], bv, acc[R], 0, 0, 0);
+          acc[R] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[d][R], bv, b == 0 ? zacc : acc[R],
+                                                           0, 0, 0);
+        bv = features(b + 1);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int R = 0; R < 8; ++R) wr[d][R] = S((b + kPrefetchBF16) * 8 + R);
@@ -342,35 +445,31 @@ __device__ __forceinline__ float mlp_logit_bf16(const Mlp& M, const float x[3],
     }
   }
   for (int l = 1; l < M.depth; ++l) {
-    // scalar bias reads: vector loads here would queue behind the ring's
-    // refills and wait for all of them
-    const ODC_CONST float* bl = cmem(M.bias) + (l - 1) * kWidth;
+    // park layer l's pre-activations and biases; fetch layer l+1's biases
 #pragma unroll
-    for (int T = 0; T < 8; ++T) {
+    for (int T = 0; T < 8; ++T)
 #pragma unroll
-      for (int beta = 0; beta < 2; ++beta) {
-        v8bf v;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int i = 8 * beta + j;
-          v[j] = (__bf16)fmaxf(acc[T][i] + bias_of(bl, T, i, h), 0.0f);
-        }
-        act[(2 * T + beta) * 64 + lane] = v;
-      }
-      acc[T] = (v16f){};
-    }
+      for (int g = 0; g < 4; ++g)
+        act4[(4 * T + g) * 64 + lane] =
+            (v4f){acc[T][4 * g], acc[T][4 * g + 1], acc[T][4 * g + 2], acc[T][4 * g + 3]};
+    tab4[lane] = tb;
+    tb = Bg[(size_t)l * 64];
     const int wn = (M.kb1b + (l - 1) * kHiddenBlocksBF16 + kPrefetchBF16) * 8;
-    v8bf bvn = act[lane];
+    bv = bf16_operand(act4[lane], act4[64 + lane], tab4[h], tab4[2 + h]);
 #pragma unroll
     for (int b0 = 0; b0 < kHiddenBlocksBF16; b0 += kPrefetchBF16) {
 #pragma unroll
       for (int d = 0; d < kPrefetchBF16; ++d) {
         const int b = b0 + d;
-        const v8bf bv = bvn;
-        bvn = act[((b + 1) & (kHiddenBlocksBF16 - 1)) * 64 + lane];
+        const int bn = (b + 1) & (kHiddenBlocksBF16 - 1);
+        const v4f a0 = act4[(2 * bn) * 64 + lane], a1 = act4[(2 * bn + 1) * 64 + lane];
+        const v4f t0 = tab4[4 * bn + h], t1 = tab4[4 * bn + 2 + h];
 #pragma unroll
         for (int R = 0; R < 8; ++R)
-          acc[R] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[d][R], bv, acc[R], 0, 0, 0);
+          acc[R] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[d][R], bv, b == 0 ? zacc : acc[R],
+                                                           0, 0, 0);
+        // the next block's operand (after the last block: unused)
+        bv = bf16_operand(a0, a1, t0, t1);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int R = 0; R < 8; ++R) wr[d][R] = S(wn + b * 8 + R);
@@ -378,20 +477,7 @@ __device__ __forceinline__ float mlp_logit_bf16(const Mlp& M, const float x[3],
       }
     }
   }
-  const ODC_CONST float* bl = cmem(M.bias) + (M.depth - 1) * kWidth;
-  const ODC_CONST float* wo = cmem(M.wout);
-  float part = 0.0f;
-#pragma unroll
-  for (int T = 0; T < 8; ++T) {
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const float a = fmaxf(acc[T][i] + bias_of(bl, T, i, h), 0.0f);
-      const float p = bias_of(wo, T, i, h) * a;
-      part = part + p;
-    }
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  return mlp_finish(M, part, x);
+  return mlp_output(M, acc, h, zero, x);
 }
 
 }  // namespace odc
