@@ -28,6 +28,8 @@ PRIM_FLOATS = 20
 OP_UNION, OP_SUBTRACT, OP_INTERSECT = 0, 1, 2
 PRIM_SPHERE, PRIM_BOX, PRIM_HALFSPACE = 0, 1, 2
 FIELD_CSG, FIELD_MLP = 0, 1
+# ablation baselines (Table 3): linear 1D points, gradient normals, 2-triangle split
+ABL_LINEAR_1D, ABL_GRAD_NORMALS, ABL_MDC_SPLIT = 1, 2, 4
 
 
 @dataclasses.dataclass
@@ -58,6 +60,7 @@ class Grid:
     range1: float = 0.8
     range2: float = math.sqrt(2.0) / 2.0
     qef_tau: float = 1e-2
+    ablation: int = 0   # 0 = the method; bits 1, 2, 4 = the Table 3 baselines
 
     @property
     def h(self) -> float:

@@ -135,49 +135,108 @@ static int csg_label(const orc_field* f, const float x[3]) {
   return acc;
 }
 
-/* Logit z of the MLP occupancy phi = sigmoid(z), binary64:
- * z = out_scale * MLP(gamma(x)) - sdf_gain * sdf(x),
+/* Logit z(x) of an MLP field (App. B network: gamma, depth ReLU layers, a
+ * linear output; then the sdf term), in binary64 at a binary64 point.
+ *   z = out_scale * y(gamma(x)) - sdf_gain * sdf(x)
  * gamma(x) = (x, sin(2^k pi x), cos(2^k pi x)), k = 0..n_bands-1,
- * sdf = min over spheres of (|x - c| - r). */
-static double mlp_logit(const orc_field* f, const float xf[3]) {
-  double x[3] = {xf[0], xf[1], xf[2]};
-  int in = f->in_dim, W = f->width;
-  double* h0 = (double*)malloc(sizeof(double) * (size_t)(in > W ? in : W));
-  double* h1 = (double*)malloc(sizeof(double) * (size_t)W);
-  for (int a = 0; a < 3; ++a) h0[a] = x[a];
+ * sdf = min over spheres of (|x - c| - r).
+ * With grad != NULL also dz/dx by reverse-mode differentiation: the ReLU's
+ * derivative is 0 where its input is <= 0 (the forward pass keeps exactly
+ * the positive inputs), and the sdf term differentiates through its nearest
+ * sphere (the first in index order on a tie). */
+static double mlp_eval(const orc_field* f, const double x[3], double grad[3]) {
+  const int in = f->in_dim, W = f->width, D = f->depth;
+  double* act = (double*)malloc(sizeof(double) * ((size_t)in + (size_t)D * W));
+  double* pre = (double*)malloc(sizeof(double) * (size_t)D * W);
+  for (int a = 0; a < 3; ++a) act[a] = x[a];
   for (int k = 0; k < f->n_bands; ++k) {
     double s = ldexp(1.0, k);
     for (int a = 0; a < 3; ++a) {
-      h0[3 + 6 * k + a] = sin(M_PI * (s * x[a]));
-      h0[3 + 6 * k + 3 + a] = cos(M_PI * (s * x[a]));
+      act[3 + 6 * k + a] = sin(M_PI * (s * x[a]));
+      act[3 + 6 * k + 3 + a] = cos(M_PI * (s * x[a]));
     }
   }
+  /* layer l reads its input at act + off_in[l] and writes its output after it */
   const float* w = f->weights;
+  const float* Wl_of[64];
+  size_t off = 0;
   int n_in = in;
-  for (int layer = 0; layer < f->depth; ++layer) {
+  for (int l = 0; l < D; ++l) {
     const float* Wl = w;
     const float* bl = w + (size_t)W * n_in;
+    Wl_of[l] = Wl;
+    double* hin = act + off;
+    double* hout = act + off + n_in;
     for (int j = 0; j < W; ++j) {
       double acc = bl[j];
-      for (int i = 0; i < n_in; ++i) acc += (double)Wl[(size_t)j * n_in + i] * h0[i];
-      h1[j] = acc > 0.0 ? acc : 0.0;
+      for (int i = 0; i < n_in; ++i) acc += (double)Wl[(size_t)j * n_in + i] * hin[i];
+      pre[(size_t)l * W + j] = acc;
+      hout[j] = acc > 0.0 ? acc : 0.0;
     }
     w = bl + W;
-    for (int j = 0; j < W; ++j) h0[j] = h1[j];
+    off += n_in;
     n_in = W;
   }
+  const double* hlast = act + off;
   double y = w[W];
-  for (int i = 0; i < W; ++i) y += (double)w[i] * h0[i];
-  free(h0);
-  free(h1);
-  double sdf = INFINITY;
+  for (int i = 0; i < W; ++i) y += (double)w[i] * hlast[i];
+  double sdf = INFINITY, dnear[3] = {0, 0, 0}, rnear = 0.0;
   for (int s = 0; s < f->n_spheres; ++s) {
     const float* sp = f->spheres + 4 * s;
     double dx = x[0] - sp[0], dy = x[1] - sp[1], dz = x[2] - sp[2];
-    double d = sqrt(dx * dx + dy * dy + dz * dz) - sp[3];
-    if (d < sdf) sdf = d;
+    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    double d = r - sp[3];
+    if (d < sdf) {
+      sdf = d;
+      dnear[0] = dx;
+      dnear[1] = dy;
+      dnear[2] = dz;
+      rnear = r;
+    }
   }
+  if (grad) {
+    /* g = dz/d(pre-activation) of the current layer, walked down */
+    double* g = (double*)malloc(sizeof(double) * (size_t)(W > in ? W : in));
+    double* gn = (double*)malloc(sizeof(double) * (size_t)(W > in ? W : in));
+    for (int j = 0; j < W; ++j)
+      g[j] = pre[(size_t)(D - 1) * W + j] > 0.0 ? f->out_scale * (double)w[j] : 0.0;
+    for (int l = D - 1; l >= 0; --l) {
+      const int ni = l == 0 ? in : W;
+      for (int i = 0; i < ni; ++i) {
+        double acc = 0.0;
+        for (int j = 0; j < W; ++j) acc += (double)Wl_of[l][(size_t)j * ni + i] * g[j];
+        gn[i] = acc;
+      }
+      if (l > 0)
+        for (int i = 0; i < W; ++i) g[i] = pre[(size_t)(l - 1) * W + i] > 0.0 ? gn[i] : 0.0;
+    }
+    /* gn = dz/dgamma; chain through gamma */
+    for (int a = 0; a < 3; ++a) {
+      double d = gn[a];
+      for (int k = 0; k < f->n_bands; ++k) {
+        double s = ldexp(1.0, k);
+        d += gn[3 + 6 * k + a] * M_PI * s * cos(M_PI * (s * x[a]));
+        d -= gn[3 + 6 * k + 3 + a] * M_PI * s * sin(M_PI * (s * x[a]));
+      }
+      if (rnear > 0.0) d -= f->sdf_gain * dnear[a] / rnear;
+      grad[a] = d;
+    }
+    free(g);
+    free(gn);
+  }
+  free(act);
+  free(pre);
   return f->out_scale * y - f->sdf_gain * sdf;
+}
+
+static double mlp_logit(const orc_field* f, const float xf[3]) {
+  double x[3] = {xf[0], xf[1], xf[2]};
+  return mlp_eval(f, x, NULL);
+}
+
+double orc_logit_grad(const orc_field* f, const double x[3], double grad[3]) {
+  if (f->kind != ORC_FIELD_MLP || f->depth > 64) return NAN;
+  return mlp_eval(f, x, grad);
 }
 
 int orc_label_world(const orc_field* f, const float xyz[3], int* tie, double* margin) {
@@ -227,6 +286,37 @@ static double bisect_edge(const orc_field* f, const orc_params* p, int a, const 
   return 0.5 * (lo_t + hi_t);
 }
 
+/* MDC's 1D point (Eq. 1) from continuous occupancy, the ablation baseline:
+ * psi = phi - 1/2 at the edge's two corners, written psi = tanh(z/2)/2 for
+ * phi = sigmoid(z) (the same number, without the cancellation near 1/2), and
+ * t = psi(lower) / (psi(lower) - psi(upper)).  A CSG field's occupancy is
+ * the label itself, so t = 1/2. */
+static double linear_edge(const orc_field* f, const orc_params* p, int a, const int pos[3]) {
+  int up[3] = {pos[0], pos[1], pos[2]};
+  up[a] += 1;
+  double psi[2];
+  for (int e = 0; e < 2; ++e) {
+    const int* q = e == 0 ? pos : up;
+    if (f->kind == ORC_FIELD_CSG) {
+      psi[e] = orc_corner_label(f, p, q[0], q[1], q[2], NULL) - 0.5;
+    } else {
+      float g[3] = {(float)q[0], (float)q[1], (float)q[2]}, x[3];
+      grid_to_world(p, g, x);
+      psi[e] = 0.5 * tanh(0.5 * mlp_logit(f, x));
+    }
+  }
+  return psi[0] / (psi[0] - psi[1]);
+}
+
+static double edge_point_mode(const orc_field* f, const orc_params* p, int a, const int pos[3],
+                              int label0, int* tie_step) {
+  if (p->ablation & ORC_ABL_LINEAR_1D) {
+    *tie_step = 0;
+    return linear_edge(f, p, a, pos);
+  }
+  return bisect_edge(f, p, a, pos, label0, tie_step);
+}
+
 double orc_edge_point(const orc_field* f, const orc_params* p, int64_t eid, int* tie_step) {
   int N = p->res, a, pos[3];
   edge_decode(N, eid, &a, pos);
@@ -235,7 +325,7 @@ double orc_edge_point(const orc_field* f, const orc_params* p, int64_t eid, int*
   int l0 = orc_corner_label(f, p, pos[0], pos[1], pos[2], NULL);
   int l1 = orc_corner_label(f, p, up[0], up[1], up[2], NULL);
   if (l0 == l1) return -1.0;
-  return bisect_edge(f, p, a, pos, l0, tie_step);
+  return edge_point_mode(f, p, a, pos, l0, tie_step);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -815,6 +905,23 @@ static int cell_solve(const cell_ctx* cx, const int c[3], double* verts, int* pa
       tie |= et;
       double pe[3] = {off[0], off[1], off[2]};
       pe[axis] = t;
+      double* row = planes + 6 * n;
+      if (p->ablation & ORC_ABL_GRAD_NORMALS) {
+        /* Eq. 2 with the field's gradient at the 1D point (the ablation
+         * baseline); the query point is built as the searches build theirs */
+        float g[3] = {(float)gpos[0], (float)gpos[1], (float)gpos[2]}, xw[3];
+        g[axis] = (float)gpos[axis] + (float)t;
+        grid_to_world(p, g, xw);
+        double xd[3] = {xw[0], xw[1], xw[2]}, gr[3];
+        mlp_eval(cx->f, xd, gr);
+        double gl = sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
+        for (int q = 0; q < 3; ++q) {
+          row[q] = gl > 0.0 ? gr[q] / gl : 0.0;
+          row[3 + q] = pe[q];
+        }
+        ++n;
+        continue;
+      }
       /* the two faces of this cell that contain the edge */
       double pfs[2][3];
       for (int w = 0; w < 2; ++w) {
@@ -850,7 +957,6 @@ static int cell_solve(const cell_ctx* cx, const int c[3], double* verts, int* pa
       double nn[3] = {a1[1] * a2[2] - a1[2] * a2[1], a1[2] * a2[0] - a1[0] * a2[2],
                       a1[0] * a2[1] - a1[1] * a2[0]};
       double nl = sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
-      double* row = planes + 6 * n;
       for (int x = 0; x < 3; ++x) {
         row[x] = nl > 0.0 ? nn[x] / nl : 0.0;
         row[3 + x] = pe[x];
@@ -919,6 +1025,8 @@ static int valid_params(const orc_field* f, const orc_params* p) {
   if (p->lin1 < 1 || p->lin2 < 1 || p->bin1 < 0 || p->bin2 < 0) return 0;
   if (f->kind == ORC_FIELD_CSG && (f->n_prims < 1 || !f->prims)) return 0;
   if (f->kind == ORC_FIELD_MLP && (!f->weights || f->depth < 1 || f->width < 1)) return 0;
+  if (p->ablation & ~(ORC_ABL_LINEAR_1D | ORC_ABL_GRAD_NORMALS | ORC_ABL_MDC_SPLIT)) return 0;
+  if ((p->ablation & ORC_ABL_GRAD_NORMALS) && (f->kind != ORC_FIELD_MLP || f->depth > 64)) return 0;
   return 1;
 }
 
@@ -975,7 +1083,7 @@ int orc_mesh_extract(const orc_field* f, const orc_params* p, orc_mesh* m) {
     int a, pos[3], ts = 0;
     edge_decode(N, m->edge_id[x], &a, pos);
     int l0 = lab[corner_id(N, pos[0], pos[1], pos[2])];
-    m->edge_t[x] = bisect_edge(f, p, a, pos, l0, &ts);
+    m->edge_t[x] = edge_point_mode(f, p, a, pos, l0, &ts);
     m->edge_tie_step[x] = ts;
   }
 
@@ -1022,7 +1130,14 @@ int orc_mesh_extract(const orc_field* f, const orc_params* p, orc_mesh* m) {
     float P1[2], P2[2];
     face_edge_point(fa, (float)m->edge_t[ia], P1);
     face_edge_point(fb, (float)m->edge_t[ib], P2);
-    pair_result r = search_pair(f, p, &g, L, P1, P2);
+    pair_result r;
+    if (p->ablation & ORC_ABL_GRAD_NORMALS) {
+      /* gradient normals need no 2D points */
+      memset(&r, 0, sizeof(r));
+      r.pf[0] = r.pf[1] = NAN;
+    } else {
+      r = search_pair(f, p, &g, L, P1, P2);
+    }
     m->pair_pf[2 * x] = r.pf[0];
     m->pair_pf[2 * x + 1] = r.pf[1];
     int ctie = 0;
@@ -1141,8 +1256,13 @@ int orc_mesh_extract(const orc_field* f, const orc_params* p, orc_mesh* m) {
     if (lower_in) pout[a] += 1.0;
     else pin[a] += 1.0;
     int it = 0;
-    m->edge_case[x] = orc_ic_case(Q, pin, pout, p->ic_tie_tol, &it);
-    m->edge_case_tie[x] = (uint8_t)(tie || it);
+    if (p->ablation & ORC_ABL_MDC_SPLIT) {
+      m->edge_case[x] = 1; /* the plain two-triangle split (ablation baseline) */
+      m->edge_case_tie[x] = 0;
+    } else {
+      m->edge_case[x] = orc_ic_case(Q, pin, pout, p->ic_tie_tol, &it);
+      m->edge_case_tie[x] = (uint8_t)(tie || it);
+    }
   }
   int64_t n3 = 0, nt = 0;
   for (int64_t x = 0; x < ne; ++x) {

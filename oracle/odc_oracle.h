@@ -70,7 +70,16 @@ typedef struct {
   double qef_tau;           /* eigenvalue truncation, relative to the largest */
   double ic_tie_tol;        /* vertex uncertainty (cell widths) for IC near-ties */
   int n_threads;            /* 0 = all */
+  int ablation;             /* 0 = the method; else ORC_ABL_* bits (Table 3 baselines) */
 } orc_params;
+
+/* Ablation baselines (Sec. 4 / Table 3), each replacing one step of the
+ * method with Manifold Dual Contouring's:
+ *   LINEAR_1D     1D points by Eq. 1 from psi = phi - 1/2 at the corners
+ *   GRAD_NORMALS  QEF normals = the field gradient at the 1D point (Eq. 2;
+ *                 MLP fields only), no 2D points
+ *   MDC_SPLIT     every quad split as case 1 (no intersection-free split) */
+enum { ORC_ABL_LINEAR_1D = 1, ORC_ABL_GRAD_NORMALS = 2, ORC_ABL_MDC_SPLIT = 4 };
 
 typedef struct {
   int res;
@@ -132,6 +141,9 @@ int orc_cell_vertices(const orc_field* f, const orc_params* p, int64_t cell_id,
                       double* verts, int* partmap, int* tie, double* kappa);
 
 /* Building blocks exposed for pinning tests. */
+/* Logit z and its gradient dz/dx at a binary64 point of an MLP field (NAN
+ * for other fields). */
+double orc_logit_grad(const orc_field* f, const double x[3], double grad[3]);
 /* Line-binary search along a face-local ray on face `face_id` (FP32 ray
  * geometry as in the search).  Returns the near parameter s; q receives the point. */
 float orc_line_binary(const orc_field* f, const orc_params* p, int64_t face_id,

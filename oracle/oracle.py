@@ -40,7 +40,8 @@ class _Params(C.Structure):
     _fields_ = [("lo", C.c_double * 3), ("size", C.c_double), ("res", C.c_int),
                 ("iters_1d", C.c_int), ("lin1", C.c_int), ("bin1", C.c_int), ("lin2", C.c_int),
                 ("bin2", C.c_int), ("range1", C.c_float), ("range2", C.c_float),
-                ("qef_tau", C.c_double), ("ic_tie_tol", C.c_double), ("n_threads", C.c_int)]
+                ("qef_tau", C.c_double), ("ic_tie_tol", C.c_double), ("n_threads", C.c_int),
+                ("ablation", C.c_int)]
 
 
 _P = C.POINTER
@@ -94,6 +95,8 @@ def lib():
                                       _P(C.c_float), C.c_int, C.c_float, C.c_int, C.c_int,
                                       _P(C.c_float), _P(C.c_int)]
         L.orc_line_binary.restype = C.c_float
+        L.orc_logit_grad.argtypes = [_P(_Field), _P(C.c_double), _P(C.c_double)]
+        L.orc_logit_grad.restype = C.c_double
         L.orc_cube_partitions.argtypes = [C.c_int, C.c_int, _P(C.c_int)]
         L.orc_cube_partitions.restype = C.c_int
         L.orc_qef_solve.argtypes = [C.c_int, _P(C.c_double), C.c_double, _P(C.c_double),
@@ -125,7 +128,7 @@ class Oracle:
                         field.out_scale, mlp_tie_eps)
         self.p = _Params((C.c_double * 3)(*grid.lo), grid.size, grid.res, grid.iters_1d,
                          grid.lin1, grid.bin1, grid.lin2, grid.bin2, grid.range1, grid.range2,
-                         grid.qef_tau, ic_tie_tol, n_threads)
+                         grid.qef_tau, ic_tie_tol, n_threads, getattr(grid, "ablation", 0))
 
     def mesh(self) -> dict:
         m = _Mesh()
@@ -196,6 +199,13 @@ class Oracle:
         n = lib().orc_cell_vertices(C.byref(self.f), C.byref(self.p), int(cid), v,
                                     C.byref(pm), C.byref(tie), kap)
         return n, np.array(v[:3 * n]).reshape(n, 3), pm.value, tie.value
+
+    def logit_grad(self, x):
+        """Binary64 logit and gradient at a binary64 point (MLP fields)."""
+        xd = (C.c_double * 3)(*[float(v) for v in x])
+        g = (C.c_double * 3)()
+        z = lib().orc_logit_grad(C.byref(self.f), xd, g)
+        return z, np.array(g[:])
 
     def line_binary(self, fid, p0, d, s0, rng, n_lin, n_bin):
         a = np.asarray(p0, np.float32)
