@@ -67,3 +67,57 @@ def compare_discrete(r, m):
 
 def mesh_labels_from_oracle(m):
     return m["corner_label"]
+
+
+def corner_ijk(c, n1):
+    return c % n1, (c // n1) % n1, c // (n1 * n1)
+
+
+def edge_corners(e, N):
+    """The two corner indices of crossing edge e (axis-major edge numbering)."""
+    n1 = N + 1
+    ea = N * n1 * n1
+    a, loc = int(e) // ea, int(e) % ea
+    dims = [n1, n1, n1]
+    dims[a] = N
+    p = [loc % dims[0], (loc // dims[0]) % dims[1], loc // (dims[0] * dims[1])]
+    c0 = p[0] + n1 * (p[1] + n1 * p[2])
+    p[a] += 1
+    return c0, p[0] + n1 * (p[1] + n1 * p[2])
+
+
+def sampled_labels(r, g, o, rng, n_uniform, n_edges):
+    """GPU corner labels against the oracle at uniform corners and at both ends
+    of sampled crossing edges; returns the number of near-ties skipped."""
+    n1 = g.res + 1
+    cs = list(rng.integers(0, n1 ** 3, n_uniform))
+    for e in r["edge_ids"][rng.integers(0, len(r["edge_ids"]), n_edges)]:
+        cs.extend(edge_corners(e, g.res))
+    ties = 0
+    for c in cs:
+        lab, tie = o.corner_label(*corner_ijk(int(c), n1))
+        if tie:
+            ties += 1
+            continue
+        assert r["corner_label"][c] == lab, int(c)
+    return len(cs), ties
+
+
+def interior_edge_count(edge_ids, N):
+    """Crossing edges with all four cells inside the grid."""
+    n1 = N + 1
+    e = edge_ids.astype(np.int64)
+    ea = N * n1 * n1
+    a, loc = e // ea, e % ea
+    interior = np.ones(len(e), bool)
+    for ax in range(3):
+        sel = a == ax
+        dims = [n1, n1, n1]
+        dims[ax] = N
+        ijk = [loc[sel] % dims[0], (loc[sel] // dims[0]) % dims[1], loc[sel] // (dims[0] * dims[1])]
+        inner = np.ones(int(sel.sum()), bool)
+        for o in range(3):
+            if o != ax:
+                inner &= (ijk[o] > 0) & (ijk[o] < N)
+        interior[sel] = inner
+    return int(interior.sum())
