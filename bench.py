@@ -17,6 +17,8 @@ Other modes (not run by default):
   --mode copy   a plain device-to-device copy of --copy-mib MiB, repeated
                 --steps times: the reference kernel that scales the HBM byte
                 counters (FETCH_SIZE, WRITE_SIZE) of a profile.
+  --mode ablation  Table 3's rows (MDC, + 1D search, + 2D search, ODC) on the
+                same field: time, counts, manifold check, mean |phi - 1/2|.
   --mode serve  Poisson arrivals (20 requests/s, 50/50 CSG/MLP, res 64/128/
                 256/512 with weights .4/.3/.2/.1) through the continuous-
                 batching server; p50/p99 latency (completion - arrival) and
@@ -120,6 +122,24 @@ def cpu_baseline(field, grid, seconds: float, sub: int = 16, seed: int = 0, cham
             "method": "symmetric mean squared point-to-surface distance, 20k area samples per "
                       "mesh, GPU mesh of the same sub-box at the benchmark's precision; max over boxes"}
     return out
+
+
+def mesh_quality(ctx, df, grid, samples: int = 1000000, params=None) -> dict:
+    """The paper's quality measures of the last mesh (Sec. 6, Table 3), outside
+    the timed region: mean |phi - 1/2| at area-uniform surface samples (phi
+    from the fp32 field evaluation on the GPU), self-intersecting triangle
+    pairs (counted on the GPU) and the closed-manifold check."""
+    from paper_2409_13418_amd import odc
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from meshcheck import is_closed_oriented_manifold, sample_surface
+    r = ctx.extract(df, params if params is not None else odc.default_params(grid))
+    v = r["vertices"].cpu().numpy().astype(np.float64)
+    t = r["triangles"].cpu().numpy()
+    ok, _ = is_closed_oriented_manifold(t, len(v))
+    z = ctx.field_eval(df, sample_surface(v, t, samples, seed=5)).astype(np.float64)
+    return {"abs_phi_minus_half": float(np.mean(np.abs(0.5 * np.tanh(0.5 * z)))),
+            "self_intersecting_pairs": ctx.self_intersections(r["vertices"], r["triangles"], grid.h),
+            "closed_manifold": bool(ok), "samples": samples}
 
 
 def _batch_mode(args):
@@ -286,6 +306,60 @@ def _serve_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def _ablation_mode(args):
+    """Table 3's structure on the benchmark field: Manifold Dual Contouring,
+    + the 1D search, + the 2D search, + the intersection-free split (= ODC).
+    Per row: extraction time, counts, the manifold check, and the fitting
+    error mean |phi - 1/2| at area-uniform samples of the mesh (phi from the
+    fp32 field evaluation on the GPU)."""
+    import torch
+    from paper_2409_13418_amd import odc
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from meshcheck import is_closed_oriented_manifold, sample_surface
+
+    field = I.mlp_field(3)
+    prec = odc.PREC_BF16_GUARDED if args.precision == "bf16" else odc.PREC_FP32
+    ctx = odc.Context(0)
+    df = odc.DeviceField(field)
+    rows = []
+    for name, mode in (("MDC", 7), ("+ 1D search", 6), ("+ 2D search", 4), ("+ IC (= ODC)", 0)):
+        grid = I.unit_grid(args.res, 15)
+        grid.ablation = mode
+        params = odc.default_params(grid, prec)
+        for _ in range(max(args.warmup, 1)):
+            ctx.extract(df, params)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.extract_async(df, params, cap_hint=(ctx.cap_v, ctx.cap_t))
+            counts = ctx.sync()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        r = ctx.extract(df, params)
+        v = r["vertices"].cpu().numpy().astype(np.float64)
+        t = r["triangles"].cpu().numpy()
+        ok, why = is_closed_oriented_manifold(t, len(v))
+        pts = sample_surface(v, t, args.ablation_samples, seed=5)
+        z = ctx.field_eval(df, pts).astype(np.float64)
+        fit = float(np.mean(np.abs(0.5 * np.tanh(0.5 * z))))
+        si = ctx.self_intersections(r["vertices"], r["triangles"], grid.h)
+        rows.append({"row": name, "ablation": mode, "ms": ms,
+                     "cells_per_s": counts["n_active_cells"] / (ms / 1e3),
+                     "n_vertices": counts["n_vertices"], "n_triangles": counts["n_triangles"],
+                     "n_case3": r["n_case3"], "abs_phi_minus_half": fit,
+                     "self_intersecting_pairs": si, "closed_manifold": bool(ok)})
+        print(f"# {name}: {ms:.1f} ms, |phi-1/2| {fit:.3e}, SI pairs {si}, V {counts['n_vertices']}, "
+              f"T {counts['n_triangles']}, manifold {ok}", file=sys.stderr, flush=True)
+    print(json.dumps({
+        "metric": "Table 3 ablation rows on the 256^3 MLP field", "n_gpus": 1,
+        "dtype": "bf16+fp32" if prec == odc.PREC_BF16_GUARDED else "fp32", "data": "synthetic",
+        "steps": args.steps,
+        "config": {"workload": f"mlp{args.res}_ablation", "res": args.res,
+                   "samples": args.ablation_samples,
+                   "fit": "mean |phi - 1/2| = mean |tanh(z/2)|/2 at area-uniform mesh samples",
+                   "self_intersections": "pairs of vertex-disjoint triangles that intersect"},
+        "rows": rows}), flush=True)
+
+
 def _copy_mode(args):
     import torch
     n = int(args.copy_mib) << 20
@@ -303,7 +377,9 @@ def _copy_mode(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", choices=("single", "batch", "serve", "copy"), default="single")
+    ap.add_argument("--mode", choices=("single", "batch", "serve", "copy", "ablation"),
+                    default="single")
+    ap.add_argument("--ablation-samples", type=int, default=1000000)
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-requests", type=int, default=1200)
@@ -330,6 +406,8 @@ def main():
         return _serve_mode(args)
     if args.mode == "copy":
         return _copy_mode(args)
+    if args.mode == "ablation":
+        return _ablation_mode(args)
 
     import torch
     from paper_2409_13418_amd import odc
@@ -399,6 +477,7 @@ def main():
         "stages_ms": stages,
         "roofline": roofline,
     }
+    out["quality"] = mesh_quality(ctx, df, grid, params=params)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(field, grid, args.cpu_seconds, chamfer=(ctx, df, prec))
         cham = cb.pop("chamfer_vs_oracle", None)

@@ -97,7 +97,19 @@ typedef struct {
   double fp64_cond;      /* QEF redone in binary64 above this condition number (1e6) */
   int32_t precision;     /* ODC_PREC_* */
   float guard_logit;     /* bf16 guard band on z: 2 atanh(0.02) for |phi - 0.5| < 0.01 */
+  int32_t ablation;      /* 0 = the method; ODC_ABL_* bits select Table 3's baselines */
 } odc_params;
+
+/* Ablation baselines (Sec. 4 and Table 3): each bit replaces one step of the
+ * method with Manifold Dual Contouring's.
+ *  LINEAR_1D     1D points by Eq. 1 from psi = phi - 1/2 = tanh(z/2)/2 at the
+ *                edge's corners (binary32; 1/2 for a CSG field)
+ *  GRAD_NORMALS  QEF normals = the logit's gradient at the 1D point (Eq. 2),
+ *                by forward-mode differentiation through the network on the
+ *                matrix cores; no 2D points are searched.  MLP fields only
+ *                (UNSUPPORTED otherwise)
+ *  MDC_SPLIT     every quad split as case 1 of App. A.1.5 (no case 3) */
+enum { ODC_ABL_LINEAR_1D = 1, ODC_ABL_GRAD_NORMALS = 2, ODC_ABL_MDC_SPLIT = 4 };
 
 /* Output buffers (device, caller-owned).  vertices: 3 floats per vertex,
  * world coordinates.  triangles: 3 int32 vertex ids each, oriented so the
@@ -193,9 +205,25 @@ int32_t odc_set_launch_config(odc_context* ctx, const int32_t* grid_elem_mlp_blo
  *  7 cell counts          uint32: npart | flipmask << 4 (bit lf: local face 2*axis+side)
  *  8 vertex base          int32 per active cell
  *  9 emission case        int32 per crossing edge: 0 none, 1, 2, 3
+ * 10 edge gradients       3 floats per crossing edge: dz/dx at the 1D point (world
+ *                         units; ODC_ABL_GRAD_NORMALS only, else 0 elements)
  * Errors: INVALID_ARG for an unknown `which`; CAPACITY when cap_bytes is too small. */
 int32_t odc_get_intermediate(odc_context* ctx, int32_t which, void* dst, int64_t cap_bytes,
                              int64_t* n);
+
+/* Self-intersections of a triangle mesh (the quality metric of Sec. 6 and
+ * Table 3): the number of pairs of triangles that share no vertex and whose
+ * closed triangles intersect, counted on the context's GPU.  vertices:
+ * n_vertices x 3 floats, triangles: n_triangles x 3 int32 (device memory,
+ * caller-owned).  cell > 0 is the side of the uniform grid that finds
+ * candidate pairs (the meshing grid's cell width suits this library's
+ * meshes; the count does not depend on it).  Allocates and frees temporary
+ * device memory and synchronises the context's stream.
+ * Errors: INVALID_ARG for bad arguments, a vertex index out of range, a
+ * non-finite triangle or one spanning more than 4096 grid cubes. */
+int32_t odc_count_self_intersections(odc_context* ctx, const float* vertices, int64_t n_vertices,
+                                     const int32_t* triangles, int64_t n_triangles, double cell,
+                                     int64_t* count);
 
 /* Evaluates the field at n world points (xyz: device, 3 floats each) into z
  * (device, n floats): for MLP fields the logit z (inside iff z > 0) computed

@@ -144,7 +144,15 @@ static int csg_label(const orc_field* f, const float x[3]) {
  * derivative is 0 where its input is <= 0 (the forward pass keeps exactly
  * the positive inputs), and the sdf term differentiates through its nearest
  * sphere (the first in index order on a tie). */
+static double mlp_eval_m(const orc_field* f, const double x[3], double grad[3], double margin[2]);
 static double mlp_eval(const orc_field* f, const double x[3], double grad[3]) {
+  return mlp_eval_m(f, x, grad, NULL);
+}
+
+/* As mlp_eval; margin (if not NULL) receives how far the gradient is from a
+ * switch: [0] the gap between the two nearest spheres' distances, [1] the
+ * smallest |pre-activation| of any ReLU. */
+static double mlp_eval_m(const orc_field* f, const double x[3], double grad[3], double margin[2]) {
   const int in = f->in_dim, W = f->width, D = f->depth;
   double* act = (double*)malloc(sizeof(double) * ((size_t)in + (size_t)D * W));
   double* pre = (double*)malloc(sizeof(double) * (size_t)D * W);
@@ -180,19 +188,27 @@ static double mlp_eval(const orc_field* f, const double x[3], double grad[3]) {
   const double* hlast = act + off;
   double y = w[W];
   for (int i = 0; i < W; ++i) y += (double)w[i] * hlast[i];
-  double sdf = INFINITY, dnear[3] = {0, 0, 0}, rnear = 0.0;
+  double sdf = INFINITY, sdf2 = INFINITY, dnear[3] = {0, 0, 0}, rnear = 0.0;
   for (int s = 0; s < f->n_spheres; ++s) {
     const float* sp = f->spheres + 4 * s;
     double dx = x[0] - sp[0], dy = x[1] - sp[1], dz = x[2] - sp[2];
     double r = sqrt(dx * dx + dy * dy + dz * dz);
     double d = r - sp[3];
+    if (d >= sdf && d < sdf2) sdf2 = d;
     if (d < sdf) {
+      sdf2 = sdf;
       sdf = d;
       dnear[0] = dx;
       dnear[1] = dy;
       dnear[2] = dz;
       rnear = r;
     }
+  }
+  if (margin) {
+    margin[0] = sdf2 - sdf;
+    double mp = INFINITY;
+    for (size_t i = 0; i < (size_t)D * W; ++i) mp = fmin(mp, fabs(pre[i]));
+    margin[1] = mp;
   }
   if (grad) {
     /* g = dz/d(pre-activation) of the current layer, walked down */
@@ -234,9 +250,9 @@ static double mlp_logit(const orc_field* f, const float xf[3]) {
   return mlp_eval(f, x, NULL);
 }
 
-double orc_logit_grad(const orc_field* f, const double x[3], double grad[3]) {
+double orc_logit_grad(const orc_field* f, const double x[3], double grad[3], double margin[2]) {
   if (f->kind != ORC_FIELD_MLP || f->depth > 64) return NAN;
-  return mlp_eval(f, x, grad);
+  return mlp_eval_m(f, x, grad, margin);
 }
 
 int orc_label_world(const orc_field* f, const float xyz[3], int* tie, double* margin) {
@@ -715,7 +731,7 @@ static void jacobi3(double A[3][3], double V[3][3], double ev[3]) {
 /* argmin_x sum (n.(x - p))^2 = mass point + A^+_tau r; returns the vertex.
  * Sets *trunc_tie when an eigenvalue sits at the truncation threshold. */
 static void qef_solve(int n, const double* pl, double tau, double out[3], double* kappa,
-                      int* trunc_tie) {
+                      int* trunc_tie, double* gap) {
   double c[3] = {0, 0, 0};
   for (int i = 0; i < n; ++i)
     for (int a = 0; a < 3; ++a) c[a] += pl[6 * i + 3 + a];
@@ -734,6 +750,7 @@ static void qef_solve(int n, const double* pl, double tau, double out[3], double
     }
   }
   if (trunc_tie) *trunc_tie = 0;
+  if (gap) *gap = INFINITY;
   out[0] = c[0]; out[1] = c[1]; out[2] = c[2];
   if (used == 0) { if (kappa) *kappa = INFINITY; return; }
   double V[3][3], ev[3];
@@ -741,6 +758,17 @@ static void qef_solve(int n, const double* pl, double tau, double out[3], double
   double lmax = fmax(ev[0], fmax(ev[1], ev[2]));
   double lmin = fmin(ev[0], fmin(ev[1], ev[2]));
   if (kappa) *kappa = lmin > 0.0 ? lmax / lmin : INFINITY;
+  /* smallest distance between a kept and a dropped eigenvalue, relative to
+   * the largest: how well a decomposition's rounding separates the kept
+   * subspace (the solution's sensitivity to it grows as 1/gap) */
+  if (gap) {
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        int keep_i = ev[i] >= tau * lmax && ev[i] > 0.0;
+        int keep_j = ev[j] >= tau * lmax && ev[j] > 0.0;
+        if (keep_i && !keep_j) *gap = fmin(*gap, (ev[i] - ev[j]) / lmax);
+      }
+  }
   for (int k = 0; k < 3; ++k) {
     if (trunc_tie && fabs(ev[k] - tau * lmax) <= 1e-5 * lmax) *trunc_tie = 1;
     if (!(ev[k] >= tau * lmax) || ev[k] <= 0.0) continue;
@@ -750,7 +778,7 @@ static void qef_solve(int n, const double* pl, double tau, double out[3], double
 }
 
 void orc_qef_solve(int n, const double* planes, double tau, double out[3], double* kappa) {
-  qef_solve(n, planes, tau, out, kappa, NULL);
+  qef_solve(n, planes, tau, out, kappa, NULL, NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -875,7 +903,7 @@ static void ctx_pair_pf(const cell_ctx* cx, int64_t fid, int slot, double pf[2],
 
 /* Computes the partitions and vertices of cell c; returns the count. */
 static int cell_solve(const cell_ctx* cx, const int c[3], double* verts, int* partmap_out,
-                      int* flipmask_out, int* tie_out, double* kappa_out) {
+                      int* flipmask_out, int* tie_out, double* kappa_out, double* gap_out) {
   const orc_params* p = cx->p;
   int N = p->res;
   int cfg = cell_config(cx->f, p, cx->labels, c);
@@ -963,9 +991,10 @@ static int cell_solve(const cell_ctx* cx, const int c[3], double* verts, int* pa
       }
       ++n;
     }
-    double x[3], kap;
+    double x[3], kap, gp;
     int tt = 0;
-    qef_solve(n, planes, p->qef_tau, x, &kap, &tt);
+    qef_solve(n, planes, p->qef_tau, x, &kap, &tt, &gp);
+    if (gap_out) gap_out[part] = gp;
     tie |= tt;
     if (kap > kmax) kmax = kap;
     for (int a = 0; a < 3; ++a) verts[3 * part + a] = c[a] + x[a];
@@ -1010,7 +1039,7 @@ int orc_cell_vertices(const orc_field* f, const orc_params* p, int64_t cid, doub
   cx.p = p;
   int N = p->res;
   int c[3] = {(int)(cid % N), (int)((cid / N) % N), (int)(cid / ((int64_t)N * N))};
-  return cell_solve(&cx, c, verts, partmap, NULL, tie, kappa);
+  return cell_solve(&cx, c, verts, partmap, NULL, tie, kappa, NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1172,9 +1201,11 @@ int orc_mesh_extract(const orc_field* f, const orc_params* p, orc_mesh* m) {
     if (cidx[cid] >= 0) m->cell_id[cidx[cid]] = (int32_t)cid;
   double* cverts;
   double* ckap;
+  double* cgap;
   uint8_t* ctie;
   ALLOC(cverts, 12 * nc);
   ALLOC(ckap, 4 * nc);
+  ALLOC(cgap, 4 * nc);
   ALLOC(ctie, nc);
   int32_t* etie;
   ALLOC(etie, ne);
@@ -1195,7 +1226,7 @@ int orc_mesh_extract(const orc_field* f, const orc_params* p, orc_mesh* m) {
     int64_t cid = m->cell_id[x];
     int c[3] = {(int)(cid % N), (int)((cid / N) % N), (int)(cid / ((int64_t)N * N))};
     int pm, fm, tie = 0;
-    int npart = cell_solve(&cx, c, cverts + 12 * x, &pm, &fm, &tie, ckap + 4 * x);
+    int npart = cell_solve(&cx, c, cverts + 12 * x, &pm, &fm, &tie, ckap + 4 * x, cgap + 4 * x);
     m->cell_npart[x] = npart;
     m->cell_partmap[x] = pm;
     m->cell_flipmask[x] = fm;
@@ -1275,6 +1306,7 @@ int orc_mesh_extract(const orc_field* f, const orc_params* p, orc_mesh* m) {
   ALLOC(m->vert, 3 * m->n_vertices);
   ALLOC(m->vert_tie, m->n_vertices);
   ALLOC(m->vert_kappa, m->n_vertices);
+  ALLOC(m->vert_gap, m->n_vertices);
   ALLOC(m->tris, 3 * nt);
   for (int64_t x = 0; x < nc; ++x)
     for (int q = 0; q < m->cell_npart[x]; ++q) {
@@ -1282,6 +1314,7 @@ int orc_mesh_extract(const orc_field* f, const orc_params* p, orc_mesh* m) {
       for (int y = 0; y < 3; ++y) m->vert[3 * v + y] = cverts[12 * x + 3 * q + y];
       m->vert_tie[v] = m->cell_tie[x];
       m->vert_kappa[v] = ckap[4 * x + q];
+      m->vert_gap[v] = cgap[4 * x + q];
     }
   int64_t v3 = nv, tw = 0;
   for (int64_t x = 0; x < ne; ++x) {
@@ -1304,6 +1337,7 @@ int orc_mesh_extract(const orc_field* f, const orc_params* p, orc_mesh* m) {
       m->vert[3 * v3 + a] += m->edge_t[x];
       m->vert_tie[v3] = (uint8_t)(m->edge_tie_step[x] != 0);
       m->vert_kappa[v3] = 0.0;
+      m->vert_gap[v3] = INFINITY;
       for (int q = 0; q < 4; ++q) {
         T[3 * q] = (int32_t)v3;
         T[3 * q + 1] = Qd[q];
@@ -1316,6 +1350,7 @@ int orc_mesh_extract(const orc_field* f, const orc_params* p, orc_mesh* m) {
   free(quad);
   free(cverts);
   free(ckap);
+  free(cgap);
   free(ctie);
   free(etie);
   free(cidx);
@@ -1329,8 +1364,123 @@ void orc_mesh_free(orc_mesh* m) {
   void* ptrs[] = {m->corner_label, m->corner_tie, m->edge_id, m->edge_t, m->edge_tie_step,
                   m->pair_face, m->pair_info, m->pair_pf, m->pair_tie, m->pair_sin,
                   m->cell_id, m->cell_npart, m->cell_partmap, m->cell_flipmask, m->cell_vbase,
-                  m->cell_tie, m->vert, m->vert_tie, m->vert_kappa, m->edge_case,
+                  m->cell_tie, m->vert, m->vert_tie, m->vert_kappa, m->vert_gap, m->edge_case,
                   m->edge_case_tie, m->tris};
   for (size_t i = 0; i < sizeof(ptrs) / sizeof(ptrs[0]); ++i) free(ptrs[i]);
   memset(m, 0, sizeof(*m));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Self-intersections (a quality metric of Sec. 6): pairs of triangles that  */
+/* share no vertex and whose closed triangles intersect, by brute force over */
+/* all pairs.  Non-coplanar pairs: an edge of one meets the other triangle, */
+/* found by solving p + s (q - p) = A + u (B - A) + v (C - A) with Cramer's  */
+/* rule.  Coplanar pairs: no separating axis among the six edge normals in   */
+/* the common plane.                                                         */
+/* ------------------------------------------------------------------------ */
+
+static void sub3(const double a[3], const double b[3], double o[3]) {
+  for (int k = 0; k < 3; ++k) o[k] = a[k] - b[k];
+}
+static void cross3(const double a[3], const double b[3], double o[3]) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double dot3(const double a[3], const double b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+/* segment pq against triangle ABC, the triangle's plane not containing pq */
+static int segment_hits_triangle(const double p[3], const double q[3], const double A[3],
+                                 const double B[3], const double C[3]) {
+  double d[3], e1[3], e2[3], r[3];
+  sub3(q, p, d);
+  sub3(B, A, e1);
+  sub3(C, A, e2);
+  sub3(p, A, r);
+  /* [e1 e2 -d] (u v s)^T = r */
+  double md[3] = {-d[0], -d[1], -d[2]}, c12[3];
+  cross3(e1, e2, c12);
+  double det = dot3(c12, md);
+  if (det == 0.0) return 0; /* parallel to the plane */
+  double t1[3], t2[3], t3[3];
+  cross3(r, e2, t1);
+  cross3(e1, r, t2);
+  double u = dot3(t1, md) / det;
+  double v = dot3(t2, md) / det;
+  cross3(e1, e2, t3);
+  double s = dot3(t3, r) / det;
+  return s >= 0.0 && s <= 1.0 && u >= 0.0 && v >= 0.0 && u + v <= 1.0;
+}
+
+static int coplanar_overlap(const double P[3][3], const double Q[3][3], const double n[3]) {
+  /* separating-axis test: axes n x (edge) of both triangles */
+  for (int w = 0; w < 2; ++w) {
+    const double(*T)[3] = w == 0 ? P : Q;
+    for (int e = 0; e < 3; ++e) {
+      double ed[3], ax[3];
+      sub3(T[(e + 1) % 3], T[e], ed);
+      cross3(n, ed, ax);
+      double pmin = INFINITY, pmax = -INFINITY, qmin = INFINITY, qmax = -INFINITY;
+      for (int k = 0; k < 3; ++k) {
+        double a = dot3(ax, P[k]), b = dot3(ax, Q[k]);
+        pmin = fmin(pmin, a); pmax = fmax(pmax, a);
+        qmin = fmin(qmin, b); qmax = fmax(qmax, b);
+      }
+      if (pmax < qmin || qmax < pmin) return 0;
+    }
+  }
+  return 1;
+}
+
+static int triangles_intersect(const double P[3][3], const double Q[3][3]) {
+  double e1[3], e2[3], n[3];
+  sub3(P[1], P[0], e1);
+  sub3(P[2], P[0], e2);
+  cross3(e1, e2, n);
+  int coplanar = 1;
+  for (int k = 0; k < 3; ++k) {
+    double r[3];
+    sub3(Q[k], P[0], r);
+    if (dot3(n, r) != 0.0) coplanar = 0;
+  }
+  if (coplanar) return coplanar_overlap(P, Q, n);
+  for (int e = 0; e < 3; ++e) {
+    if (segment_hits_triangle(P[e], P[(e + 1) % 3], Q[0], Q[1], Q[2])) return 1;
+    if (segment_hits_triangle(Q[e], Q[(e + 1) % 3], P[0], P[1], P[2])) return 1;
+  }
+  return 0;
+}
+
+int64_t orc_self_intersections(const float* vertices, int64_t n_vertices, const int32_t* tris,
+                               int64_t n_tris) {
+  (void)n_vertices;
+  int64_t count = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : count)
+  for (int64_t a = 0; a < n_tris; ++a) {
+    double P[3][3], lo[3], hi[3];
+    for (int k = 0; k < 3; ++k)
+      for (int c = 0; c < 3; ++c) P[k][c] = vertices[3 * (int64_t)tris[3 * a + k] + c];
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = fmin(P[0][c], fmin(P[1][c], P[2][c]));
+      hi[c] = fmax(P[0][c], fmax(P[1][c], P[2][c]));
+    }
+    for (int64_t b = a + 1; b < n_tris; ++b) {
+      int shared = 0;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) shared |= tris[3 * a + i] == tris[3 * b + j];
+      if (shared) continue;
+      double Q[3][3];
+      int apart = 0;
+      for (int k = 0; k < 3; ++k)
+        for (int c = 0; c < 3; ++c) Q[k][c] = vertices[3 * (int64_t)tris[3 * b + k] + c];
+      for (int c = 0; c < 3; ++c) {
+        double ql = fmin(Q[0][c], fmin(Q[1][c], Q[2][c])), qh = fmax(Q[0][c], fmax(Q[1][c], Q[2][c]));
+        if (qh < lo[c] || ql > hi[c]) apart = 1;
+      }
+      if (!apart && triangles_intersect(P, Q)) ++count;
+    }
+  }
+  return count;
 }

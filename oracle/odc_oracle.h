@@ -113,6 +113,7 @@ typedef struct {
   double* vert;             /* grid units */
   uint8_t* vert_tie;
   double* vert_kappa;       /* largest/smallest eigenvalue of the normal matrix */
+  double* vert_gap;         /* smallest (kept - dropped) eigenvalue gap / largest; inf if none dropped */
   /* emission, one entry per crossing edge */
   int32_t* edge_case;       /* 0 = no quad (grid boundary), 1, 2, 3 */
   uint8_t* edge_case_tie;
@@ -142,8 +143,10 @@ int orc_cell_vertices(const orc_field* f, const orc_params* p, int64_t cell_id,
 
 /* Building blocks exposed for pinning tests. */
 /* Logit z and its gradient dz/dx at a binary64 point of an MLP field (NAN
- * for other fields). */
-double orc_logit_grad(const orc_field* f, const double x[3], double grad[3]);
+ * for other fields).  margin (may be NULL) receives the distance to a switch
+ * of the gradient's formula: [0] the gap between the two nearest spheres'
+ * distances, [1] the smallest |pre-activation| of any ReLU. */
+double orc_logit_grad(const orc_field* f, const double x[3], double grad[3], double margin[2]);
 /* Line-binary search along a face-local ray on face `face_id` (FP32 ray
  * geometry as in the search).  Returns the near parameter s; q receives the point. */
 float orc_line_binary(const orc_field* f, const orc_params* p, int64_t face_id,
@@ -155,6 +158,10 @@ float orc_line_binary(const orc_field* f, const orc_params* p, int64_t face_id,
 int orc_cube_partitions(int config, int flipmask, int* partmap);
 /* Truncated pseudo-inverse QEF: n planes (normal, point) in rows of 6. */
 void orc_qef_solve(int n, const double* planes, double tau, double out[3], double* kappa);
+/* Self-intersections: the number of pairs of triangles sharing no vertex
+ * whose closed triangles intersect (brute force over all pairs). */
+int64_t orc_self_intersections(const float* vertices, int64_t n_vertices, const int32_t* tris,
+                               int64_t n_tris);
 /* Intersection-free split of an oriented quad; returns case 1..3. */
 int orc_ic_case(const double q[4][3], const double pin[3], const double pout[3],
                 double tol, int* tie);

@@ -58,6 +58,7 @@ _MESH_FIELDS = [
     ("cell_vbase", _P(C.c_int32)), ("cell_tie", _P(C.c_uint8)),
     ("n_vertices", C.c_int64), ("vert", _P(C.c_double)), ("vert_tie", _P(C.c_uint8)),
     ("vert_kappa", _P(C.c_double)),
+    ("vert_gap", _P(C.c_double)),
     ("edge_case", _P(C.c_int32)), ("edge_case_tie", _P(C.c_uint8)),
     ("n_case3", C.c_int64), ("n_tris", C.c_int64), ("tris", _P(C.c_int32)),
 ]
@@ -95,8 +96,10 @@ def lib():
                                       _P(C.c_float), C.c_int, C.c_float, C.c_int, C.c_int,
                                       _P(C.c_float), _P(C.c_int)]
         L.orc_line_binary.restype = C.c_float
-        L.orc_logit_grad.argtypes = [_P(_Field), _P(C.c_double), _P(C.c_double)]
+        L.orc_logit_grad.argtypes = [_P(_Field), _P(C.c_double), _P(C.c_double), _P(C.c_double)]
         L.orc_logit_grad.restype = C.c_double
+        L.orc_self_intersections.argtypes = [_P(C.c_float), C.c_int64, _P(C.c_int32), C.c_int64]
+        L.orc_self_intersections.restype = C.c_int64
         L.orc_cube_partitions.argtypes = [C.c_int, C.c_int, _P(C.c_int)]
         L.orc_cube_partitions.restype = C.c_int
         L.orc_qef_solve.argtypes = [C.c_int, _P(C.c_double), C.c_double, _P(C.c_double),
@@ -160,6 +163,7 @@ class Oracle:
             out["vert"] = grab("vert", m.n_vertices, 3)
             out["vert_tie"] = grab("vert_tie", m.n_vertices)
             out["vert_kappa"] = grab("vert_kappa", m.n_vertices)
+            out["vert_gap"] = grab("vert_gap", m.n_vertices)
             out["tris"] = grab("tris", m.n_tris, 3)
         finally:
             lib().orc_mesh_free(C.byref(m))
@@ -200,11 +204,15 @@ class Oracle:
                                     C.byref(pm), C.byref(tie), kap)
         return n, np.array(v[:3 * n]).reshape(n, 3), pm.value, tie.value
 
-    def logit_grad(self, x):
-        """Binary64 logit and gradient at a binary64 point (MLP fields)."""
+    def logit_grad(self, x, with_margin=False):
+        """Binary64 logit and gradient at a binary64 point (MLP fields); with
+        with_margin also (nearest-sphere gap, smallest |ReLU input|)."""
         xd = (C.c_double * 3)(*[float(v) for v in x])
         g = (C.c_double * 3)()
-        z = lib().orc_logit_grad(C.byref(self.f), xd, g)
+        mg = (C.c_double * 2)()
+        z = lib().orc_logit_grad(C.byref(self.f), xd, g, mg)
+        if with_margin:
+            return z, np.array(g[:]), (mg[0], mg[1])
         return z, np.array(g[:])
 
     def line_binary(self, fid, p0, d, s0, rng, n_lin, n_bin):
@@ -244,3 +252,11 @@ def ic_case(quad, pin, pout, tol=0.0):
     c = lib().orc_ic_case(q.ctypes.data_as(_P(C.c_double)), a.ctypes.data_as(_P(C.c_double)),
                           b.ctypes.data_as(_P(C.c_double)), tol, C.byref(tie))
     return c, tie.value
+
+
+def self_intersections(vertices, tris) -> int:
+    """Pairs of vertex-disjoint triangles that intersect (brute force)."""
+    v = np.ascontiguousarray(vertices, np.float32)
+    t = np.ascontiguousarray(tris, np.int32)
+    return int(lib().orc_self_intersections(v.ctypes.data_as(_P(C.c_float)), len(v),
+                                            t.ctypes.data_as(_P(C.c_int32)), len(t)))

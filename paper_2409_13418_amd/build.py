@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libodc.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("odc_kernels.hip", "odc_api.hip", "odc_server.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f)
+           for f in ("odc_kernels.hip", "odc_api.hip", "odc_server.hip", "odc_quality.hip")]
 HEADERS = [os.path.join(HERE, "csrc", f) for f in ("odc_device.h", "odc_mlp.h", "odc_job.h", "odc_internal.h",
                                                        "odc_context.h")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

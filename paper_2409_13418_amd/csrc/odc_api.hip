@@ -209,6 +209,10 @@ int32_t odc::validate_job(odc_context* ctx, const odc_field* f, const odc_params
     return fail(ctx, ODC_ERR_INVALID_ARG, "qef_tau outside [0,1)");
   if (p->precision != ODC_PREC_FP32 && p->precision != ODC_PREC_BF16_GUARDED)
     return fail(ctx, ODC_ERR_INVALID_ARG, "unknown precision %d", p->precision);
+  if (p->ablation & ~(ODC_ABL_LINEAR_1D | ODC_ABL_GRAD_NORMALS | ODC_ABL_MDC_SPLIT))
+    return fail(ctx, ODC_ERR_INVALID_ARG, "unknown ablation bits 0x%x", p->ablation);
+  if ((p->ablation & ODC_ABL_GRAD_NORMALS) && f->kind != ODC_FIELD_MLP)
+    return fail(ctx, ODC_ERR_UNSUPPORTED, "gradient normals need an MLP field");
   if ((o->cap_vertices > 0 && !o->vertices) || (o->cap_triangles > 0 && !o->triangles) ||
       o->cap_vertices < 0 || o->cap_triangles < 0)
     return fail(ctx, ODC_ERR_INVALID_ARG, "NULL output buffer with non-zero capacity");
@@ -266,6 +270,7 @@ void job_scalars(Job& J, const odc_field* f, const odc_params* p, int ce) {
   J.qef_tau = p->qef_tau;
   J.guard_logit = p->guard_logit;
   J.fp64_cond = p->fp64_cond;
+  J.ablation = p->ablation;
   J.nw_c = (J.g.nc + 31) / 32;
   J.nw_e = (3 * J.g.ea + 31) / 32;
   J.nw_f = (3 * J.g.fa + 31) / 32;
@@ -278,7 +283,7 @@ void job_scalars(Job& J, const odc_field* f, const odc_params* p, int ce) {
 // Byte sizes of a job's scratch regions (each a multiple of 256).
 struct Layout {
   size_t grid[13];
-  size_t active[16];
+  size_t active[17];
   size_t grid_total = 0, active_total = 0;
   size_t mlpw = 0, guard = 0, status = 0;
   int guard_cap = 0;
@@ -313,6 +318,8 @@ Layout job_layout(const Job& J, const odc_field* f, bool guard_full) {
     L.active[i] = asz[i];
     L.active_total += asz[i];
   }
+  L.active[16] = (J.ablation & kAblGradNormals) ? align_up(ne * 3 * sizeof(float)) : 0;
+  L.active_total += L.active[16];
   L.status = align_up(4 * sizeof(unsigned long long));
   if (f->kind == ODC_FIELD_MLP) {
     const int kb1f = kb1_fp32(f->in_dim), kb1b = kb1_bf16(f->in_dim), d = f->depth;
@@ -343,16 +350,17 @@ void job_bind(Job& J, const Layout& L, const odc_field* f, char* grid, char* act
     *gp[i] = (uint32_t*)(grid + off);
     off += L.grid[i];
   }
-  void** ap[16] = {(void**)&J.elist,    (void**)&J.et,    (void**)&J.ecase, (void**)&J.ntri,
+  void** ap[17] = {(void**)&J.elist,    (void**)&J.et,    (void**)&J.ecase, (void**)&J.ntri,
                    (void**)&J.n3,       (void**)&J.tprefix, (void**)&J.c3prefix,
                    (void**)&J.quad,     (void**)&J.plist, (void**)&J.pf,    (void**)&J.clist,
                    (void**)&J.cpm,      (void**)&J.cnf,   (void**)&J.npart, (void**)&J.vbase,
-                   (void**)&J.vloc};
+                   (void**)&J.vloc,     (void**)&J.egrad};
   off = 0;
-  for (int i = 0; i < 16; ++i) {
+  for (int i = 0; i < 17; ++i) {
     *ap[i] = active + off;
     off += L.active[i];
   }
+  if (!(J.ablation & kAblGradNormals)) J.egrad = nullptr;
   J.status = (unsigned long long*)status;
   if (f->kind == ODC_FIELD_MLP) {
     const int d = f->depth;
@@ -451,6 +459,7 @@ static PipelineShape shape_of(odc_context* ctx, int n) {
       sh.any_mlp = true;
       if (J.precision == 0) sh.any_mlp_fp32 = true;
       else sh.any_mlp_bf16 = true;
+      if (J.ablation & kAblGradNormals) sh.any_grad = true;
     }
   }
   return sh;
@@ -458,7 +467,7 @@ static PipelineShape shape_of(odc_context* ctx, int n) {
 
 static bool same_shape(const PipelineShape& a, const PipelineShape& b) {
   return a.any_csg == b.any_csg && a.any_mlp == b.any_mlp && a.any_mlp_fp32 == b.any_mlp_fp32 &&
-         a.any_mlp_bf16 == b.any_mlp_bf16;
+         a.any_mlp_bf16 == b.any_mlp_bf16 && a.any_grad == b.any_grad;
 }
 static bool same_cfg(const LaunchCfg& a, const LaunchCfg& b) {
   return a.grid_blocks == b.grid_blocks && a.elem_blocks == b.elem_blocks &&
@@ -656,6 +665,11 @@ extern "C" int32_t odc_get_intermediate(odc_context* ctx, int32_t which, void* d
     case 7: src = J.cnf; count = (int64_t)o[2]; break;
     case 8: src = J.vbase; count = (int64_t)o[2]; break;
     case 9: src = J.ecase; count = (int64_t)o[0]; break;
+    case 10:
+      src = J.egrad;
+      count = J.egrad ? (int64_t)o[0] : 0;
+      elem = 12;
+      break;
     default: return fail(ctx, ODC_ERR_INVALID_ARG, "unknown intermediate %d", which);
   }
   *n = count;

@@ -23,6 +23,7 @@ struct LaunchCfg {
 // Which kernels a launch needs.
 struct PipelineShape {
   bool any_csg = false, any_mlp = false, any_mlp_fp32 = false, any_mlp_bf16 = false;
+  bool any_grad = false;  // some job takes gradient normals
 };
 
 // The whole path for njobs jobs in device memory; ev (9 events, or NULL)

@@ -20,6 +20,9 @@
 
 namespace odc {
 
+// ablation bits of a job (the public ODC_ABL_* values)
+constexpr int kAblLinear1D = 1, kAblGradNormals = 2, kAblMdcSplit = 4;
+
 struct Job {
   Grid g;
   int kind;       // 0 CSG, 1 MLP
@@ -30,6 +33,7 @@ struct Job {
   int iters_1d, lin1, bin1, lin2, bin2;
   float range1, range2, qef_tau, guard_logit;
   double fp64_cond;
+  int ablation;   // ODC_ABL_* bits (0 = the method)
 
   int nw_c, nw_e, nw_f, nw_cell;       // words of the corner / edge / face / cell bit sets
   int cap_edges, cap_pairs, cap_cells;  // active-set scratch capacities
@@ -66,6 +70,7 @@ struct Job {
   uint32_t* npart;
   uint32_t* vbase;
   float* vloc;
+  float* egrad;  // dz/dx at each crossing edge's 1D point (gradient-normal ablation)
 
   // outputs (caller memory)
   float* out_v;

@@ -599,9 +599,31 @@ __global__ __launch_bounds__(256) void k_bisect_csg(const Job* __restrict__ jobs
   for_units(jobs, njobs, gthread(), nthreads(),
             [](const Job& J) { return J.kind == 0 ? n_edges_of(J) : 0; },
             [&](const Job& J, int x) {
+              if (J.ablation & kAblLinear1D) {
+                // Eq. 1 on binary occupancy: psi = +-1/2 at the two ends
+                J.et[x] = 0.5f;
+                return;
+              }
               CsgLabel lab{&J.g, J.prims, J.n_prims};
               J.et[x] = bisect_edge(J, lab, J.elist[x]);
             });
+}
+
+// Eq. 1 (the linear-1D ablation): psi = phi - 1/2 = tanh(z/2)/2 at the two
+// corners of the edge, t = psi0 / (psi0 - psi1), binary32.
+__device__ __forceinline__ float linear_edge_mlp(const Job& J, int e, float* act) {
+  int a, p[3];
+  edge_pos(J.g, e, a, p);
+  float psi[2];
+#pragma unroll 1
+  for (int end = 0; end < 2; ++end) {
+    const float gp[3] = {(float)p[0], (float)p[1], (float)p[2]};
+    float x[3];
+    grid_world(J.g, gp, x);
+    psi[end] = 0.5f * tanhf(0.5f * mlp_logit_fp32(J.mlp, x, act));
+    add_at3(p, a, 1);
+  }
+  return psi[0] / (psi[0] - psi[1]);
 }
 
 __global__ __launch_bounds__(256) void k_bisect_mlp(const Job* __restrict__ jobs, int njobs) {
@@ -614,9 +636,44 @@ __global__ __launch_bounds__(256) void k_bisect_mlp(const Job* __restrict__ jobs
               const int lane = lane_id();
               const int x = t * 32 + (lane & 31);
               const bool valid = x < ne;
-              MlpLabel lab{&J.g, &J.mlp, act};
-              const float tt = bisect_edge(J, lab, J.elist[valid ? x : ne - 1]);
+              const int e = J.elist[valid ? x : ne - 1];
+              float tt;
+              if (J.ablation & kAblLinear1D) {
+                tt = linear_edge_mlp(J, e, act);
+              } else {
+                MlpLabel lab{&J.g, &J.mlp, act};
+                tt = bisect_edge(J, lab, e);
+              }
               if (valid && lane < 32) J.et[x] = tt;
+            });
+}
+
+// Gradient of the logit at each crossing edge's 1D point (the gradient-normal
+// ablation, Eq. 2), by forward-mode differentiation on the matrix cores:
+// 8 edges per wavefront pass, 4 channels each (value and 3 derivatives).
+__global__ __launch_bounds__(256) void k_grad_mlp(const Job* __restrict__ jobs, int njobs) {
+  __shared__ __align__(16) float act_lds[kBlock / 64][kActWords];
+  float* act = act_lds[threadIdx.x >> 6];
+  for_units(jobs, njobs, gwave(), nwaves(),
+            [](const Job& J) {
+              return (J.kind == 1 && (J.ablation & kAblGradNormals)) ? (n_edges_of(J) + 7) >> 3
+                                                                      : 0;
+            },
+            [&](const Job& J, int t) {
+              const int ne = n_edges_of(J);
+              const int lane = lane_id();
+              const int q = (lane & 31) >> 2, ch = lane & 3;
+              const int x = t * 8 + q;
+              const bool valid = x < ne;
+              const int xi = valid ? x : ne - 1;
+              int a, p[3];
+              edge_pos(J.g, J.elist[xi], a, p);
+              float gp[3] = {(float)p[0], (float)p[1], (float)p[2]};
+              set_at3(gp, a, (float)at3(p, a) + J.et[xi]);
+              float w[3];
+              grid_world(J.g, gp, w);
+              const float v = mlp_logit_fp32<true>(J.mlp, w, act);
+              if (valid && lane < 32 && ch != 0) J.egrad[3 * x + ch - 1] = v;
             });
 }
 
@@ -814,7 +871,10 @@ __global__ __launch_bounds__(256) void k_search2d_mlp(const Job* __restrict__ jo
   __shared__ __align__(16) float act_lds[kBlock / 64][kActWords];
   float* act = act_lds[threadIdx.x >> 6];
   for_units(jobs, njobs, gwave(), nwaves(),
-            [](const Job& J) { return J.kind == 1 ? (n_pairs_of(J) + 31) >> 5 : 0; },
+            [](const Job& J) {
+              return (J.kind == 1 && !(J.ablation & kAblGradNormals)) ? (n_pairs_of(J) + 31) >> 5
+                                                                       : 0;
+            },
             [&](const Job& J, int t) {
               const int np = n_pairs_of(J);
               const int lane = lane_id();
@@ -990,6 +1050,32 @@ __device__ __forceinline__ bool edge_plane(const Job& j, const int c[3], int fm,
 // false when T is float and the normal matrix's condition number exceeds
 // fp64_cond (including a singular matrix); the caller then redoes the
 // decomposition in binary64.
+// The gradient-normal ablation's plane at crossing edge le of cell c: the
+// 1D point and the normalised logit gradient there (binary64 from the
+// binary32 gradient).  Returns false for a zero gradient.
+__device__ __forceinline__ bool edge_grad_plane(const Job& j, const int c[3], int le, double pe[3],
+                                                double n[3]) {
+  const int ax = le >> 2;
+  int b1, b2;
+  other_axes(ax, b1, b2);
+  int off[3] = {0, 0, 0};
+  off[b1] = le & 1;
+  off[b2] = (le >> 1) & 1;
+  const int gid = edge_index(j.g, ax, c[0] + off[0], c[1] + off[1], c[2] + off[2]);
+  const int es = edge_slot(j, gid);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    pe[k] = (double)off[k];
+    n[k] = (double)j.egrad[3 * es + k];
+  }
+  pe[ax] = (double)j.et[es];
+  const double nl = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  if (!(nl > 0.0)) return false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) n[k] /= nl;
+  return true;
+}
+
 template <typename T>
 __device__ bool qef_partition(const Job& j, const int c[3], int cfg, int fm, uint32_t pm,
                               int part, double x[3]) {
@@ -1023,7 +1109,11 @@ __device__ bool qef_partition(const Job& j, const int c[3], int cfg, int fm, uin
   for (int le = 0; le < 12; ++le) {
     if (!cube_edge_crosses(cfg, le) || (int)((pm >> (2 * le)) & 3u) != part) continue;
     double pe[3], n[3];
-    if (!edge_plane(j, c, fm, le, pe, n)) continue;
+    if (j.ablation & kAblGradNormals) {
+      if (!edge_grad_plane(j, c, le, pe, n)) continue;
+    } else if (!edge_plane(j, c, fm, le, pe, n)) {
+      continue;
+    }
     const double dd = n[0] * (pe[0] - cm[0]) + n[1] * (pe[1] - cm[1]) + n[2] * (pe[2] - cm[2]);
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -1169,7 +1259,7 @@ __global__ __launch_bounds__(256) void k_emit_count(const Job* __restrict__ jobs
                 concave[k] = (triple3(u0, u1, u2) < 0.0f) || (triple3(w0, w1, w2) > 0.0f);
               }
               int cs = 3;
-              if (!concave[1] && !concave[3]) cs = 1;
+              if ((J.ablation & kAblMdcSplit) || (!concave[1] && !concave[3])) cs = 1;
               else if (!concave[0] && !concave[2]) cs = 2;
               J.ecase[x] = (uint32_t)cs;
               J.quad[x] = qd;
@@ -1264,6 +1354,7 @@ hipError_t launch_pipeline(const Job* d, int njobs, const PipelineShape& sh,
   mark(4);
   if (sh.any_csg) k_search2d_csg<<<cfg.elem_blocks, kBlock, 0, s>>>(d, njobs);
   if (sh.any_mlp) k_search2d_mlp<<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
+  if (sh.any_grad) k_grad_mlp<<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
   mark(5);
   k_cell_count<<<cfg.elem_blocks, kBlock, 0, s>>>(d, njobs, table);
   scan<3>(d, njobs, cfg, s);

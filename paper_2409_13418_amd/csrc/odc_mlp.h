@@ -152,6 +152,43 @@ __device__ __forceinline__ float pair_feature_fast(int p, float quarter_h, int h
   return __builtin_amdgcn_sinf(pair_phase(p, x) + quarter_h);
 }
 
+// Forward-mode differentiation (the gradient-normal ablation): lane l's
+// column l%32 is channel ch = l%4 of query (l%32)/4; channel 0 carries the
+// value, channel 1 + d the derivative along x_d.  Member h of pair p in
+// channel ch:
+__device__ __forceinline__ float pair_tangent(int p, int h, int ch, const float x[3]) {
+  const int d = ch - 1;
+  if (p == 0) return ch == 0 ? (h ? x[1] : x[0]) : ((h ? d == 1 : d == 0) ? 1.0f : 0.0f);
+  if (p == 1) return ch == 0 ? (h ? 0.0f : x[2]) : ((!h && d == 2) ? 1.0f : 0.0f);
+  const int q = p - 2, j = q / 3, a = q % 3;
+  const float r = pair_phase(p, x);
+  const float sn = __builtin_amdgcn_sinf(r), cs = __builtin_amdgcn_cosf(r);
+  // d/dx_a sin(pi 2^j x_a) = pi 2^j cos(pi 2^j x_a); the cosine's is -pi 2^j sin
+  const float w = (float)(3.14159265358979323846 * (double)(1 << j));
+  if (ch == 0) return h ? cs : sn;
+  return d == a ? (h ? -w * sn : w * cs) : 0.0f;
+}
+
+// The value of lane 4k of this lane's quad (DPP quad permutation 0,0,0,0).
+__device__ __forceinline__ float quad_lead(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x00, 0xF, 0xF, false));
+}
+
+// B operand of a hidden layer from a parked pre-activation a and its bias b:
+// relu(a + b) for values; for derivative channels a where the value's
+// pre-activation is positive (the ReLU's derivative, 0 at 0), else 0.
+template <bool kTan>
+__device__ __forceinline__ float relu_operand(float a, float b, int ch) {
+  const float s = a + b;
+  if constexpr (!kTan) {
+    return fmaxf(s, 0.0f);
+  } else {
+    const float lead = quad_lead(s);
+    return ch == 0 ? fmaxf(s, 0.0f) : (lead > 0.0f ? a : 0.0f);
+  }
+}
+
 // |x - c| - r of one sphere (c, r): squared distance by fused multiply-adds,
 // hardware square root (within 1 ulp).
 __device__ __forceinline__ float sphere_term(float cx, float cy, float cz, float r,
@@ -162,9 +199,32 @@ __device__ __forceinline__ float sphere_term(float cx, float cy, float cz, float
 }
 
 // z = out_scale * y - sdf_gain * sdf, from the two half-wave partial sums
+template <bool kTan = false>
 __device__ __forceinline__ float mlp_finish(const Mlp& M, float part, const float x[3]) {
   const float other = __shfl_xor(part, 32);
   const float y0 = (lane_id() < 32) ? (part + other) : (other + part);
+  if constexpr (kTan) {
+    // derivative channels: out_scale dy/dx_d - sdf_gain (x_d - c_d)/|x - c|
+    // through the nearest sphere (the first in index order on a tie)
+    const ODC_CONST float* sp = cmem(M.spheres);
+    float sdf = INFINITY, near[3] = {0.0f, 0.0f, 0.0f}, dist = 1.0f;
+    for (int s = 0; s < M.n_spheres; ++s) {
+      const float dx = x[0] - sp[4 * s], dy = x[1] - sp[4 * s + 1], dz = x[2] - sp[4 * s + 2];
+      const float r = __builtin_amdgcn_sqrtf(__builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx)));
+      const float dd = r - sp[4 * s + 3];
+      if (dd < sdf) {
+        sdf = dd;
+        near[0] = dx;
+        near[1] = dy;
+        near[2] = dz;
+        dist = r;
+      }
+    }
+    const int ch = lane_id() & 3;
+    if (ch == 0) return M.out_scale * (y0 + *cmem(M.bout)) - M.sdf_gain * sdf;
+    const float nd = ch == 1 ? near[0] : (ch == 2 ? near[1] : near[2]);
+    return M.out_scale * y0 - (dist > 0.0f ? M.sdf_gain * (nd / dist) : 0.0f);
+  }
   const float y = y0 + *cmem(M.bout);
   // spheres four at a time (one 16-dword scalar load each, issued one group
   // ahead of its use), then the rest
@@ -212,8 +272,10 @@ constexpr int kGroupsF32 = kHiddenBlocksF32 / 4;  // 32 groups of 4 K blocks
 // Output layer of either path from the last layer's pre-activations in the
 // accumulators: y = sum_n wout[n] relu(pre_n + bias_n), lane half h taking
 // neurons 8G + 4h + d in the order (G, d), then the sdf term.
+template <bool kTan = false>
 __device__ __forceinline__ float mlp_output(const Mlp& M, const v16f (&acc)[8], int h, int zero,
                                             const float x[3]) {
+  const int ch = lane_id() & 3;
   const ODC_GLOBAL v4f* Bl = (const ODC_GLOBAL v4f*)gmem(M.bias) + (size_t)(M.depth - 1) * 64 + h + zero;
   const ODC_GLOBAL v4f* Wo = (const ODC_GLOBAL v4f*)gmem(M.wout) + h + zero;
   float part = 0.0f;
@@ -230,12 +292,12 @@ __device__ __forceinline__ float mlp_output(const Mlp& M, const v16f (&acc)[8], 
       const int G = G0 + u, T = G >> 2, g = G & 3;
 #pragma unroll
       for (int d = 0; d < 4; ++d) {
-        const float a = fmaxf(acc[T][4 * g + d] + bb[u][d], 0.0f);
+        const float a = relu_operand<kTan>(acc[T][4 * g + d], bb[u][d], ch);
         part = __builtin_fmaf(wo[u][d], a, part);
       }
     }
   }
-  return mlp_finish(M, part, x);
+  return mlp_finish<kTan>(M, part, x);
 }
 
 // Weight fragments stream through a ring of kPrefetchF32 K blocks held in
@@ -251,10 +313,16 @@ __device__ __forceinline__ float mlp_output(const Mlp& M, const v16f (&acc)[8], 
 constexpr int kPrefetchF32 = 4;
 static_assert(kPrefetchF32 == 4, "one ring turn per group of four K blocks");
 
+//
+// kTan: forward-mode differentiation instead (8 queries of 4 channels each,
+// see pair_tangent); lane l returns channel l%4 of query (l%32)/4: the logit,
+// then dz/dx, dz/dy, dz/dz.
+template <bool kTan = false>
 __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
                                                 float* __restrict__ act) {
   const int lane = lane_id();
   const int h = lane >> 5;
+  const int ch = lane & 3;
   // The offset is an opaque zero so that the ring's first loads stay here:
   // hoisted out of a caller's query loop they would pin 32 registers for its
   // whole length.
@@ -287,7 +355,8 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
   // Each block's B operand is formed while the previous block's matrix
   // instructions run (no VALU-to-MFMA dependency at the block boundary).
   const int ng = M.kb1f / kPrefetchF32;
-  float bv = pair_feature(0, h, x);
+  auto feature = [&](int p) { return kTan ? pair_tangent(p, h, ch, x) : pair_feature(p, h, x); };
+  float bv = feature(0);
 #pragma unroll
   for (int gi = 0; gi < kMaxGroups1F32; ++gi) {
     if (gi == 0 || gi < ng) {
@@ -298,7 +367,7 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
         for (int R = 0; R < 8; ++R)
           acc[R] = __builtin_amdgcn_mfma_f32_32x32x2f32(wr[d][R >> 2][R & 3], bv,
                                                         b == 0 ? zacc : acc[R], 0, 0, 0);
-        bv = pair_feature(b + 1, h, x);
+        bv = feature(b + 1);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int q = 0; q < 2; ++q) wr[d][q] = S((b + kPrefetchF32) * 2 + q);
@@ -318,7 +387,7 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
     const int wn = (M.kb1f + (l - 1) * kHiddenBlocksF32 + kPrefetchF32) * 2;
     const ODC_GLOBAL v4f* Bn = Bv + (size_t)(l - 1) * 64;
     v4f an = act4[lane];
-    bv = fmaxf(an[0] + bq[0][0], 0.0f);
+    bv = relu_operand<kTan>(an[0], bq[0][0], ch);
     // fully unrolled: a loop back-edge here makes the wait-count insertion
     // drain every load in flight at the top of each trip
 #pragma unroll
@@ -333,8 +402,8 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
           acc[R] = __builtin_amdgcn_mfma_f32_32x32x2f32(wr[d][R >> 2][R & 3], bv,
                                                         b == 0 ? zacc : acc[R], 0, 0, 0);
         // the next block's operand (after the last group: unused)
-        bv = d < 3 ? fmaxf(a[d + 1] + bq[G & 1][d + 1], 0.0f)
-                   : fmaxf(an[0] + bq[(G + 1) & 1][0], 0.0f);
+        bv = d < 3 ? relu_operand<kTan>(a[d + 1], bq[G & 1][d + 1], ch)
+                   : relu_operand<kTan>(an[0], bq[(G + 1) & 1][0], ch);
         // refill the slot just consumed (same registers: no copies); the
         // first block's refill also fetches the next group's bias (after the
         // last group: group 0 of the next layer, or of the output layer)
@@ -346,7 +415,7 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
       }
     }
   }
-  return mlp_output(M, acc, h, zero, x);
+  return mlp_output<kTan>(M, acc, h, zero, x);
 }
 
 // bf16 operands, fp32 accumulation (all 64 lanes must be active).  `act`

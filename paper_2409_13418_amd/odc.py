@@ -21,7 +21,8 @@ PREC_FP32, PREC_BF16_GUARDED = 0, 1
 INTERMEDIATES = {"labels": (0, np.uint32), "edge_ids": (1, np.int32), "edge_t": (2, np.float32),
                  "pairs": (3, np.int32), "pair_pf": (4, np.float64), "cell_ids": (5, np.int32),
                  "cell_partmap": (6, np.uint32), "cell_nf": (7, np.uint32),
-                 "vertex_base": (8, np.int32), "edge_case": (9, np.int32)}
+                 "vertex_base": (8, np.int32), "edge_case": (9, np.int32),
+                 "edge_grad": (10, np.float32)}
 
 
 class OdcError(RuntimeError):
@@ -42,7 +43,7 @@ class Params(C.Structure):
                 ("iters_1d", C.c_int32), ("lin1", C.c_int32), ("bin1", C.c_int32),
                 ("lin2", C.c_int32), ("bin2", C.c_int32), ("range1", C.c_float),
                 ("range2", C.c_float), ("qef_tau", C.c_float), ("fp64_cond", C.c_double),
-                ("precision", C.c_int32), ("guard_logit", C.c_float)]
+                ("precision", C.c_int32), ("guard_logit", C.c_float), ("ablation", C.c_int32)]
 
 
 class MeshBuffers(C.Structure):
@@ -61,6 +62,7 @@ class MeshCounts(C.Structure):
 
 
 SERVE_FIFO, SERVE_SHORTEST = 0, 1
+ABL_LINEAR_1D, ABL_GRAD_NORMALS, ABL_MDC_SPLIT = 1, 2, 4
 
 
 class ServerConfig(C.Structure):
@@ -91,7 +93,7 @@ EXPORTS = ("odc_status_string", "odc_last_error", "odc_context_create", "odc_con
            "odc_autotune", "odc_set_launch_config", "odc_server_create", "odc_server_destroy",
            "odc_server_last_error", "odc_server_footprint", "odc_server_submit",
            "odc_server_poll", "odc_server_wait", "odc_server_get_stats",
-           "odc_server_reset_stats")
+           "odc_server_reset_stats", "odc_count_self_intersections")
 STAGES = ("labels", "classify", "compact", "bisect", "search2d", "cell_count", "cell_qef", "emit")
 
 _lib = None
@@ -166,6 +168,9 @@ def load(path: str = LIB_PATH):
     L.odc_server_get_stats.restype = C.c_int32
     L.odc_server_reset_stats.argtypes = [C.c_void_p]
     L.odc_server_reset_stats.restype = C.c_int32
+    L.odc_count_self_intersections.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                               C.c_int64, C.c_double, C.POINTER(C.c_int64)]
+    L.odc_count_self_intersections.restype = C.c_int32
     _lib = L
     return L
 
@@ -183,6 +188,7 @@ def default_params(grid, precision: int = PREC_FP32) -> Params:
     p.qef_tau = float(grid.qef_tau)
     p.precision = int(precision)
     p.guard_logit = float(2.0 * math.atanh(0.02))
+    p.ablation = int(getattr(grid, "ablation", 0))
     return p
 
 
@@ -327,6 +333,21 @@ class Context:
         self._check(rc, "odc_field_eval")
         return z.cpu().numpy()
 
+    def self_intersections(self, vertices, triangles, cell: float) -> int:
+        """Pairs of vertex-disjoint triangles that intersect (device tensors or
+        host arrays; counted on this context's GPU)."""
+        torch = self.torch
+        v = torch.as_tensor(np.asarray(vertices, np.float32) if not torch.is_tensor(vertices)
+                            else vertices, device=self.device).float().contiguous()
+        t = torch.as_tensor(np.asarray(triangles, np.int32) if not torch.is_tensor(triangles)
+                            else triangles, device=self.device).int().contiguous()
+        n = C.c_int64()
+        rc = load().odc_count_self_intersections(self.h, C.c_void_p(v.data_ptr()), v.numel() // 3,
+                                                 C.c_void_p(t.data_ptr()), t.numel() // 3,
+                                                 float(cell), C.byref(n))
+        self._check(rc, "odc_count_self_intersections")
+        return int(n.value)
+
     def set_graph(self, enable: bool):
         self._check(load().odc_context_set_graph(self.h, 1 if enable else 0), "set_graph")
 
@@ -409,13 +430,15 @@ class Context:
         if rc not in (OK, ERR_CAPACITY):
             self._check(rc, "odc_get_intermediate")
         count = int(n.value)
-        elem = 16 if name == "pair_pf" else 4
+        elem = {"pair_pf": 16, "edge_grad": 12}.get(name, 4)
         t = self.torch.empty(max(count * elem, 4), dtype=self.torch.uint8, device=self.device)
         rc = L.odc_get_intermediate(self.h, which, C.c_void_p(t.data_ptr()), count * elem,
                                     C.byref(n))
         self._check(rc, "odc_get_intermediate")
         a = t[:count * elem].cpu().numpy().view(dt)
-        return a.reshape(count, 2) if name == "pair_pf" else a
+        if name == "pair_pf":
+            return a.reshape(count, 2)
+        return a.reshape(count, 3) if name == "edge_grad" else a
 
 
 class OutputBuffers:

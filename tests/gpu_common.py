@@ -21,7 +21,7 @@ def gpu_run(field, grid, precision=0, ctx=None, want_local=True):
         r["vertices_local"] = out["vertices_local"].cpu().numpy()
         r["vertex_ref"] = out["vertex_ref"].cpu().numpy()
     for name in ("labels", "edge_ids", "edge_t", "pairs", "pair_pf", "cell_ids",
-                 "cell_partmap", "cell_nf", "vertex_base", "edge_case"):
+                 "cell_partmap", "cell_nf", "vertex_base", "edge_case", "edge_grad"):
         r[name] = ctx.intermediate(name)
     N = grid.res
     nc = (N + 1) ** 3
@@ -71,6 +71,23 @@ def mesh_labels_from_oracle(m):
 
 def corner_ijk(c, n1):
     return c % n1, (c // n1) % n1, c // (n1 * n1)
+
+
+def edge_origin(e, N):
+    """Axis and lower-corner grid position of edge e (axis-major numbering)."""
+    n1 = N + 1
+    ea = N * n1 * n1
+    a, loc = int(e) // ea, int(e) % ea
+    dims = [n1, n1, n1]
+    dims[a] = N
+    return a, [loc % dims[0], (loc // dims[0]) % dims[1], loc // (dims[0] * dims[1])]
+
+
+def world32(grid, gp):
+    """World point of grid point gp in binary32, x = lo + g h (two rounded
+    operations, h = (float)(size / res)), as both sides build query points."""
+    h = np.float32(grid.size / grid.res)
+    return [np.float32(grid.lo[a]) + np.float32(gp[a]) * h for a in range(3)]
 
 
 def edge_corners(e, N):

@@ -106,6 +106,12 @@ def _sample_surface(v, t, n, rng):
     return (1 - r1)[:, None] * a[idx] + (r1 * (1 - r2))[:, None] * b[idx] + (r1 * r2)[:, None] * c[idx]
 
 
+def sample_surface(v, t, n, seed=0):
+    """n area-uniform points on the triangle mesh (v, t)."""
+    return _sample_surface(np.asarray(v, np.float64), np.asarray(t), n,
+                           np.random.default_rng(seed))
+
+
 def _to_surface_sq(p, v, t, k=16):
     """Exact squared distance from points p to the triangle mesh (v, t).
     Candidates are the triangles with the k nearest centroids; a point is

@@ -1,0 +1,149 @@
+"""Table 3's ablation baselines on the GPU against the oracle: Manifold Dual
+Contouring's linear 1D points (Eq. 1), gradient normals (Eq. 2, by
+forward-mode differentiation through the network on the matrix cores) and
+the plain two-triangle split, alone and as the table's rows (MDC = all three,
++1D = gradient normals and plain split, +2D = plain split).
+
+Tolerances, derived from the arithmetic:
+  linear t      |dt| <= (|dpsi0| + |dpsi1|) / |psi0 - psi1| + 2^-24 with
+                |dpsi| <= |dz| / 4 + 2^-24 and |dz| <= 2e-6, the binary32
+                logit error the other MLP parity tests observe
+  gradients     relative 1e-4 (binary32 forward mode through four 256-wide
+                layers; observed ~1e-6), except at a near-switch of the
+                gradient's formula: two spheres within 1e-5 of being the
+                nearest, or a ReLU input within 1e-5 of 0 (binary32 may take
+                the other branch there; both gradients are then valid)
+  vertices      1e-5 cell widths with 2D-point normals (the method's bar);
+                5e-4 with gradient normals: a normal off by d rotates its
+                plane, and the QEF's retained eigenvalues >= tau lambda_max
+                amplify that up to 1/tau = 100 times.  Plus, where the QEF
+                drops an eigenvalue, 16 * 2^-24 / gap: the binary32
+                decomposition resolves the kept subspace only to ~2^-24
+                lambda_max / gap (gap = smallest kept-minus-dropped
+                eigenvalue over the largest, from the oracle).  Off-surface
+                1D points (linear mode) make such small gaps common.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import odc_inputs as I
+import meshcheck as M
+from gpu_common import compare_discrete, edge_origin, gpu_run, vertex_grid_coords, world32
+
+pytestmark = pytest.mark.gpu
+
+MLP_TIE = 1e-5
+DZ = 2e-6
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2409_13418_amd import odc
+    c = odc.Context(0)
+    yield c
+    c.close()
+
+
+def _psi(o, g, gp):
+    _, _, z = o.label_world(np.array(world32(g, gp), np.float32))
+    return 0.5 * math.tanh(0.5 * z)
+
+
+@pytest.mark.parametrize("mode", [1, 2, 4, 6, 7])
+def test_mlp_ablation_modes(ctx, oracle_mod, mode):
+    f = I.mlp_field(3)
+    g = I.unit_grid(24, 15)
+    g.ablation = mode
+    r, _ = gpu_run(f, g, precision=0, ctx=ctx)
+    o = oracle_mod.Oracle(f, g, mlp_tie_eps=MLP_TIE)
+    m = o.mesh()
+    assert np.array_equal(r["corner_label"], m["corner_label"])
+    assert compare_discrete(r, m) == []
+    N = g.res
+    et = r["edge_t"].astype(np.float64)
+    if mode & I.ABL_LINEAR_1D:
+        worst = 0.0
+        for x, e in enumerate(m["edge_id"]):
+            a, p = edge_origin(e, N)
+            q = list(p)
+            q[a] += 1
+            s0, s1 = _psi(o, g, p), _psi(o, g, q)
+            bound = 2 * (DZ / 4 + 2.0 ** -24) / abs(s0 - s1) + 2.0 ** -24
+            d = abs(et[x] - m["edge_t"][x])
+            worst = max(worst, d / bound)
+            assert d <= bound, (int(e), et[x], m["edge_t"][x], bound)
+        print(f"mode {mode}: linear 1D points within {worst:.2f} of their bound")
+    else:
+        ts = m["edge_tie_step"]
+        d = np.abs(et - m["edge_t"])
+        assert np.all(d[ts == 0] == 0)
+    if mode & I.ABL_GRAD_NORMALS:
+        eg = r["edge_grad"].astype(np.float64)
+        assert eg.shape == (len(m["edge_id"]), 3)
+        rel, near = [], []
+        for x, e in enumerate(m["edge_id"]):
+            a, p = edge_origin(e, N)
+            gp = [np.float32(v) for v in p]
+            gp[a] = np.float32(np.float32(p[a]) + np.float32(r["edge_t"][x]))
+            _, go, mg = o.logit_grad([float(v) for v in world32(g, gp)], with_margin=True)
+            rel.append(np.linalg.norm(eg[x] - go) / np.linalg.norm(go))
+            near.append(min(mg) < 1e-5)
+        rel, near = np.array(rel), np.array(near)
+        print(f"mode {mode}: gradient relative error max {rel[~near].max():.2e} "
+              f"({int(near.sum())} near a switch, max there {rel.max():.2e}), "
+              f"median {np.median(rel):.2e}")
+        assert np.all(rel[~near] <= 1e-4)
+        assert near.sum() <= 0.03 * len(near)
+    else:
+        assert len(r["edge_grad"]) == 0
+    nvp = int(m["cell_npart"].sum())
+    vg = vertex_grid_coords(r, N)[:nvp]
+    dv = np.max(np.abs(vg - m["vert"][:nvp]), axis=1)
+    clean = m["vert_tie"][:nvp] == 0
+    tol = (5e-4 if mode & I.ABL_GRAD_NORMALS else 1e-5) + 16 * 2.0 ** -24 / m["vert_gap"][:nvp]
+    print(f"mode {mode}: {int(clean.sum())}/{nvp} vertices without a near-tie, max err "
+          f"{dv[clean].max() if clean.any() else 0:.2e}, all {dv.max():.2e}")
+    assert np.all(dv[clean] <= tol[clean])
+    # a near-tie in a search moves a point by a search step; the QEF may
+    # amplify it, within a quarter cell
+    assert np.all(dv <= 0.25), float(dv.max())
+    if mode & I.ABL_MDC_SPLIT:
+        assert set(np.unique(r["edge_case"])) <= {0, 1} and r["n_case3"] == 0
+        assert np.array_equal(r["edge_case"], m["edge_case"])
+        assert np.array_equal(r["triangles"], m["tris"])
+    ok, why = M.is_closed_oriented_manifold(r["triangles"], r["n_vertices"])
+    assert ok, why
+
+
+def test_csg_linear_and_split(ctx, oracle_mod):
+    f = I.csg_random_field(2)
+    g = I.unit_grid(40, 15)
+    g.ablation = I.ABL_LINEAR_1D | I.ABL_MDC_SPLIT
+    r, _ = gpu_run(f, g, ctx=ctx)
+    m = oracle_mod.Oracle(f, g).mesh()
+    assert compare_discrete(r, m) == []
+    assert np.all(r["edge_t"] == 0.5) and np.array_equal(r["edge_t"].astype(np.float64), m["edge_t"])
+    assert np.array_equal(r["triangles"], m["tris"])
+    nvp = int(m["cell_npart"].sum())
+    dv = np.max(np.abs(vertex_grid_coords(r, g.res)[:nvp] - m["vert"][:nvp]), axis=1)
+    tol = 1e-5 + 16 * 2.0 ** -24 / m["vert_gap"][:nvp]
+    w = int(np.argmax(dv / tol))
+    print(f"csg linear+split: max vertex error {dv.max():.2e}; worst against its bound "
+          f"{dv[w]:.2e} of {tol[w]:.2e} (eigen-gap {m['vert_gap'][w]:.2e})")
+    assert np.all((dv <= tol) | (m["vert_tie"][:nvp] != 0)), float(dv.max())
+
+
+def test_gradient_normals_need_an_mlp_field(ctx):
+    from paper_2409_13418_amd import odc
+    g = I.unit_grid(16)
+    g.ablation = I.ABL_GRAD_NORMALS
+    with pytest.raises(odc.OdcError) as e:
+        ctx.extract(odc.DeviceField(I.csg_random_field(2)), odc.default_params(g))
+    assert e.value.status == odc.ERR_UNSUPPORTED
+    p = odc.default_params(I.unit_grid(16))
+    p.ablation = 8
+    with pytest.raises(odc.OdcError) as e:
+        ctx.extract(odc.DeviceField(I.csg_random_field(2)), p)
+    assert e.value.status == odc.ERR_INVALID_ARG
