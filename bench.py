@@ -17,8 +17,10 @@ Other modes (not run by default):
   --mode copy   a plain device-to-device copy of --copy-mib MiB, repeated
                 --steps times: the reference kernel that scales the HBM byte
                 counters (FETCH_SIZE, WRITE_SIZE) of a profile.
-  --mode ablation  Table 3's rows (MDC, + 1D search, + 2D search, ODC) on the
-                same field: time, counts, manifold check, mean |phi - 1/2|.
+  --mode ablation  Table 3's rows (MDC, + 1D search, + 2D search, ODC; the last
+                two also with 3D points clamped to their cells) on the same
+                field: time, counts, manifold check, mean |phi - 1/2|,
+                self-intersecting triangle pairs.
   --mode serve  Poisson arrivals (20 requests/s, 50/50 CSG/MLP, res 64/128/
                 256/512 with weights .4/.3/.2/.1) through the continuous-
                 batching server; p50/p99 latency (completion - arrival) and
@@ -322,9 +324,12 @@ def _ablation_mode(args):
     ctx = odc.Context(0)
     df = odc.DeviceField(field)
     rows = []
-    for name, mode in (("MDC", 7), ("+ 1D search", 6), ("+ 2D search", 4), ("+ IC (= ODC)", 0)):
+    for name, mode, clamp in (("MDC", 7, 0), ("+ 1D search", 6, 0), ("+ 2D search", 4, 0),
+                              ("+ IC (= ODC)", 0, 0), ("+ 2D search, 3D points clamped", 4, 1),
+                              ("+ IC, 3D points clamped", 0, 1)):
         grid = I.unit_grid(args.res, 15)
         grid.ablation = mode
+        grid.clamp = clamp
         params = odc.default_params(grid, prec)
         for _ in range(max(args.warmup, 1)):
             ctx.extract(df, params)
@@ -342,7 +347,7 @@ def _ablation_mode(args):
         z = ctx.field_eval(df, pts).astype(np.float64)
         fit = float(np.mean(np.abs(0.5 * np.tanh(0.5 * z))))
         si = ctx.self_intersections(r["vertices"], r["triangles"], grid.h)
-        rows.append({"row": name, "ablation": mode, "ms": ms,
+        rows.append({"row": name, "ablation": mode, "clamp_vertices": clamp, "ms": ms,
                      "cells_per_s": counts["n_active_cells"] / (ms / 1e3),
                      "n_vertices": counts["n_vertices"], "n_triangles": counts["n_triangles"],
                      "n_case3": r["n_case3"], "abs_phi_minus_half": fit,

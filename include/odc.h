@@ -98,6 +98,10 @@ typedef struct {
   int32_t precision;     /* ODC_PREC_* */
   float guard_logit;     /* bf16 guard band on z: 2 atanh(0.02) for |phi - 0.5| < 0.01 */
   int32_t ablation;      /* 0 = the method; ODC_ABL_* bits select Table 3's baselines */
+  int32_t clamp_vertices; /* 1: clamp each 3D point into its cell.  The paper is silent
+                          * and the method leaves them where the QEF puts them (0);
+                          * clamping keeps the intersection-free split's envelope
+                          * argument valid (fewer self-intersections) */
 } odc_params;
 
 /* Ablation baselines (Sec. 4 and Table 3): each bit replaces one step of the

@@ -61,6 +61,7 @@ class Grid:
     range2: float = math.sqrt(2.0) / 2.0
     qef_tau: float = 1e-2
     ablation: int = 0   # 0 = the method; bits 1, 2, 4 = the Table 3 baselines
+    clamp: int = 0      # 1 = clamp each 3D point into its cell (not the method's reading)
 
     @property
     def h(self) -> float:

@@ -997,6 +997,8 @@ static int cell_solve(const cell_ctx* cx, const int c[3], double* verts, int* pa
     if (gap_out) gap_out[part] = gp;
     tie |= tt;
     if (kap > kmax) kmax = kap;
+    if (p->clamp)
+      for (int a = 0; a < 3; ++a) x[a] = fmin(fmax(x[a], 0.0), 1.0);
     for (int a = 0; a < 3; ++a) verts[3 * part + a] = c[a] + x[a];
     if (kappa_out) kappa_out[part] = kap;
   }

@@ -71,6 +71,7 @@ typedef struct {
   double ic_tie_tol;        /* vertex uncertainty (cell widths) for IC near-ties */
   int n_threads;            /* 0 = all */
   int ablation;             /* 0 = the method; else ORC_ABL_* bits (Table 3 baselines) */
+  int clamp;                /* 1: clamp each 3D point into its cell (the method leaves it) */
 } orc_params;
 
 /* Ablation baselines (Sec. 4 / Table 3), each replacing one step of the

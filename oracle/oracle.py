@@ -41,7 +41,7 @@ class _Params(C.Structure):
                 ("iters_1d", C.c_int), ("lin1", C.c_int), ("bin1", C.c_int), ("lin2", C.c_int),
                 ("bin2", C.c_int), ("range1", C.c_float), ("range2", C.c_float),
                 ("qef_tau", C.c_double), ("ic_tie_tol", C.c_double), ("n_threads", C.c_int),
-                ("ablation", C.c_int)]
+                ("ablation", C.c_int), ("clamp", C.c_int)]
 
 
 _P = C.POINTER
@@ -131,7 +131,8 @@ class Oracle:
                         field.out_scale, mlp_tie_eps)
         self.p = _Params((C.c_double * 3)(*grid.lo), grid.size, grid.res, grid.iters_1d,
                          grid.lin1, grid.bin1, grid.lin2, grid.bin2, grid.range1, grid.range2,
-                         grid.qef_tau, ic_tie_tol, n_threads, getattr(grid, "ablation", 0))
+                         grid.qef_tau, ic_tie_tol, n_threads, getattr(grid, "ablation", 0),
+                         getattr(grid, "clamp", 0))
 
     def mesh(self) -> dict:
         m = _Mesh()

@@ -211,6 +211,8 @@ int32_t odc::validate_job(odc_context* ctx, const odc_field* f, const odc_params
     return fail(ctx, ODC_ERR_INVALID_ARG, "unknown precision %d", p->precision);
   if (p->ablation & ~(ODC_ABL_LINEAR_1D | ODC_ABL_GRAD_NORMALS | ODC_ABL_MDC_SPLIT))
     return fail(ctx, ODC_ERR_INVALID_ARG, "unknown ablation bits 0x%x", p->ablation);
+  if (p->clamp_vertices != 0 && p->clamp_vertices != 1)
+    return fail(ctx, ODC_ERR_INVALID_ARG, "clamp_vertices must be 0 or 1");
   if ((p->ablation & ODC_ABL_GRAD_NORMALS) && f->kind != ODC_FIELD_MLP)
     return fail(ctx, ODC_ERR_UNSUPPORTED, "gradient normals need an MLP field");
   if ((o->cap_vertices > 0 && !o->vertices) || (o->cap_triangles > 0 && !o->triangles) ||
@@ -271,6 +273,7 @@ void job_scalars(Job& J, const odc_field* f, const odc_params* p, int ce) {
   J.guard_logit = p->guard_logit;
   J.fp64_cond = p->fp64_cond;
   J.ablation = p->ablation;
+  J.clamp = p->clamp_vertices;
   J.nw_c = (J.g.nc + 31) / 32;
   J.nw_e = (3 * J.g.ea + 31) / 32;
   J.nw_f = (3 * J.g.fa + 31) / 32;

@@ -34,6 +34,7 @@ struct Job {
   float range1, range2, qef_tau, guard_logit;
   double fp64_cond;
   int ablation;   // ODC_ABL_* bits (0 = the method)
+  int clamp;      // clamp 3D points into their cells
 
   int nw_c, nw_e, nw_f, nw_cell;       // words of the corner / edge / face / cell bit sets
   int cap_edges, cap_pairs, cap_cells;  // active-set scratch capacities

@@ -1170,6 +1170,8 @@ __global__ __launch_bounds__(256) void k_cell_qef(const Job* __restrict__ jobs, 
                   qef_partition<double>(J, c, cfg, fm, pm, part, xd);
                   ++fp64;
                 }
+                if (J.clamp)
+                  for (int a = 0; a < 3; ++a) xd[a] = fmin(fmax(xd[a], 0.0), 1.0);
                 const float v[3] = {(float)xd[0], (float)xd[1], (float)xd[2]};
                 const int vid = vb + part;
                 J.vloc[3 * vid] = v[0];

@@ -43,7 +43,8 @@ class Params(C.Structure):
                 ("iters_1d", C.c_int32), ("lin1", C.c_int32), ("bin1", C.c_int32),
                 ("lin2", C.c_int32), ("bin2", C.c_int32), ("range1", C.c_float),
                 ("range2", C.c_float), ("qef_tau", C.c_float), ("fp64_cond", C.c_double),
-                ("precision", C.c_int32), ("guard_logit", C.c_float), ("ablation", C.c_int32)]
+                ("precision", C.c_int32), ("guard_logit", C.c_float), ("ablation", C.c_int32),
+                ("clamp_vertices", C.c_int32)]
 
 
 class MeshBuffers(C.Structure):
@@ -189,6 +190,7 @@ def default_params(grid, precision: int = PREC_FP32) -> Params:
     p.precision = int(precision)
     p.guard_logit = float(2.0 * math.atanh(0.02))
     p.ablation = int(getattr(grid, "ablation", 0))
+    p.clamp_vertices = int(getattr(grid, "clamp", 0))
     return p
 
 

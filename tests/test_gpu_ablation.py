@@ -147,3 +147,25 @@ def test_gradient_normals_need_an_mlp_field(ctx):
     with pytest.raises(odc.OdcError) as e:
         ctx.extract(odc.DeviceField(I.csg_random_field(2)), p)
     assert e.value.status == odc.ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("kind", ["mlp", "csg"])
+def test_clamped_vertices(ctx, oracle_mod, kind):
+    f = I.mlp_field(3) if kind == "mlp" else I.csg_random_field(2)
+    g = I.unit_grid(24 if kind == "mlp" else 32, 15)
+    g.clamp = 1
+    r, _ = gpu_run(f, g, precision=0, ctx=ctx)
+    m = oracle_mod.Oracle(f, g, mlp_tie_eps=MLP_TIE).mesh()
+    assert compare_discrete(r, m) == []
+    nvp = int(m["cell_npart"].sum())
+    vl = r["vertices_local"][:nvp]
+    assert np.all((vl >= 0.0) & (vl <= 1.0))
+    dv = np.max(np.abs(vertex_grid_coords(r, g.res)[:nvp] - m["vert"][:nvp]), axis=1)
+    clean = m["vert_tie"][:nvp] == 0
+    tol = 1e-5 + 16 * 2.0 ** -24 / m["vert_gap"][:nvp]
+    assert np.all(dv[clean] <= tol[clean])
+    assert np.all(dv <= 0.25)
+    if np.all(r["edge_case"] == m["edge_case"]):
+        assert np.array_equal(r["triangles"], m["tris"])
+    ok, why = M.is_closed_oriented_manifold(r["triangles"], r["n_vertices"])
+    assert ok, why

@@ -170,3 +170,22 @@ def test_gradient_normals_need_an_mlp_field(oracle_mod):
     except ValueError:
         return
     raise AssertionError("CSG field with gradient normals was accepted")
+
+
+def test_clamped_vertices_are_the_projection(oracle_mod):
+    """The clamp option moves each partition vertex to the nearest point of its
+    cell and nothing else: vertices inside stay, the rest are projected."""
+    f = I.mlp_field(3)
+    g0 = I.unit_grid(16)
+    g1 = I.unit_grid(16)
+    g1.clamp = 1
+    m0 = oracle_mod.Oracle(f, g0, mlp_tie_eps=1e-5).mesh()
+    m1 = oracle_mod.Oracle(f, g1, mlp_tie_eps=1e-5).mesh()
+    nvp = int(m0["cell_npart"].sum())
+    N = g0.res
+    owner = np.searchsorted(m0["cell_vbase"], np.arange(nvp), side="right") - 1
+    cid = m0["cell_id"][owner]
+    c = np.stack([cid % N, (cid // N) % N, cid // (N * N)], 1).astype(float)
+    assert np.array_equal(m1["vert"][:nvp], np.clip(m0["vert"][:nvp], c, c + 1))
+    outside = np.any((m0["vert"][:nvp] < c) | (m0["vert"][:nvp] > c + 1), axis=1)
+    assert outside.sum() > 0
