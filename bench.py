@@ -313,18 +313,23 @@ def _ablation_mode(args):
     + the 1D search, + the 2D search, + the intersection-free split (= ODC).
     Per row: extraction time, counts, the manifold check, and the fitting
     error mean |phi - 1/2| at area-uniform samples of the mesh (phi from the
-    fp32 field evaluation on the GPU)."""
+    fp32 field evaluation on the GPU).  With --ablation-field sdf the input is
+    a signed distance psi (the same zero set): the MDC row interpolates psi
+    itself and the fitting error is mean |psi|, as for the paper's DeepSDF
+    results."""
     import torch
     from paper_2409_13418_amd import odc
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from meshcheck import is_closed_oriented_manifold, sample_surface
 
-    field = I.mlp_field(3)
+    sdf = args.ablation_field == "sdf"
+    field = I.sdf_mlp_field(3) if sdf else I.mlp_field(3)
+    mdc = 7 | (I.ABL_SDF_INPUT if sdf else 0)
     prec = odc.PREC_BF16_GUARDED if args.precision == "bf16" else odc.PREC_FP32
     ctx = odc.Context(0)
     df = odc.DeviceField(field)
     rows = []
-    for name, mode, clamp in (("MDC", 7, 0), ("+ 1D search", 6, 0), ("+ 2D search", 4, 0),
+    for name, mode, clamp in (("MDC", mdc, 0), ("+ 1D search", 6, 0), ("+ 2D search", 4, 0),
                               ("+ IC (= ODC)", 0, 0), ("+ 2D search, 3D points clamped", 4, 1),
                               ("+ IC, 3D points clamped", 0, 1)):
         grid = I.unit_grid(args.res, 15)
@@ -345,22 +350,25 @@ def _ablation_mode(args):
         ok, why = is_closed_oriented_manifold(t, len(v))
         pts = sample_surface(v, t, args.ablation_samples, seed=5)
         z = ctx.field_eval(df, pts).astype(np.float64)
-        fit = float(np.mean(np.abs(0.5 * np.tanh(0.5 * z))))
+        fit = float(np.mean(np.abs(z) if sdf else np.abs(0.5 * np.tanh(0.5 * z))))
         si = ctx.self_intersections(r["vertices"], r["triangles"], grid.h)
         rows.append({"row": name, "ablation": mode, "clamp_vertices": clamp, "ms": ms,
                      "cells_per_s": counts["n_active_cells"] / (ms / 1e3),
                      "n_vertices": counts["n_vertices"], "n_triangles": counts["n_triangles"],
-                     "n_case3": r["n_case3"], "abs_phi_minus_half": fit,
+                     "n_case3": r["n_case3"], ("abs_psi" if sdf else "abs_phi_minus_half"): fit,
                      "self_intersecting_pairs": si, "closed_manifold": bool(ok)})
-        print(f"# {name}: {ms:.1f} ms, |phi-1/2| {fit:.3e}, SI pairs {si}, V {counts['n_vertices']}, "
+        print(f"# {name}: {ms:.1f} ms, {'|psi|' if sdf else '|phi-1/2|'} {fit:.3e}, SI pairs {si}, "
+              f"V {counts['n_vertices']}, "
               f"T {counts['n_triangles']}, manifold {ok}", file=sys.stderr, flush=True)
     print(json.dumps({
-        "metric": "Table 3 ablation rows on the 256^3 MLP field", "n_gpus": 1,
+        "metric": f"Table 3 ablation rows on the {args.res}^3 MLP "
+                  f"{'signed-distance' if sdf else 'occupancy'} field", "n_gpus": 1,
         "dtype": "bf16+fp32" if prec == odc.PREC_BF16_GUARDED else "fp32", "data": "synthetic",
         "steps": args.steps,
-        "config": {"workload": f"mlp{args.res}_ablation", "res": args.res,
+        "config": {"workload": f"{'sdf' if sdf else 'mlp'}{args.res}_ablation", "res": args.res,
                    "samples": args.ablation_samples,
-                   "fit": "mean |phi - 1/2| = mean |tanh(z/2)|/2 at area-uniform mesh samples",
+                   "fit": ("mean |psi| = mean |z| at area-uniform mesh samples" if sdf else
+                           "mean |phi - 1/2| = mean |tanh(z/2)|/2 at area-uniform mesh samples"),
                    "self_intersections": "pairs of vertex-disjoint triangles that intersect"},
         "rows": rows}), flush=True)
 
@@ -385,6 +393,7 @@ def main():
     ap.add_argument("--mode", choices=("single", "batch", "serve", "copy", "ablation"),
                     default="single")
     ap.add_argument("--ablation-samples", type=int, default=1000000)
+    ap.add_argument("--ablation-field", choices=("occupancy", "sdf"), default="occupancy")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-requests", type=int, default=1200)

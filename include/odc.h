@@ -112,8 +112,16 @@ typedef struct {
  *                by forward-mode differentiation through the network on the
  *                matrix cores; no 2D points are searched.  MLP fields only
  *                (UNSUPPORTED otherwise)
- *  MDC_SPLIT     every quad split as case 1 of App. A.1.5 (no case 3) */
-enum { ODC_ABL_LINEAR_1D = 1, ODC_ABL_GRAD_NORMALS = 2, ODC_ABL_MDC_SPLIT = 4 };
+ *  MDC_SPLIT     every quad split as case 1 of App. A.1.5 (no case 3)
+ *  SDF_INPUT     with LINEAR_1D only (INVALID_ARG otherwise): the field is a
+ *                signed distance psi (inside where psi < 0, the DeepSDF
+ *                results of S.3.5) carried as its logit z = -psi (say
+ *                out_scale = -1 and sdf_gain = 0 take the network's output as
+ *                psi), so Eq. 1 interpolates z itself rather than tanh(z/2)/2.
+ *                The method proper needs no flag for such a field: it reads
+ *                only the sign of z.  No effect on CSG fields (t = 1/2). */
+enum { ODC_ABL_LINEAR_1D = 1, ODC_ABL_GRAD_NORMALS = 2, ODC_ABL_MDC_SPLIT = 4,
+       ODC_ABL_SDF_INPUT = 8 };
 
 /* Output buffers (device, caller-owned).  vertices: 3 floats per vertex,
  * world coordinates.  triangles: 3 int32 vertex ids each, oriented so the

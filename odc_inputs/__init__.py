@@ -29,7 +29,7 @@ OP_UNION, OP_SUBTRACT, OP_INTERSECT = 0, 1, 2
 PRIM_SPHERE, PRIM_BOX, PRIM_HALFSPACE = 0, 1, 2
 FIELD_CSG, FIELD_MLP = 0, 1
 # ablation baselines (Table 3): linear 1D points, gradient normals, 2-triangle split
-ABL_LINEAR_1D, ABL_GRAD_NORMALS, ABL_MDC_SPLIT = 1, 2, 4
+ABL_LINEAR_1D, ABL_GRAD_NORMALS, ABL_MDC_SPLIT, ABL_SDF_INPUT = 1, 2, 4, 8
 
 
 @dataclasses.dataclass
@@ -173,6 +173,16 @@ def mlp_field(seed: int = 3, n_spheres: int = 32, width: int = 256, depth: int =
     return Field(kind=FIELD_MLP, weights=w, in_dim=in_dim, width=width, depth=depth,
                  n_bands=n_bands, spheres=sph, sdf_gain=sdf_gain, out_scale=out_scale,
                  name=f"mlp{seed}")
+
+
+def sdf_mlp_field(seed: int = 3) -> Field:
+    """A neural signed-distance input (DeepSDF-like): psi = sdf(x) - 0.015
+    MLP(gamma(x)), with inside where psi < 0.  Its logit z = -psi is mlp_field's
+    logit divided by 20, so the two fields share their zero set (up to the
+    rounding of the two scale factors)."""
+    f = mlp_field(seed, out_scale=0.015, sdf_gain=1.0)
+    f.name = f"sdf{seed}"
+    return f
 
 
 def mlp_weight_count(in_dim: int, width: int, depth: int) -> int:

@@ -318,7 +318,8 @@ static double linear_edge(const orc_field* f, const orc_params* p, int a, const 
     } else {
       float g[3] = {(float)q[0], (float)q[1], (float)q[2]}, x[3];
       grid_to_world(p, g, x);
-      psi[e] = 0.5 * tanh(0.5 * mlp_logit(f, x));
+      const double z = mlp_logit(f, x);
+      psi[e] = (p->ablation & ORC_ABL_SDF_INPUT) ? z : 0.5 * tanh(0.5 * z);
     }
   }
   return psi[0] / (psi[0] - psi[1]);
@@ -1056,7 +1057,10 @@ static int valid_params(const orc_field* f, const orc_params* p) {
   if (p->lin1 < 1 || p->lin2 < 1 || p->bin1 < 0 || p->bin2 < 0) return 0;
   if (f->kind == ORC_FIELD_CSG && (f->n_prims < 1 || !f->prims)) return 0;
   if (f->kind == ORC_FIELD_MLP && (!f->weights || f->depth < 1 || f->width < 1)) return 0;
-  if (p->ablation & ~(ORC_ABL_LINEAR_1D | ORC_ABL_GRAD_NORMALS | ORC_ABL_MDC_SPLIT)) return 0;
+  if (p->ablation &
+      ~(ORC_ABL_LINEAR_1D | ORC_ABL_GRAD_NORMALS | ORC_ABL_MDC_SPLIT | ORC_ABL_SDF_INPUT))
+    return 0;
+  if ((p->ablation & ORC_ABL_SDF_INPUT) && !(p->ablation & ORC_ABL_LINEAR_1D)) return 0;
   if ((p->ablation & ORC_ABL_GRAD_NORMALS) && (f->kind != ORC_FIELD_MLP || f->depth > 64)) return 0;
   return 1;
 }

@@ -80,7 +80,10 @@ typedef struct {
  *   GRAD_NORMALS  QEF normals = the field gradient at the 1D point (Eq. 2;
  *                 MLP fields only), no 2D points
  *   MDC_SPLIT     every quad split as case 1 (no intersection-free split) */
-enum { ORC_ABL_LINEAR_1D = 1, ORC_ABL_GRAD_NORMALS = 2, ORC_ABL_MDC_SPLIT = 4 };
+enum { ORC_ABL_LINEAR_1D = 1, ORC_ABL_GRAD_NORMALS = 2, ORC_ABL_MDC_SPLIT = 4,
+       /* with LINEAR_1D: the field's logit is a signed distance (SDF input,
+        * inside where z > 0), and Eq. 1 interpolates z itself */
+       ORC_ABL_SDF_INPUT = 8 };
 
 typedef struct {
   int res;

@@ -209,8 +209,11 @@ int32_t odc::validate_job(odc_context* ctx, const odc_field* f, const odc_params
     return fail(ctx, ODC_ERR_INVALID_ARG, "qef_tau outside [0,1)");
   if (p->precision != ODC_PREC_FP32 && p->precision != ODC_PREC_BF16_GUARDED)
     return fail(ctx, ODC_ERR_INVALID_ARG, "unknown precision %d", p->precision);
-  if (p->ablation & ~(ODC_ABL_LINEAR_1D | ODC_ABL_GRAD_NORMALS | ODC_ABL_MDC_SPLIT))
+  if (p->ablation &
+      ~(ODC_ABL_LINEAR_1D | ODC_ABL_GRAD_NORMALS | ODC_ABL_MDC_SPLIT | ODC_ABL_SDF_INPUT))
     return fail(ctx, ODC_ERR_INVALID_ARG, "unknown ablation bits 0x%x", p->ablation);
+  if ((p->ablation & ODC_ABL_SDF_INPUT) && !(p->ablation & ODC_ABL_LINEAR_1D))
+    return fail(ctx, ODC_ERR_INVALID_ARG, "SDF input applies to linear 1D points only");
   if (p->clamp_vertices != 0 && p->clamp_vertices != 1)
     return fail(ctx, ODC_ERR_INVALID_ARG, "clamp_vertices must be 0 or 1");
   if ((p->ablation & ODC_ABL_GRAD_NORMALS) && f->kind != ODC_FIELD_MLP)

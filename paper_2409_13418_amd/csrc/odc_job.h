@@ -21,7 +21,7 @@
 namespace odc {
 
 // ablation bits of a job (the public ODC_ABL_* values)
-constexpr int kAblLinear1D = 1, kAblGradNormals = 2, kAblMdcSplit = 4;
+constexpr int kAblLinear1D = 1, kAblGradNormals = 2, kAblMdcSplit = 4, kAblSdfInput = 8;
 
 struct Job {
   Grid g;

@@ -610,7 +610,8 @@ __global__ __launch_bounds__(256) void k_bisect_csg(const Job* __restrict__ jobs
 }
 
 // Eq. 1 (the linear-1D ablation): psi = phi - 1/2 = tanh(z/2)/2 at the two
-// corners of the edge, t = psi0 / (psi0 - psi1), binary32.
+// corners of the edge (z itself for SDF input), t = psi0 / (psi0 - psi1),
+// binary32.
 __device__ __forceinline__ float linear_edge_mlp(const Job& J, int e, float* act) {
   int a, p[3];
   edge_pos(J.g, e, a, p);
@@ -620,7 +621,8 @@ __device__ __forceinline__ float linear_edge_mlp(const Job& J, int e, float* act
     const float gp[3] = {(float)p[0], (float)p[1], (float)p[2]};
     float x[3];
     grid_world(J.g, gp, x);
-    psi[end] = 0.5f * tanhf(0.5f * mlp_logit_fp32(J.mlp, x, act));
+    const float z = mlp_logit_fp32(J.mlp, x, act);
+    psi[end] = (J.ablation & kAblSdfInput) ? z : 0.5f * tanhf(0.5f * z);
     add_at3(p, a, 1);
   }
   return psi[0] / (psi[0] - psi[1]);

@@ -63,7 +63,7 @@ class MeshCounts(C.Structure):
 
 
 SERVE_FIFO, SERVE_SHORTEST = 0, 1
-ABL_LINEAR_1D, ABL_GRAD_NORMALS, ABL_MDC_SPLIT = 1, 2, 4
+ABL_LINEAR_1D, ABL_GRAD_NORMALS, ABL_MDC_SPLIT, ABL_SDF_INPUT = 1, 2, 4, 8
 
 
 class ServerConfig(C.Structure):

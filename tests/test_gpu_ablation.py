@@ -2,12 +2,15 @@
 Contouring's linear 1D points (Eq. 1), gradient normals (Eq. 2, by
 forward-mode differentiation through the network on the matrix cores) and
 the plain two-triangle split, alone and as the table's rows (MDC = all three,
-+1D = gradient normals and plain split, +2D = plain split).
++1D = gradient normals and plain split, +2D = plain split), and on an SDF
+input (a field whose logit is minus a signed distance): ODC itself, linear
+points on psi (mode 9) and the MDC row on psi (mode 15).
 
 Tolerances, derived from the arithmetic:
   linear t      |dt| <= (|dpsi0| + |dpsi1|) / |psi0 - psi1| + 2^-24 with
                 |dpsi| <= |dz| / 4 + 2^-24 and |dz| <= 2e-6, the binary32
-                logit error the other MLP parity tests observe
+                logit error the other MLP parity tests observe (|dpsi| <=
+                |dz| + 2^-24 for SDF input, where psi is z itself)
   gradients     relative 1e-4 (binary32 forward mode through four 256-wide
                 layers; observed ~1e-6), except at a near-switch of the
                 gradient's formula: two spheres within 1e-5 of being the
@@ -46,18 +49,22 @@ def ctx():
     c.close()
 
 
-def _psi(o, g, gp):
+def _psi(o, g, gp, mode):
     _, _, z = o.label_world(np.array(world32(g, gp), np.float32))
-    return 0.5 * math.tanh(0.5 * z)
+    return z if mode & I.ABL_SDF_INPUT else 0.5 * math.tanh(0.5 * z)
 
 
-@pytest.mark.parametrize("mode", [1, 2, 4, 6, 7])
-def test_mlp_ablation_modes(ctx, oracle_mod, mode):
-    f = I.mlp_field(3)
+@pytest.mark.parametrize("field,mode", [("occ", 1), ("occ", 2), ("occ", 4), ("occ", 6),
+                                        ("occ", 7), ("sdf", 0), ("sdf", 9), ("sdf", 15)])
+def test_mlp_ablation_modes(ctx, oracle_mod, field, mode):
+    # the SDF input's logit is the occupancy field's over 20: so are its
+    # binary32 error and its tie margin
+    scale = 1.0 if field == "occ" else 1.0 / 20
+    f = I.mlp_field(3) if field == "occ" else I.sdf_mlp_field(3)
     g = I.unit_grid(24, 15)
     g.ablation = mode
     r, _ = gpu_run(f, g, precision=0, ctx=ctx)
-    o = oracle_mod.Oracle(f, g, mlp_tie_eps=MLP_TIE)
+    o = oracle_mod.Oracle(f, g, mlp_tie_eps=MLP_TIE * scale)
     m = o.mesh()
     assert np.array_equal(r["corner_label"], m["corner_label"])
     assert compare_discrete(r, m) == []
@@ -69,12 +76,13 @@ def test_mlp_ablation_modes(ctx, oracle_mod, mode):
             a, p = edge_origin(e, N)
             q = list(p)
             q[a] += 1
-            s0, s1 = _psi(o, g, p), _psi(o, g, q)
-            bound = 2 * (DZ / 4 + 2.0 ** -24) / abs(s0 - s1) + 2.0 ** -24
+            s0, s1 = _psi(o, g, p, mode), _psi(o, g, q, mode)
+            dpsi = DZ * scale if mode & I.ABL_SDF_INPUT else DZ / 4
+            bound = 2 * (dpsi + 2.0 ** -24) / abs(s0 - s1) + 2.0 ** -24
             d = abs(et[x] - m["edge_t"][x])
             worst = max(worst, d / bound)
             assert d <= bound, (int(e), et[x], m["edge_t"][x], bound)
-        print(f"mode {mode}: linear 1D points within {worst:.2f} of their bound")
+        print(f"{field} mode {mode}: linear 1D points within {worst:.2f} of their bound")
     else:
         ts = m["edge_tie_step"]
         d = np.abs(et - m["edge_t"])
@@ -91,7 +99,7 @@ def test_mlp_ablation_modes(ctx, oracle_mod, mode):
             rel.append(np.linalg.norm(eg[x] - go) / np.linalg.norm(go))
             near.append(min(mg) < 1e-5)
         rel, near = np.array(rel), np.array(near)
-        print(f"mode {mode}: gradient relative error max {rel[~near].max():.2e} "
+        print(f"{field} mode {mode}: gradient relative error max {rel[~near].max():.2e} "
               f"({int(near.sum())} near a switch, max there {rel.max():.2e}), "
               f"median {np.median(rel):.2e}")
         assert np.all(rel[~near] <= 1e-4)
@@ -103,7 +111,7 @@ def test_mlp_ablation_modes(ctx, oracle_mod, mode):
     dv = np.max(np.abs(vg - m["vert"][:nvp]), axis=1)
     clean = m["vert_tie"][:nvp] == 0
     tol = (5e-4 if mode & I.ABL_GRAD_NORMALS else 1e-5) + 16 * 2.0 ** -24 / m["vert_gap"][:nvp]
-    print(f"mode {mode}: {int(clean.sum())}/{nvp} vertices without a near-tie, max err "
+    print(f"{field} mode {mode}: {int(clean.sum())}/{nvp} vertices without a near-tie, max err "
           f"{dv[clean].max() if clean.any() else 0:.2e}, all {dv.max():.2e}")
     assert np.all(dv[clean] <= tol[clean])
     # a near-tie in a search moves a point by a search step; the QEF may
@@ -135,18 +143,20 @@ def test_csg_linear_and_split(ctx, oracle_mod):
     assert np.all((dv <= tol) | (m["vert_tie"][:nvp] != 0)), float(dv.max())
 
 
-def test_gradient_normals_need_an_mlp_field(ctx):
+def test_ablation_bits_are_checked(ctx):
     from paper_2409_13418_amd import odc
     g = I.unit_grid(16)
     g.ablation = I.ABL_GRAD_NORMALS
     with pytest.raises(odc.OdcError) as e:
         ctx.extract(odc.DeviceField(I.csg_random_field(2)), odc.default_params(g))
     assert e.value.status == odc.ERR_UNSUPPORTED
-    p = odc.default_params(I.unit_grid(16))
-    p.ablation = 8
-    with pytest.raises(odc.OdcError) as e:
-        ctx.extract(odc.DeviceField(I.csg_random_field(2)), p)
-    assert e.value.status == odc.ERR_INVALID_ARG
+    # an unknown bit, and SDF input without the linear points
+    for bits in (16, I.ABL_SDF_INPUT, I.ABL_SDF_INPUT | I.ABL_MDC_SPLIT):
+        p = odc.default_params(I.unit_grid(16))
+        p.ablation = bits
+        with pytest.raises(odc.OdcError) as e:
+            ctx.extract(odc.DeviceField(I.sdf_mlp_field(3)), p)
+        assert e.value.status == odc.ERR_INVALID_ARG, bits
 
 
 @pytest.mark.parametrize("kind", ["mlp", "csg"])

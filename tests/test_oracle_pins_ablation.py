@@ -189,3 +189,70 @@ def test_clamped_vertices_are_the_projection(oracle_mod):
     assert np.array_equal(m1["vert"][:nvp], np.clip(m0["vert"][:nvp], c, c + 1))
     outside = np.any((m0["vert"][:nvp] < c) | (m0["vert"][:nvp] > c + 1), axis=1)
     assert outside.sum() > 0
+
+
+def test_sdf_input_interpolates_the_distance(oracle_mod):
+    """SDF input: the logit of a sphere field with gain 1 is minus its signed
+    distance, and Eq. 1 on that distance is exact up to the distance's
+    curvature along the edge (no tanh term)."""
+    c = np.array([20.05, 0.3, -0.2])
+    f = _sphere_only(c, 20.0, 1.0)
+    g = I.unit_grid(16)
+    g.ablation = I.ABL_LINEAR_1D | I.ABL_SDF_INPUT
+    m = oracle_mod.Oracle(f, g).mesh()
+    N, n1 = g.res, g.res + 1
+    cf = np.asarray(np.float32(c), np.float64)
+    rf = float(np.float32(20.0))
+    for e, t in zip(m["edge_id"], m["edge_t"]):
+        ea = N * n1 * n1
+        a, loc = int(e) // ea, int(e) % ea
+        dims = [n1, n1, n1]
+        dims[a] = N
+        p = np.array([loc % dims[0], (loc // dims[0]) % dims[1], loc // (dims[0] * dims[1])], float)
+        x0 = -0.5 + p * g.h
+        d = np.zeros(3); d[a] = g.h
+        A = d @ d; B = 2 * d @ (x0 - cf); Cc = (x0 - cf) @ (x0 - cf) - rf * rf
+        s = min([(-B + sg * math.sqrt(B * B - 4 * A * Cc)) / (2 * A) for sg in (-1, 1)],
+                key=lambda q: abs(q - 0.5))
+        dsdf = abs(np.linalg.norm(x0 + d - cf) - np.linalg.norm(x0 - cf))
+        assert abs(t - s) <= 1e-9 + g.h ** 2 / (4 * rf) / dsdf, (int(e), t, s)
+    # without the linear mode the flag is rejected
+    g2 = I.unit_grid(8)
+    g2.ablation = I.ABL_SDF_INPUT
+    try:
+        oracle_mod.Oracle(f, g2).mesh()
+    except ValueError:
+        return
+    raise AssertionError("SDF input without linear 1D points was accepted")
+
+
+def test_sdf_input_gives_the_occupancy_mesh(oracle_mod):
+    """SDF input (s = [psi < 0]): the method reads only the sign of the field,
+    so a signed-distance field and an occupancy field with the same zero set
+    give the same mesh.  sdf_mlp_field's logit is mlp_field's divided by 20
+    (the scale factors round differently, but no decision of this grid falls
+    between the two)."""
+    g = I.unit_grid(16)
+    mo = oracle_mod.Oracle(I.mlp_field(3), g, mlp_tie_eps=1e-6).mesh()
+    ms = oracle_mod.Oracle(I.sdf_mlp_field(3), g, mlp_tie_eps=5e-8).mesh()
+    # the tie margins scale with the field, so both flag the same decisions
+    assert np.array_equal(mo["corner_tie"], ms["corner_tie"])
+    assert np.array_equal(mo["corner_label"], ms["corner_label"])
+    assert np.array_equal(mo["edge_id"], ms["edge_id"])
+    assert np.array_equal(mo["edge_tie_step"], ms["edge_tie_step"])
+    assert np.array_equal(mo["edge_t"], ms["edge_t"])
+    assert np.array_equal(mo["tris"], ms["tris"])
+    assert np.array_equal(mo["pair_pf"], ms["pair_pf"])
+    assert np.array_equal(mo["vert_tie"], ms["vert_tie"])
+    assert np.array_equal(mo["vert"], ms["vert"])
+    # Eq. 1 on the two inputs: psi = z/20 linearly vs tanh(z/2)/2, so the
+    # linear points differ, by at most the tanh curvature over an edge
+    g1 = I.unit_grid(16)
+    g1.ablation = I.ABL_LINEAR_1D
+    g2 = I.unit_grid(16)
+    g2.ablation = I.ABL_LINEAR_1D | I.ABL_SDF_INPUT
+    lo = oracle_mod.Oracle(I.mlp_field(3), g1, mlp_tie_eps=1e-6).mesh()
+    ls = oracle_mod.Oracle(I.sdf_mlp_field(3), g2, mlp_tie_eps=5e-8).mesh()
+    assert np.array_equal(lo["edge_id"], ls["edge_id"])
+    d = np.abs(lo["edge_t"] - ls["edge_t"])
+    assert d.max() > 1e-6 and d.max() < 0.5
