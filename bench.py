@@ -457,10 +457,11 @@ def main():
 
     # roofline of the dominant kernel: the 2D-point search (fp32 matrix cores)
     per_query = MLP_FLOP_PER_QUERY(field)
-    per_pair = 1 + (grid.lin1 + grid.bin1) + 2 * (grid.lin2 + grid.bin2)
     dom = max(("bisect", "search2d", "labels"), key=lambda k: stages[k])
     if dom == "search2d":
-        flop = counts["n_pairs"] * per_pair * per_query
+        # the queries the kernel evaluated for real pairs (linear samples that
+        # no pair of a wavefront needed are skipped)
+        flop = counts["n_search2d_queries"] * per_query
         peak = PEAK_FP32_MFMA
     elif dom == "bisect":
         flop = counts["n_active_edges"] * grid.iters_1d * per_query
@@ -487,7 +488,8 @@ def main():
         "p99_step_ms": float(np.percentile(step_ms, 99)),
         "counts": {k: counts[k] for k in ("n_active_cells", "n_active_edges", "n_pairs",
                                           "n_vertices", "n_triangles", "n_queries",
-                                          "n_guard_corners", "n_fp64_cells")},
+                                          "n_search2d_queries", "n_guard_corners",
+                                          "n_fp64_cells")},
         "stages_ms": stages,
         "roofline": roofline,
     }

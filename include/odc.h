@@ -148,6 +148,9 @@ typedef struct {
   int64_t n_fp64_cells;    /* QEF solves redone in binary64 */
   int64_t n_guard_corners; /* bf16 corner queries re-evaluated in fp32 */
   int64_t n_queries;       /* occupancy queries issued */
+  int64_t n_search2d_queries; /* of which in the 2D searches: n_pairs x (1 + lin1 + bin1 +
+                                 2 (lin2 + bin2)), less the linear samples past the first
+                                 label change of every pair a wavefront holds (MLP) */
 } odc_mesh_counts;
 
 /* Status text (static storage). */

@@ -140,13 +140,13 @@ extern "C" int32_t odc_context_create(int32_t device, void* stream, odc_context*
            hipSuccess ||
        hipHostMalloc((void**)&ctx->hweights, kMaxJobs * sizeof(float*), hipHostMallocDefault) !=
            hipSuccess ||
-       hipHostMalloc((void**)&ctx->hgather, kMaxJobs * 8 * sizeof(unsigned long long),
+       hipHostMalloc((void**)&ctx->hgather, kMaxJobs * kGatherWords * sizeof(unsigned long long),
                      hipHostMallocDefault) != hipSuccess))
     rc = ODC_ERR_OUT_OF_MEMORY;
   if (rc == ODC_OK) rc = ensure(ctx, ctx->table, 256 * sizeof(uint32_t));
   if (rc == ODC_OK) rc = ensure(ctx, ctx->djobs, kMaxJobs * sizeof(Job));
   if (rc == ODC_OK) rc = ensure(ctx, ctx->dweights, kMaxJobs * sizeof(float*));
-  if (rc == ODC_OK) rc = ensure(ctx, ctx->dgather, kMaxJobs * 8 * sizeof(unsigned long long));
+  if (rc == ODC_OK) rc = ensure(ctx, ctx->dgather, kMaxJobs * kGatherWords * sizeof(unsigned long long));
   if (rc == ODC_OK && launch_partition_table(P<uint32_t>(ctx->table), ctx->stream) != hipSuccess)
     rc = ODC_ERR_HIP;
   if (rc == ODC_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) rc = ODC_ERR_HIP;
@@ -526,7 +526,7 @@ static int32_t run_batch(odc_context* ctx, int n) {
   }
   HIP_TRY(ctx, launch_gather(d, n, P<unsigned long long>(ctx->dgather), s));
   HIP_TRY(ctx, hipMemcpyAsync(ctx->hgather, P<unsigned long long>(ctx->dgather),
-                              n * 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+                              n * kGatherWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
   return ODC_OK;
 }
 
@@ -561,11 +561,11 @@ extern "C" int32_t odc_mesh_extract_batch(odc_context* ctx, int32_t n, const odc
 }
 
 bool odc::job_overflowed(const odc_context* ctx, int k) {
-  return (ctx->hgather[8 * k + 7] >> 32) != 0;
+  return (ctx->hgather[kGatherWords * k + 7] >> 32) != 0;
 }
 
 int odc::needed_edges(const odc_context* ctx, int k, bool* guard_over) {
-  const unsigned long long* o = ctx->hgather + 8 * k;
+  const unsigned long long* o = ctx->hgather + kGatherWords * k;
   if (guard_over) *guard_over = o[6] > (unsigned long long)ctx->hjobs[k].guard_cap;
   long long need = (long long)o[0];
   if ((long long)((o[1] + 1) / 2) > need) need = (long long)((o[1] + 1) / 2);
@@ -599,7 +599,7 @@ static int32_t finish(odc_context* ctx) {
 }
 
 void odc::fill_counts(const odc_context* ctx, int k, odc_mesh_counts* c) {
-  const unsigned long long* o = ctx->hgather + 8 * k;
+  const unsigned long long* o = ctx->hgather + kGatherWords * k;
   const Job& J = ctx->hjobs[k];
   memset(c, 0, sizeof(*c));
   c->n_active_edges = (int64_t)o[0];
@@ -610,9 +610,16 @@ void odc::fill_counts(const odc_context* ctx, int k, odc_mesh_counts* c) {
   c->n_triangles = (int64_t)o[4];
   c->n_guard_corners = (int64_t)o[6];
   c->n_fp64_cells = (int64_t)(o[7] & 0xFFFFFFFFull);
+  // occupancy queries: every corner, the bf16 guard's fp32 repeats, the 1D
+  // points (two corner queries each for linear points), the 2D searches less
+  // the linear samples no lane of a wavefront needed (none with gradient
+  // normals, whose passes are not occupancy queries)
   const int64_t per_pair = 1 + (J.lin1 + J.bin1) + 2 * (J.lin2 + J.bin2);
-  c->n_queries = (int64_t)J.g.nc + c->n_guard_corners + c->n_active_edges * J.iters_1d +
-                 c->n_pairs * per_pair;
+  c->n_search2d_queries =
+      (J.ablation & kAblGradNormals) ? 0 : c->n_pairs * per_pair - (int64_t)o[8];
+  c->n_queries = (int64_t)J.g.nc + c->n_guard_corners +
+                 c->n_active_edges * ((J.ablation & kAblLinear1D) ? 2 : J.iters_1d) +
+                 c->n_search2d_queries;
   c->n_flipped_faces = -1;
 }
 

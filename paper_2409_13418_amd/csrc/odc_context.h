@@ -49,7 +49,7 @@ struct odc_context {
   odc::DevBuf djobs, dweights, dgather, table;
   odc::Job* hjobs = nullptr;               // pinned
   const float** hweights = nullptr;        // pinned
-  unsigned long long* hgather = nullptr;   // pinned, 8 per job
+  unsigned long long* hgather = nullptr;   // pinned, kGatherWords per job
   odc::LaunchCfg cfg;
   double cap_scale = 1.0;
   // timing

@@ -267,15 +267,16 @@ __global__ void k_clear_status(const Job* __restrict__ jobs, int njobs) {
     jobs[k].status[0] = 0;
     jobs[k].status[1] = 0;
     jobs[k].status[2] = 0;
+    jobs[k].status[3] = 0;
   }
 }
 
-// per job: raw totals and status for the host (8 x uint64)
+// per job: raw totals and status for the host (kGatherWords x uint64)
 __global__ void k_gather(const Job* __restrict__ jobs, int njobs,
                          unsigned long long* __restrict__ out) {
   for (int k = gthread(); k < njobs; k += nthreads()) {
     const Job& J = jobs[k];
-    unsigned long long* o = out + 8 * k;
+    unsigned long long* o = out + kGatherWords * k;
     const int ne = n_edges_of(J), nc = n_cells_of(J);
     o[0] = J.eprefix[J.nw_e];
     o[1] = J.pprefix[J.nw_f];
@@ -285,6 +286,7 @@ __global__ void k_gather(const Job* __restrict__ jobs, int njobs,
     o[5] = J.c3prefix[ne];
     o[6] = J.status[0];
     o[7] = J.status[1] | (J.status[2] << 32);
+    o[8] = J.status[3];
   }
 }
 
@@ -562,6 +564,9 @@ struct CsgLabel {
     grid_world(*g, gp, x);
     return csg_inside(prims, n, x);
   }
+  // CSG queries are per thread and cheap: none is skipped, so the query
+  // count stays exact without a per-thread counter
+  __device__ __forceinline__ bool skippable(int) const { return false; }
 };
 
 // wave-cooperative: every lane of the wave must call it together
@@ -574,6 +579,9 @@ struct MlpLabel {
     grid_world(*g, gp, x);
     return mlp_logit_fp32(*m, x, act) > 0.0f;
   }
+  // the wavefront evaluates together, so it skips only when no lane needs
+  // the answer
+  __device__ __forceinline__ bool skippable(int unneeded) const { return __all(unneeded); }
 };
 
 // ------------------------------------------------------------ (b) 1D points
@@ -754,7 +762,7 @@ struct LineBinary {
 // wavefront can batch each query across its lanes.  `lab` is called from
 // exactly one place.
 template <class Lab>
-__device__ double2 search_pair(const Job& j, const Lab& lab, int face, int slot) {
+__device__ double2 search_pair(const Job& j, const Lab& lab, int face, int slot, int& skipped) {
   const Grid& g = j.g;
   FaceFrame fr;
   face_pos(g, face, fr.a, fr.p);
@@ -774,6 +782,7 @@ __device__ double2 search_pair(const Job& j, const Lab& lab, int face, int slot)
   const int total = 1 + n1 + 2 * n2;
   LineBinary lb;
   int sm = 0;
+  skipped = 0;
   float q[2] = {m[0], m[1]}, q1[2] = {0, 0}, s1 = 0.0f;
   for (int step = 0; step < total; ++step) {
     // the query of this step
@@ -789,10 +798,18 @@ __device__ double2 search_pair(const Job& j, const Lab& lab, int face, int slot)
       s = lb.param(k);
       lb.point(s, P);
     }
-    float gp[3] = {(float)fr.p[0], (float)fr.p[1], (float)fr.p[2]};
-    add_at3(gp, fr.u, P[0]);
-    add_at3(gp, fr.v, P[1]);
-    const int l = lab(gp);
+    // a linear sample after the first label change cannot move the bracket
+    // (the change already fixed i*), so its query is skipped where the label
+    // functor allows; the bracket bookkeeping still runs (and ignores l)
+    int l = 0;
+    if (step == 0 || k >= lb.nl || !lab.skippable(lb.found)) {
+      float gp[3] = {(float)fr.p[0], (float)fr.p[1], (float)fr.p[2]};
+      add_at3(gp, fr.u, P[0]);
+      add_at3(gp, fr.v, P[1]);
+      l = lab(gp);
+    } else {
+      ++skipped;
+    }
     if (step == 0) {
       // step 1: the ray from m orthogonal to l, towards a corner whose label
       // differs from m's; when both sides qualify, the side of the corner the
@@ -865,7 +882,8 @@ __global__ __launch_bounds__(256) void k_search2d_csg(const Job* __restrict__ jo
             [&](const Job& J, int x) {
               CsgLabel lab{&J.g, J.prims, J.n_prims};
               const int rec = J.plist[x];
-              J.pf[x] = search_pair(J, lab, rec >> 1, rec & 1);
+              int skipped;
+              J.pf[x] = search_pair(J, lab, rec >> 1, rec & 1, skipped);
             });
 }
 
@@ -884,8 +902,12 @@ __global__ __launch_bounds__(256) void k_search2d_mlp(const Job* __restrict__ jo
               const bool valid = x < np;
               MlpLabel lab{&J.g, &J.mlp, act};
               const int rec = J.plist[valid ? x : np - 1];
-              const double2 r = search_pair(J, lab, rec >> 1, rec & 1);
+              int skipped;  // wave-uniform
+              const double2 r = search_pair(J, lab, rec >> 1, rec & 1, skipped);
               if (valid && lane < 32) J.pf[x] = r;
+              if (lane == 0 && skipped)
+                atomicAdd(&J.status[3],
+                          (unsigned long long)skipped * (unsigned long long)min(32, np - t * 32));
             });
 }
 

@@ -6,10 +6,12 @@
 // triangle is entered in each cube its bounding box overlaps, the entries are
 // sorted by cube, and each pair of entries of one cube is tested there only
 // if that cube holds the lowest corner of the two boxes' overlap, so every
-// pair is tested once.  The test is exact orientation arithmetic in binary64
-// on binary32 inputs (no rounding decides a sign except in degenerate,
-// touching configurations): a non-coplanar pair intersects iff an edge of
-// one meets the other closed triangle; a coplanar pair, iff an edge pair
+// pair is tested once.  The test takes orientation determinants in binary64
+// on binary32 inputs: the coordinate differences are exact (for coordinates
+// of like magnitude) and only the products round, so rounding can decide a
+// sign only for a nearly degenerate, touching configuration (a determinant
+// within ~2^-50 of its terms).  A non-coplanar pair intersects iff an edge
+// of one meets the other closed triangle; a coplanar pair, iff an edge pair
 // crosses or a corner of one lies in the other, in the plane's projection.
 #include <hip/hip_runtime.h>
 
@@ -145,6 +147,7 @@ __device__ bool triangles_meet(const double P[3][3], const double Q[3][3]) {
                         orient(P[0], P[1], P[2], Q[1]) == 0.0 &&
                         orient(P[0], P[1], P[2], Q[2]) == 0.0;
   if (!coplanar) {
+#pragma unroll
     for (int e = 0; e < 3; ++e) {
       if (segment_meets(P[e], P[(e + 1) % 3], Q[0], Q[1], Q[2])) return true;
       if (segment_meets(Q[e], Q[(e + 1) % 3], P[0], P[1], P[2])) return true;
@@ -157,21 +160,25 @@ __device__ bool triangles_meet(const double P[3][3], const double Q[3][3]) {
   const double n[3] = {fabs(u[1] * w[2] - u[2] * w[1]), fabs(u[2] * w[0] - u[0] * w[2]),
                        fabs(u[0] * w[1] - u[1] * w[0])};
   const int drop = n[0] >= n[1] && n[0] >= n[2] ? 0 : (n[1] >= n[2] ? 1 : 2);
-  const int i0 = drop == 0 ? 1 : 0, i1 = drop == 2 ? 1 : 2;
+  // kept coordinates i0 < i1 (selects, not indexing: the arrays stay in
+  // registers)
   double p2[3][2], q2[3][2];
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
-    p2[k][0] = P[k][i0];
-    p2[k][1] = P[k][i1];
-    q2[k][0] = Q[k][i0];
-    q2[k][1] = Q[k][i1];
+    p2[k][0] = drop == 0 ? P[k][1] : P[k][0];
+    p2[k][1] = drop == 2 ? P[k][1] : P[k][2];
+    q2[k][0] = drop == 0 ? Q[k][1] : Q[k][0];
+    q2[k][1] = drop == 2 ? Q[k][1] : Q[k][2];
   }
+#pragma unroll
   for (int e = 0; e < 3; ++e)
+#pragma unroll
     for (int f = 0; f < 3; ++f)
       if (segments_cross2(p2[e], p2[(e + 1) % 3], q2[f], q2[(f + 1) % 3])) return true;
   return in_triangle2(p2[0], q2) || in_triangle2(q2[0], p2);
 }
 
-__global__ void k_cube_pairs(const float* v, const int* t, float inv,
+__global__ void __launch_bounds__(256) k_cube_pairs(const float* v, const int* t, float inv,
                              const unsigned long long* keys, const int* vals, long long ne,
                              unsigned long long* count) {
   unsigned long long mine = 0;
@@ -184,7 +191,9 @@ __global__ void k_cube_pairs(const float* v, const int* t, float inv,
     for (long long j = i + 1; j < ne && keys[j] == key; ++j) {
       const int b = vals[j];
       bool shared = false;
+#pragma unroll
       for (int x = 0; x < 3; ++x)
+#pragma unroll
         for (int y = 0; y < 3; ++y) shared = shared || t[3 * (long long)a + x] == t[3 * (long long)b + y];
       if (shared) continue;
       float lb[3], hb[3];
@@ -199,7 +208,9 @@ __global__ void k_cube_pairs(const float* v, const int* t, float inv,
       }
       if (!overlap || cube_key(cm[0], cm[1], cm[2]) != key) continue;
       double P[3][3], Q[3][3];
+#pragma unroll
       for (int x = 0; x < 3; ++x)
+#pragma unroll
         for (int k = 0; k < 3; ++k) {
           P[x][k] = (double)v[3 * (long long)t[3 * (long long)a + x] + k];
           Q[x][k] = (double)v[3 * (long long)t[3 * (long long)b + x] + k];

@@ -56,7 +56,8 @@ class MeshBuffers(C.Structure):
 class MeshCounts(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "n_vertices", "n_triangles", "n_active_edges", "n_pairs", "n_active_cells", "n_case3",
-        "n_flipped_faces", "n_fp64_cells", "n_guard_corners", "n_queries")]
+        "n_flipped_faces", "n_fp64_cells", "n_guard_corners", "n_queries",
+        "n_search2d_queries")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}

@@ -164,3 +164,20 @@ def test_bf16_guarded_matches_fp32(ctx, res):
     assert b["n_guard_corners"] > 0
     assert np.array_equal(a["triangles"], b["triangles"])
     assert np.array_equal(a["vertices"], b["vertices"])
+
+
+def test_search2d_query_counts(ctx):
+    """The 2D searches skip a linear sample only when every pair of the
+    wavefront has seen its label change (the sample cannot move any bracket);
+    CSG searches skip none.  The reported count stays within what that
+    allows: at most lin1 - 1 + 2 (lin2 - 1) skipped per pair."""
+    g = I.unit_grid(40, 15)
+    per_pair = 1 + (g.lin1 + g.bin1) + 2 * (g.lin2 + g.bin2)
+    most = (g.lin1 - 1) + 2 * (g.lin2 - 1)
+    r, _ = gpu_run(I.csg_random_field(2), g, ctx=ctx, want_local=False)
+    assert r["n_search2d_queries"] == r["n_pairs"] * per_pair
+    r, _ = gpu_run(I.mlp_field(3), g, ctx=ctx, want_local=False)
+    n, q = r["n_pairs"], r["n_search2d_queries"]
+    print(f"mlp40: {q} 2D-search queries for {n} pairs ({q / n:.2f} per pair of {per_pair})")
+    assert n * (per_pair - most) <= q < n * per_pair
+    assert r["n_queries"] == (41 ** 3 + r["n_guard_corners"] + r["n_active_edges"] * 15 + q)
