@@ -53,3 +53,35 @@ def test_missing_library_fails_loudly(tmp_path):
             odc.load(str(tmp_path / "nope.so"))
         finally:
             odc._lib = odc._lib_backup
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every struct the binding mirrors has the header's size and member
+    offsets (a C program built against include/odc.h prints them)."""
+    import shutil
+    import subprocess
+    from paper_2409_13418_amd import odc
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirrors = {"odc_field": odc.Field, "odc_params": odc.Params,
+               "odc_mesh_buffers": odc.MeshBuffers, "odc_mesh_counts": odc.MeshCounts,
+               "odc_server_config": odc.ServerConfig, "odc_request_result": odc.RequestResult,
+               "odc_server_stats": odc.ServerStats}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "odc.h"', "int main(void) {"]
+    for cname, cls in mirrors.items():
+        lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                       text=True).stdout.splitlines())
+    for cname, cls in mirrors.items():
+        assert int(got[cname]) == C.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(cls, f).offset, (cname, f)

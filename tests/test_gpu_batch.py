@@ -34,7 +34,7 @@ def _alone(odc, jobs):
     for f, g, prec in jobs:
         r = ctx.extract(odc.DeviceField(f), odc.default_params(g, prec))
         res.append((r["vertices"].cpu().numpy().copy(), r["triangles"].cpu().numpy().copy(),
-                    r["n_active_cells"]))
+                    (r["n_active_cells"], r["n_search2d_queries"], r["n_guard_corners"])))
     ctx.close()
     return res
 
@@ -47,7 +47,9 @@ def test_batch_equals_alone(odc):
     ps = [odc.default_params(g, prec) for _, g, prec in jobs]
     out = ctx.extract_batch(dfs, ps)
     for k, (v, t, nc) in enumerate(ref):
-        assert out[k]["n_active_cells"] == nc, k
+        # the per-job counters (cleared inside the pipeline) match too
+        assert (out[k]["n_active_cells"], out[k]["n_search2d_queries"],
+                out[k]["n_guard_corners"]) == nc, k
         assert np.array_equal(out[k]["vertices"].cpu().numpy(), v), k
         assert np.array_equal(out[k]["triangles"].cpu().numpy(), t), k
     ctx.close()
@@ -63,6 +65,8 @@ def test_graph_replay_matches(odc):
     for rep in range(3):
         out = ctx.extract_batch(dfs, ps)
         for k, (v, t, nc) in enumerate(ref):
+            assert (out[k]["n_active_cells"], out[k]["n_search2d_queries"],
+                    out[k]["n_guard_corners"]) == nc, (rep, k)
             assert np.array_equal(out[k]["vertices"].cpu().numpy(), v), (rep, k)
             assert np.array_equal(out[k]["triangles"].cpu().numpy(), t), (rep, k)
     # same structure, other fields: the captured graph serves them too

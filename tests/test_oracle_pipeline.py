@@ -82,3 +82,34 @@ def test_mlp_small_pipeline(oracle_mod):
         vb = m["cell_vbase"][x]
         assert n == m["cell_npart"][x] and pm == m["cell_partmap"][x]
         assert np.array_equal(v, m["vert"][vb:vb + n])
+
+
+def test_oracle_struct_layouts_match_its_header(tmp_path):
+    """The oracle's ctypes mirrors have the C header's sizes and offsets."""
+    import ctypes as C
+    import os
+    import shutil
+    import subprocess
+    from oracle import oracle as O
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirrors = {"orc_field": O._Field, "orc_params": O._Params, "orc_mesh": O._Mesh}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "odc_oracle.h"',
+             "int main(void) {"]
+    for cname, cls in mirrors.items():
+        lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle")
+    subprocess.run([cc, "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = dict(line.split() for line in out.splitlines())
+    for cname, cls in mirrors.items():
+        assert int(got[cname]) == C.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(cls, f).offset, (cname, f)
