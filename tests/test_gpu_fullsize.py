@@ -180,3 +180,39 @@ def test_mlp256_bf16_equals_fp32(ctx, mlp256):
     assert np.array_equal(ra["triangles"], rb["triangles"])
     assert np.array_equal(ra["vertices"], rb["vertices"])
     assert rb["n_guard_corners"] > 0
+
+
+def test_sdf256_bf16_equals_fp32_and_sampled_labels(ctx, oracle_mod):
+    """The SDF input at 256^3 (the benchmark's zero set, logit 20 times
+    flatter): the guard band then holds far more corners, and the guarded
+    bf16 path must still give the fp32 path's mesh bit for bit; sampled
+    corner labels next to the surface match the oracle (tie band scaled by
+    the field's 1/20)."""
+    f = I.sdf_mlp_field(3)
+    g = I.unit_grid(256, 15)
+    rb, _ = gpu_run(f, g, precision=1, ctx=ctx, want_local=False)
+    ra, _ = gpu_run(f, g, precision=0, ctx=ctx, want_local=False)
+    assert np.array_equal(ra["corner_label"], rb["corner_label"])
+    assert np.array_equal(ra["triangles"], rb["triangles"])
+    assert np.array_equal(ra["vertices"], rb["vertices"])
+    ok, why = M.is_closed_oriented_manifold(rb["triangles"], rb["n_vertices"])
+    assert ok, why
+    o = oracle_mod.Oracle(f, g, mlp_tie_eps=MLP_TIE / 20)
+    n1 = g.res + 1
+    rng = np.random.default_rng(13)
+    ea = g.res * n1 * n1
+    ties = 0
+    for e in rb["edge_ids"][rng.integers(0, len(rb["edge_ids"]), 750)]:
+        a, loc = int(e) // ea, int(e) % ea
+        dims = [n1, n1, n1]
+        dims[a] = g.res
+        p = [loc % dims[0], (loc // dims[0]) % dims[1], loc // (dims[0] * dims[1])]
+        for end in range(2):
+            q = list(p)
+            q[a] += end
+            lab, tie = o.corner_label(*q)
+            ties += tie
+            c = q[0] + n1 * (q[1] + n1 * q[2])
+            assert tie or rb["corner_label"][c] == lab, c
+    print(f"sdf256: {rb['n_guard_corners']} guard corners (of {n1 ** 3}), "
+          f"1500 sampled corners, {ties} near-ties")
