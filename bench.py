@@ -26,7 +26,10 @@ Other modes (not run by default):
                 batching server; p50/p99 latency (completion - arrival) and
                 active cells/s over the requests after a 10 s warm-up;
                 --serve-policy shortest admits the cheapest queued job first
-                (a job older than --serve-age-ms goes first regardless).
+                (a job older than --serve-age-ms goes first regardless);
+                banded (the default) also keeps jobs estimated at more than
+                --serve-band times a batch's first job out of that batch;
+                fifo admits in arrival order.
 """
 from __future__ import annotations
 
@@ -223,9 +226,11 @@ def _serve_mode(args):
             params[(kind, res)] = odc.default_params(
                 I.unit_grid(res, 15), prec if kind == 1 else odc.PREC_FP32)
     ctx = odc.Context(0)
-    policy = odc.SERVE_SHORTEST if args.serve_policy == "shortest" else odc.SERVE_FIFO
+    policy = {"fifo": odc.SERVE_FIFO, "shortest": odc.SERVE_SHORTEST,
+              "banded": odc.SERVE_BANDED}[args.serve_policy]
     srv = odc.Server(ctx, int(args.serve_budget_gib * (1 << 30)), lanes=args.serve_lanes,
-                     max_batch=16, policy=policy, age_ms=args.serve_age_ms)
+                     max_batch=16, policy=policy, age_ms=args.serve_age_ms,
+                     band=args.serve_band)
     free_bufs = {}
     lock = threading.Lock()
 
@@ -297,7 +302,8 @@ def _serve_mode(args):
                    {"64": 0.4, "128": 0.3, "256": 0.2, "512": 0.1}, "lanes": args.serve_lanes,
                    "budget_gib": args.serve_budget_gib, "field_pool": pool,
                    "policy": args.serve_policy,
-                   "age_ms": args.serve_age_ms if args.serve_policy == "shortest" else None},
+                   "age_ms": args.serve_age_ms if args.serve_policy != "fifo" else None,
+                   "band": args.serve_band if args.serve_policy == "banded" else None},
         "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
         "max_ms": st["max_ms"], "completed": st["completed"], "failed": len(bad),
         "batches": st["batches"], "window_s": st["window_s"], "wall_s": wall,
@@ -400,7 +406,8 @@ def main():
     ap.add_argument("--serve-warmup-s", type=float, default=10.0)
     ap.add_argument("--serve-lanes", type=int, default=2)
     ap.add_argument("--serve-budget-gib", type=float, default=24.0)
-    ap.add_argument("--serve-policy", choices=("fifo", "shortest"), default="fifo")
+    ap.add_argument("--serve-policy", choices=("fifo", "shortest", "banded"), default="banded")
+    ap.add_argument("--serve-band", type=float, default=8.0)
     ap.add_argument("--serve-age-ms", type=float, default=1000.0)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)

@@ -289,16 +289,20 @@ typedef struct odc_server odc_server;
  * free arena blocks the jobs behind it.  SHORTEST: the queued job with the
  * smallest estimated work first (grid corners plus crossing-edge searches,
  * weighted by field kind), skipping jobs that do not fit; a job waiting
- * longer than age_ms goes before all others and is not skipped. */
-enum { ODC_SERVE_FIFO = 0, ODC_SERVE_SHORTEST = 1 };
+ * longer than age_ms goes before all others and is not skipped.  BANDED:
+ * SHORTEST, and a batch also skips jobs estimated at more than `band` times
+ * its first job (a batch ends with its slowest job, so small jobs are not
+ * held behind large ones); aged jobs are never skipped. */
+enum { ODC_SERVE_FIFO = 0, ODC_SERVE_SHORTEST = 1, ODC_SERVE_BANDED = 2 };
 
 typedef struct {
   int64_t hbm_budget_bytes;  /* scratch arena (>= 1 MiB) */
   int32_t n_lanes;           /* batches in flight at once, 1..8; 0 = 2 */
   int32_t max_batch;         /* jobs per batch; 0 = 16 */
   int64_t max_batch_corners; /* grid corners per batch; 0 = 2^25 */
-  int32_t policy;            /* ODC_SERVE_FIFO (0) or ODC_SERVE_SHORTEST */
-  float age_ms;              /* SHORTEST: waiting time that promotes a job; 0 = 1000 */
+  int32_t policy;            /* ODC_SERVE_FIFO (0), ODC_SERVE_SHORTEST or ODC_SERVE_BANDED */
+  float age_ms;              /* SHORTEST, BANDED: waiting time that promotes a job; 0 = 1000 */
+  float band;                /* BANDED: cost ratio a batch admits (> 1); 0 = 8 */
 } odc_server_config;
 
 typedef struct {

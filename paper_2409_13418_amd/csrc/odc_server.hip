@@ -217,14 +217,15 @@ static double job_cost(const odc_field& f, const odc_params& p) {
 }
 
 // Admits queued jobs into an idle lane (lock held): in arrival order
-// (FIFO), or cheapest first with aged jobs ahead of all (SHORTEST).
-// Returns true when a batch was launched.
+// (FIFO), or cheapest first with aged jobs ahead of all (SHORTEST, BANDED;
+// BANDED also leaves out jobs estimated at more than `band` times the
+// batch's first job).  Returns true when a batch was launched.
 static bool admit(odc_server* s, Lane& L) {
   std::vector<Request*> batch;
   int64_t corners = 0;
   std::vector<size_t> order(s->queue.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = i;
-  if (s->conf.policy == ODC_SERVE_SHORTEST) {
+  if (s->conf.policy != ODC_SERVE_FIFO) {
     const double now = ms_since(s->t0);
     auto aged = [&](const Request* r) { return now - r->res.submit_ms > s->conf.age_ms; };
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
@@ -248,6 +249,9 @@ static bool admit(odc_server* s, Lane& L) {
       if (must) break;
       continue;
     }
+    if (s->conf.policy == ODC_SERVE_BANDED && !must && !batch.empty() &&
+        r->cost > (double)s->conf.band * batch.front()->cost)
+      continue;
     if (!s->arena.alloc(r->bytes, &r->off)) {
       if (must) break;  // wait for memory rather than pass this job
       continue;
@@ -362,9 +366,12 @@ extern "C" int32_t odc_server_create(odc_context* ctx, const odc_server_config* 
   if (c.max_batch == 0) c.max_batch = 16;
   if (c.max_batch_corners == 0) c.max_batch_corners = (int64_t)1 << 25;
   if (c.age_ms == 0.0f) c.age_ms = 1000.0f;
+  if (c.band == 0.0f) c.band = 8.0f;
   if (c.hbm_budget_bytes < (1 << 20) || c.n_lanes < 1 || c.n_lanes > 8 || c.max_batch < 1 ||
       c.max_batch > kMaxJobs || c.max_batch_corners < 1 ||
-      (c.policy != ODC_SERVE_FIFO && c.policy != ODC_SERVE_SHORTEST) || !(c.age_ms > 0.0f))
+      (c.policy != ODC_SERVE_FIFO && c.policy != ODC_SERVE_SHORTEST &&
+       c.policy != ODC_SERVE_BANDED) ||
+      !(c.age_ms > 0.0f) || !(c.band > 1.0f))
     return ctx_fail(ctx, ODC_ERR_INVALID_ARG,
                     "server needs a budget >= 1 MiB, 1..8 lanes, 1..%d jobs per batch, "
                     "a known policy and age_ms > 0",

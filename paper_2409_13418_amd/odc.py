@@ -63,13 +63,14 @@ class MeshCounts(C.Structure):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
 
 
-SERVE_FIFO, SERVE_SHORTEST = 0, 1
+SERVE_FIFO, SERVE_SHORTEST, SERVE_BANDED = 0, 1, 2
 ABL_LINEAR_1D, ABL_GRAD_NORMALS, ABL_MDC_SPLIT, ABL_SDF_INPUT = 1, 2, 4, 8
 
 
 class ServerConfig(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_int64), ("n_lanes", C.c_int32), ("max_batch", C.c_int32),
-                ("max_batch_corners", C.c_int64), ("policy", C.c_int32), ("age_ms", C.c_float)]
+                ("max_batch_corners", C.c_int64), ("policy", C.c_int32), ("age_ms", C.c_float),
+                ("band", C.c_float)]
 
 
 class RequestResult(C.Structure):
@@ -480,11 +481,12 @@ class Server:
     to the objects it is given until then."""
 
     def __init__(self, ctx: Context, hbm_budget_bytes: int, lanes: int = 2, max_batch: int = 16,
-                 max_batch_corners: int = 0, policy: int = SERVE_FIFO, age_ms: float = 0.0):
+                 max_batch_corners: int = 0, policy: int = SERVE_FIFO, age_ms: float = 0.0,
+                 band: float = 0.0):
         L = load()
         self.ctx = ctx
         cfg = ServerConfig(int(hbm_budget_bytes), int(lanes), int(max_batch),
-                           int(max_batch_corners), int(policy), float(age_ms))
+                           int(max_batch_corners), int(policy), float(age_ms), float(band))
         h = C.c_void_p()
         rc = L.odc_server_create(ctx.h, C.byref(cfg), C.byref(h))
         if rc != OK:

@@ -180,4 +180,40 @@ def test_shortest_first_and_aging(odc):
     with pytest.raises(odc.OdcError) as e:
         odc.Server(ctx, 1 << 28, policy=7)
     assert e.value.status == odc.ERR_INVALID_ARG
+    with pytest.raises(odc.OdcError) as e:
+        odc.Server(ctx, 1 << 28, policy=odc.SERVE_BANDED, band=0.5)
+    assert e.value.status == odc.ERR_INVALID_ARG
+    ctx.close()
+
+
+def test_banded_keeps_large_jobs_out_of_small_batches(odc):
+    """BANDED batches a cheap job without a queued job of more than 8 times
+    its estimated work (SHORTEST batches both); the meshes are unchanged."""
+    ctx = odc.Context(0)
+    blocker = (odc.DeviceField(I.mlp_field(5300)), odc.default_params(I.unit_grid(160, 15), 0))
+    big = (odc.DeviceField(I.mlp_field(5301)), odc.default_params(I.unit_grid(96, 15), 0))
+    small = (odc.DeviceField(I.csg_random_field(5302)), odc.default_params(I.unit_grid(24, 15), 0))
+    ref = {}
+    for name, (df, p) in (("big", big), ("small", small)):
+        r = ctx.extract(df, p)
+        ref[name] = (r["vertices"].cpu().numpy().copy(), r["triangles"].cpu().numpy().copy())
+    for policy in (odc.SERVE_SHORTEST, odc.SERVE_BANDED):
+        srv = odc.Server(ctx, 1 << 31, lanes=1, max_batch=16, policy=policy, age_ms=60000.0)
+        ob = odc.OutputBuffers(1 << 20, 1 << 21)
+        tb = srv.submit(blocker[0], blocker[1], ob)
+        outs = {n: odc.OutputBuffers(len(ref[n][0]) + 16, len(ref[n][1]) + 16) for n in ref}
+        tg = srv.submit(big[0], big[1], outs["big"])
+        ts = srv.submit(small[0], small[1], outs["small"])
+        rb, rg, rs = srv.wait(tb), srv.wait(tg), srv.wait(ts)
+        srv.close()
+        assert rb["status"] == rg["status"] == rs["status"] == odc.OK
+        assert rb["done_ms"] >= max(rg["submit_ms"], rs["submit_ms"])
+        for n, r in (("big", rg), ("small", rs)):
+            got = outs[n].views(r)
+            assert np.array_equal(got["vertices"].cpu().numpy(), ref[n][0]), (policy, n)
+            assert np.array_equal(got["triangles"].cpu().numpy(), ref[n][1]), (policy, n)
+        if policy == odc.SERVE_SHORTEST:
+            assert rg["admit_ms"] == rs["admit_ms"]          # one batch
+        else:
+            assert rg["admit_ms"] >= rs["done_ms"]           # the small job's batch ran alone
     ctx.close()
