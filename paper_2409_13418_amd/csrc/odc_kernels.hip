@@ -310,44 +310,59 @@ __global__ __launch_bounds__(256) void k_labels_csg(const Job* __restrict__ jobs
             });
 }
 
-// MLP corners, 32 per wavefront: fp32, or bf16 with the guard-band corners
-// queued for fp32 re-evaluation
+// MLP corners, 32 per wavefront.  fp32: each wavefront takes label words on
+// its own.  bf16 (guard-band corners queued for fp32 re-evaluation): the four
+// wavefronts of a workgroup share one weight stream, so they take four
+// consecutive words together (workgroup-uniform units, a wavefront past the
+// end evaluating a clamped dummy) and every call of the shared evaluator is
+// made by all four.
 template <int BF16>
 __global__ __launch_bounds__(256) void k_labels_mlp(const Job* __restrict__ jobs, int njobs) {
+  static_assert(kBlock == 256, "the shared bf16 stream takes four wavefronts");
   __shared__ __align__(16) float act_lds[kBlock / 64][BF16 ? kActWordsBF16 : kActWords];
-  float* act = act_lds[threadIdx.x >> 6];
-  for_units(jobs, njobs, gwave(), nwaves(),
-            [](const Job& J) { return (J.kind == 1 && J.precision == BF16) ? J.nw_c : 0; },
-            [&](const Job& J, int t) {
-              const Grid& g = J.g;
-              const int lane = lane_id();
-              const int c = t * 32 + (lane & 31);
-              const bool valid = c < g.nc;
-              const int cc = valid ? c : g.nc - 1;
-              const int n1 = g.N + 1;
-              const float gp[3] = {(float)(cc % n1), (float)((cc / n1) % n1),
-                                   (float)(cc / (n1 * n1))};
-              float x[3];
-              grid_world(g, gp, x);
-              const float z = BF16 ? mlp_logit_bf16(J.mlp, x, act)
-                                   : mlp_logit_fp32(J.mlp, x, act);
-              const uint64_t b = __ballot(valid && z > 0.0f);
-              if (lane == 0) J.labels[t] = (uint32_t)b;
-              if (BF16) {
-                const bool q = valid && lane < 32 && fabsf(z) < J.guard_logit;
-                const uint64_t qb = __ballot(q);
-                if (qb) {
-                  unsigned long long base = 0;
-                  if (lane == 0) base = atomicAdd(&J.status[0], (unsigned long long)__popcll(qb));
-                  base = __shfl(base, 0);
-                  if (q) {
-                    const unsigned long long r = base + __popcll(qb & ((1ull << lane) - 1ull));
-                    if (r < (unsigned long long)J.guard_cap) J.guard_list[r] = (uint32_t)c;
-                    else J.status[2] = 1;  // queue full: rerun with room for every corner
-                  }
-                }
-              }
-            });
+  __shared__ __align__(16) v8bf wslots[BF16 ? kSharedSlots * 8 * 64 : 1];
+  // wave-uniform (the loads' scalar offsets depend on it)
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  float* act = act_lds[wave];
+  auto body = [&](const Job& J, int t) {
+    const Grid& g = J.g;
+    const int lane = lane_id();
+    const bool unit = t < J.nw_c;
+    const int c = t * 32 + (lane & 31);
+    const bool valid = unit && c < g.nc;
+    const int cc = valid ? c : g.nc - 1;
+    const int n1 = g.N + 1;
+    const float gp[3] = {(float)(cc % n1), (float)((cc / n1) % n1), (float)(cc / (n1 * n1))};
+    float x[3];
+    grid_world(g, gp, x);
+    const float z = BF16 ? mlp_logit_bf16_shared(J.mlp, x, act, wslots, wave)
+                         : mlp_logit_fp32(J.mlp, x, act);
+    const uint64_t b = __ballot(valid && z > 0.0f);
+    if (unit && lane == 0) J.labels[t] = (uint32_t)b;
+    if (BF16) {
+      const bool q = valid && lane < 32 && fabsf(z) < J.guard_logit;
+      const uint64_t qb = __ballot(q);
+      if (qb) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(&J.status[0], (unsigned long long)__popcll(qb));
+        base = __shfl(base, 0);
+        if (q) {
+          const unsigned long long r = base + __popcll(qb & ((1ull << lane) - 1ull));
+          if (r < (unsigned long long)J.guard_cap) J.guard_list[r] = (uint32_t)c;
+          else J.status[2] = 1;  // queue full: rerun with room for every corner
+        }
+      }
+    }
+  };
+  const auto mine = [](const Job& J) { return J.kind == 1 && J.precision == BF16; };
+  if constexpr (BF16) {
+    for_units(jobs, njobs, (int)blockIdx.x, (int)gridDim.x,
+              [&](const Job& J) { return mine(J) ? (J.nw_c + 3) >> 2 : 0; },
+              [&](const Job& J, int grp) { body(J, 4 * grp + wave); });
+  } else {
+    for_units(jobs, njobs, gwave(), nwaves(),
+              [&](const Job& J) { return mine(J) ? J.nw_c : 0; }, body);
+  }
 }
 
 // fp32 re-evaluation of the corners queued by the bf16 pass

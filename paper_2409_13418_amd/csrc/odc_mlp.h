@@ -549,4 +549,154 @@ __device__ __forceinline__ float mlp_logit_bf16(const Mlp& M, const float x[3],
   return mlp_output(M, acc, h, zero, x);
 }
 
+// The bf16 evaluation above with the weight stream shared by the four
+// wavefronts of a 256-thread workgroup.  There each wavefront streams every
+// weight fragment itself; the vector memory path (address unit busy ~80% of
+// the time) then limits the corner pass.  Here each K block (8 tiles x 64
+// lanes x 16 B = 8 KB) is loaded once per workgroup, each wavefront loading
+// two of its tiles, and staged through a ring of kSharedSlots LDS slots from
+// which all four wavefronts read their fragments: one 16-byte load per lane
+// per block instead of four.  Per block b: (i) LDS wait + workgroup barrier;
+// (ii) read block b + 1's fragments from its slot; (iii) store block b + 2
+// (loaded four blocks earlier) into its slot, the one block b - 1 occupied;
+// (iv) load block b + 6 into the freed staging registers; (v) the block's
+// matrix instructions.  The barrier orders every wavefront's reads of a
+// slot before its next store, and every store before its first read.  The
+// operands, the matrix instructions and their order are those of
+// mlp_logit_bf16, so the logit is the same bit for bit.
+//
+// All four wavefronts of the workgroup must call it together, for the same
+// field, the same number of times (one barrier per K block and one more per
+// call); `slots` is the workgroup's kSharedSlots x 8 x 64 fragment array
+// and `wave` the wavefront's index in the workgroup.
+constexpr int kSharedSlots = 3;
+constexpr int kStageBF16 = 4;  // blocks in flight in registers (as ring slots: static indices)
+static_assert(kStageBF16 == kPrefetchBF16, "layer-1 and hidden K blocks come in groups of 4");
+
+__device__ __forceinline__ void lds_block_sync() {
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+__device__ __forceinline__ float mlp_logit_bf16_shared(const Mlp& M, const float x[3],
+                                                       float* __restrict__ act,
+                                                       v8bf* __restrict__ slots, int wave) {
+  const int lane = lane_id();
+  const int h = lane >> 5;
+  int zero = 0;  // keeps the stream prologue here (see mlp_logit_fp32)
+  asm volatile("" : "+v"(zero));
+  v4f* act4 = reinterpret_cast<v4f*>(act);
+  v4f* tab4 = act4 + kGroupsF32 * 64;
+  const ODC_GLOBAL v4f* Bg = (const ODC_GLOBAL v4f*)gmem(M.bias) + lane + zero;
+  v4f tb = Bg[0];
+  // the stream ends kPrefetchBF16 blocks past the last K block; loads past
+  // the resource's size return zeros, which no matrix instruction reads
+  const __amdgpu_buffer_rsrc_t ws = weight_stream(
+      M.w1b, ((size_t)M.kb1b + (size_t)(M.depth - 1) * kHiddenBlocksBF16 + kPrefetchBF16) * 8192);
+  const int voff = (lane + zero) * 16;
+  // tile 2 wave + j of K block b (this wavefront's quarter)
+  auto Q = [&](int b, int j) -> v8bf {
+    return __builtin_bit_cast(
+        v8bf, __builtin_amdgcn_raw_buffer_load_b128(ws, voff, (b * 8 + 2 * wave + j) * 1024, 0));
+  };
+  auto slot = [&](int b, int R) -> v8bf* {
+    return slots + ((b % kSharedSlots) * 8 + R) * 64 + lane;
+  };
+  // prologue: blocks 0 and 1 into their slots, 2..5 in flight
+  {
+    const v8bf a0 = Q(0, 0), a1 = Q(0, 1), b0 = Q(1, 0), b1 = Q(1, 1);
+    *slot(0, 2 * wave) = a0;
+    *slot(0, 2 * wave + 1) = a1;
+    *slot(1, 2 * wave) = b0;
+    *slot(1, 2 * wave + 1) = b1;
+  }
+  v8bf st[kStageBF16][2];
+#pragma unroll
+  for (int d = 0; d < kStageBF16; ++d) {
+    // block 2 + d sits in entry (2 + d) % 4
+    st[(2 + d) % kStageBF16][0] = Q(2 + d, 0);
+    st[(2 + d) % kStageBF16][1] = Q(2 + d, 1);
+  }
+  lds_block_sync();
+  v8bf wr[8], wn[8];
+#pragma unroll
+  for (int R = 0; R < 8; ++R) wr[R] = *slot(0, R);
+  // one K block of the stream (d = b % 4, static): steps (i)-(iv); the
+  // caller then issues the matrix instructions with wr and sets wr = wn
+  auto advance = [&](int b, int d) {
+    lds_block_sync();
+#pragma unroll
+    for (int R = 0; R < 8; ++R) wn[R] = *slot(b + 1, R);
+    const int e = (d + 2) % kStageBF16;
+    *slot(b + 2, 2 * wave) = st[e][0];
+    *slot(b + 2, 2 * wave + 1) = st[e][1];
+    st[e][0] = Q(b + 6, 0);
+    st[e][1] = Q(b + 6, 1);
+  };
+  const v16f zacc = {};
+  v16f acc[8];
+  const float quarter_h = h ? 0.25f : 0.0f;
+  auto features = [&](int b) {
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    v4u p;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      p[j] = pack_bf16(pair_feature_fast(8 * b + 2 * j, quarter_h, h, x),
+                       pair_feature_fast(8 * b + 2 * j + 1, quarter_h, h, x));
+    return __builtin_bit_cast(v8bf, p);
+  };
+  const int ng = M.kb1b / kPrefetchBF16;
+  v8bf bv = features(0);
+#pragma unroll
+  for (int gi = 0; gi < kMaxGroups1BF16; ++gi) {
+    if (gi == 0 || gi < ng) {
+#pragma unroll
+      for (int d = 0; d < kPrefetchBF16; ++d) {
+        const int b = gi * kPrefetchBF16 + d;
+        advance(b, d);
+#pragma unroll
+        for (int R = 0; R < 8; ++R)
+          acc[R] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[R], bv, b == 0 ? zacc : acc[R],
+                                                           0, 0, 0);
+        bv = features(b + 1);
+#pragma unroll
+        for (int R = 0; R < 8; ++R) wr[R] = wn[R];
+      }
+    }
+  }
+  for (int l = 1; l < M.depth; ++l) {
+    // park layer l's pre-activations and biases; fetch layer l+1's biases
+#pragma unroll
+    for (int T = 0; T < 8; ++T)
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        act4[(4 * T + g) * 64 + lane] =
+            (v4f){acc[T][4 * g], acc[T][4 * g + 1], acc[T][4 * g + 2], acc[T][4 * g + 3]};
+    tab4[lane] = tb;
+    tb = Bg[(size_t)l * 64];
+    const int base = M.kb1b + (l - 1) * kHiddenBlocksBF16;
+    bv = bf16_operand(act4[lane], act4[64 + lane], tab4[h], tab4[2 + h]);
+#pragma unroll
+    for (int b0 = 0; b0 < kHiddenBlocksBF16; b0 += kPrefetchBF16) {
+#pragma unroll
+      for (int d = 0; d < kPrefetchBF16; ++d) {
+        const int b = b0 + d;
+        advance(base + b, d);
+        const int bn = (b + 1) & (kHiddenBlocksBF16 - 1);
+        const v4f a0 = act4[(2 * bn) * 64 + lane], a1 = act4[(2 * bn + 1) * 64 + lane];
+        const v4f t0 = tab4[4 * bn + h], t1 = tab4[4 * bn + 2 + h];
+#pragma unroll
+        for (int R = 0; R < 8; ++R)
+          acc[R] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[R], bv, b == 0 ? zacc : acc[R],
+                                                           0, 0, 0);
+        bv = bf16_operand(a0, a1, t0, t1);
+#pragma unroll
+        for (int R = 0; R < 8; ++R) wr[R] = wn[R];
+      }
+    }
+  }
+  return mlp_output(M, acc, h, zero, x);
+}
+
 }  // namespace odc
