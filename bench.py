@@ -478,6 +478,23 @@ def main():
         flop = nc * per_query
         peak = PEAK_BF16_MFMA if prec == odc.PREC_BF16_GUARDED else PEAK_FP32_MFMA
     achieved = flop / (stages[dom] / 1e3) / 1e12
+    # every matrix-core stage against its own precision's peak, and the
+    # whole extraction: the time the stages would take at peak over the
+    # measured time of all stages (the classification, scan, QEF and
+    # emission passes count as time with no matrix work)
+    nc = (grid.res + 1) ** 3
+    bf16 = prec == odc.PREC_BF16_GUARDED
+    at_peak = {
+        "labels": nc * per_query / (PEAK_BF16_MFMA if bf16 else PEAK_FP32_MFMA)
+        + counts["n_guard_corners"] * per_query / PEAK_FP32_MFMA,
+        "bisect": counts["n_active_edges"] * grid.iters_1d * per_query / PEAK_FP32_MFMA,
+        "search2d": counts["n_search2d_queries"] * per_query / PEAK_FP32_MFMA,
+    }
+    roofline_stages = {k: {"ms": stages[k], "ms_at_peak": v * 1e3, "frac": v * 1e3 / stages[k]}
+                       for k, v in at_peak.items()}
+    roofline_stages["extraction"] = {
+        "ms": sum(stages.values()), "ms_at_peak": sum(at_peak.values()) * 1e3,
+        "frac": sum(at_peak.values()) * 1e3 / sum(stages.values())}
     roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak / 1e12,
                 "unit": "TFLOP/s", "frac": achieved * 1e12 / peak,
                 "traffic": measured_traffic(dom) if prec == odc.PREC_BF16_GUARDED else None}
@@ -499,6 +516,7 @@ def main():
                                           "n_fp64_cells")},
         "stages_ms": stages,
         "roofline": roofline,
+        "roofline_stages": roofline_stages,
     }
     out["quality"] = mesh_quality(ctx, df, grid, params=params)
     if not args.no_cpu_baseline:
