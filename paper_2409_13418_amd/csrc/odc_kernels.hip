@@ -312,18 +312,18 @@ __global__ __launch_bounds__(256) void k_labels_csg(const Job* __restrict__ jobs
 
 // MLP corners, 32 per wavefront.  fp32: each wavefront takes label words on
 // its own.  bf16 (guard-band corners queued for fp32 re-evaluation): the four
-// wavefronts of a workgroup share one weight stream, so they take four
-// consecutive words together (workgroup-uniform units, a wavefront past the
-// end evaluating a clamped dummy) and every call of the shared evaluator is
-// made by all four.
+// wavefronts of a workgroup evaluate their 128 corners together, split by
+// output tiles (mlp_logit_bf16_split), so they take four consecutive words
+// together (workgroup-uniform units, a wavefront past the end evaluating a
+// clamped dummy) and every call is made by all four.
 template <int BF16>
 __global__ __launch_bounds__(256) void k_labels_mlp(const Job* __restrict__ jobs, int njobs) {
-  static_assert(kBlock == 256, "the shared bf16 stream takes four wavefronts");
-  __shared__ __align__(16) float act_lds[kBlock / 64][BF16 ? kActWordsBF16 : kActWords];
-  __shared__ __align__(16) v8bf wslots[BF16 ? kSharedSlots * 8 * 64 : 1];
+  static_assert(kBlock == 256, "the split bf16 evaluation takes four wavefronts");
+  __shared__ __align__(16) float act_lds[BF16 ? 1 : kBlock / 64][BF16 ? 4 : kActWords];
+  __shared__ __align__(16) char split_lds[BF16 ? kSplitLdsBytes : 16];
   // wave-uniform (the loads' scalar offsets depend on it)
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  float* act = act_lds[wave];
+  float* act = act_lds[BF16 ? 0 : wave];
   auto body = [&](const Job& J, int t) {
     const Grid& g = J.g;
     const int lane = lane_id();
@@ -335,7 +335,7 @@ __global__ __launch_bounds__(256) void k_labels_mlp(const Job* __restrict__ jobs
     const float gp[3] = {(float)(cc % n1), (float)((cc / n1) % n1), (float)(cc / (n1 * n1))};
     float x[3];
     grid_world(g, gp, x);
-    const float z = BF16 ? mlp_logit_bf16_shared(J.mlp, x, act, wslots, wave)
+    const float z = BF16 ? mlp_logit_bf16_split(J.mlp, x, split_lds, wave)
                          : mlp_logit_fp32(J.mlp, x, act);
     const uint64_t b = __ballot(valid && z > 0.0f);
     if (unit && lane == 0) J.labels[t] = (uint32_t)b;

@@ -549,154 +549,173 @@ __device__ __forceinline__ float mlp_logit_bf16(const Mlp& M, const float x[3],
   return mlp_output(M, acc, h, zero, x);
 }
 
-// The bf16 evaluation above with the weight stream shared by the four
-// wavefronts of a 256-thread workgroup.  There each wavefront streams every
-// weight fragment itself; the vector memory path (address unit busy ~80% of
-// the time) then limits the corner pass.  Here each K block (8 tiles x 64
-// lanes x 16 B = 8 KB) is loaded once per workgroup, each wavefront loading
-// two of its tiles, and staged through a ring of kSharedSlots LDS slots from
-// which all four wavefronts read their fragments: one 16-byte load per lane
-// per block instead of four.  Per block b: (i) LDS wait + workgroup barrier;
-// (ii) read block b + 1's fragments from its slot; (iii) store block b + 2
-// (loaded four blocks earlier) into its slot, the one block b - 1 occupied;
-// (iv) load block b + 6 into the freed staging registers; (v) the block's
-// matrix instructions.  The barrier orders every wavefront's reads of a
-// slot before its next store, and every store before its first read.  The
-// operands, the matrix instructions and their order are those of
-// mlp_logit_bf16, so the logit is the same bit for bit.
-//
-// All four wavefronts of the workgroup must call it together, for the same
-// field, the same number of times (one barrier per K block and one more per
-// call); `slots` is the workgroup's kSharedSlots x 8 x 64 fragment array
-// and `wave` the wavefront's index in the workgroup.
-constexpr int kSharedSlots = 3;
-constexpr int kStageBF16 = 4;  // blocks in flight in registers (as ring slots: static indices)
-static_assert(kStageBF16 == kPrefetchBF16, "layer-1 and hidden K blocks come in groups of 4");
-
+// LDS wait and workgroup barrier: this wavefront's LDS operations are
+// complete, and the other wavefronts' are once it returns.
 __device__ __forceinline__ void lds_block_sync() {
   __builtin_amdgcn_sched_barrier(0);
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
   __builtin_amdgcn_sched_barrier(0);
 }
 
-__device__ __forceinline__ float mlp_logit_bf16_shared(const Mlp& M, const float x[3],
-                                                       float* __restrict__ act,
-                                                       v8bf* __restrict__ slots, int wave) {
+// The bf16 evaluation of 128 queries by the four wavefronts of a
+// 256-thread workgroup, split by output tiles: wavefront w computes tiles
+// 2w and 2w + 1 (neurons 64w..64w + 63) of every layer for all four query
+// sets (set s = the 32 queries of wavefront s), streaming only those tiles'
+// weight fragments (two 16-byte loads per lane per K block).  The layers'
+// inputs are exchanged as bf16 operands through two LDS buffers of
+// [set][K block][lane] 16-byte vectors (64 KB each, alternating between
+// layers): a layer's end converts the wavefront's accumulators into its
+// share of the next layer's operands, bf16(relu(pre + bias)), then one
+// barrier.  After the last layer every wavefront parks its fp32
+// accumulators in the same 128 KB as [set][tile][group][lane] vectors and
+// reads back its own set's 8 tiles, so the output layer runs on exactly the
+// accumulators mlp_logit_bf16 would hold: operands, matrix instructions
+// (per tile and set, in K order) and the output are those of
+// mlp_logit_bf16, and the logit is the same bit for bit.
+//
+// All four wavefronts of the workgroup must call it together, for the same
+// field (depth + 2 barriers per call); `lds` is the workgroup's
+// kSplitLdsBytes and `wave` the wavefront's index in the workgroup.
+constexpr int kSplitBufBytes = 4 * kHiddenBlocksBF16 * 64 * 16;  // 64 KB
+constexpr int kSplitLdsBytes = 2 * kSplitBufBytes;
+static_assert(4 * 8 * 4 * 64 * 16 == kSplitLdsBytes, "the output park fills both buffers");
+
+__device__ __forceinline__ float mlp_logit_bf16_split(const Mlp& M, const float x[3],
+                                                      char* __restrict__ lds, int wave) {
   const int lane = lane_id();
   const int h = lane >> 5;
   int zero = 0;  // keeps the stream prologue here (see mlp_logit_fp32)
   asm volatile("" : "+v"(zero));
-  v4f* act4 = reinterpret_cast<v4f*>(act);
-  v4f* tab4 = act4 + kGroupsF32 * 64;
-  const ODC_GLOBAL v4f* Bg = (const ODC_GLOBAL v4f*)gmem(M.bias) + lane + zero;
-  v4f tb = Bg[0];
-  // the stream ends kPrefetchBF16 blocks past the last K block; loads past
-  // the resource's size return zeros, which no matrix instruction reads
+  v8bf* bufA = reinterpret_cast<v8bf*>(lds);
+  v8bf* bufB = reinterpret_cast<v8bf*>(lds + kSplitBufBytes);
+  auto op = [&](v8bf* buf, int set, int b) -> v8bf* {
+    return buf + (set * kHiddenBlocksBF16 + b) * 64 + lane;
+  };
   const __amdgpu_buffer_rsrc_t ws = weight_stream(
       M.w1b, ((size_t)M.kb1b + (size_t)(M.depth - 1) * kHiddenBlocksBF16 + kPrefetchBF16) * 8192);
   const int voff = (lane + zero) * 16;
-  // tile 2 wave + j of K block b (this wavefront's quarter)
-  auto Q = [&](int b, int j) -> v8bf {
+  // tile 2 wave + j of K block b of the stream
+  auto S = [&](int b, int j) -> v8bf {
     return __builtin_bit_cast(
         v8bf, __builtin_amdgcn_raw_buffer_load_b128(ws, voff, (b * 8 + 2 * wave + j) * 1024, 0));
   };
-  auto slot = [&](int b, int R) -> v8bf* {
-    return slots + ((b % kSharedSlots) * 8 + R) * 64 + lane;
-  };
-  // prologue: blocks 0 and 1 into their slots, 2..5 in flight
-  {
-    const v8bf a0 = Q(0, 0), a1 = Q(0, 1), b0 = Q(1, 0), b1 = Q(1, 1);
-    *slot(0, 2 * wave) = a0;
-    *slot(0, 2 * wave + 1) = a1;
-    *slot(1, 2 * wave) = b0;
-    *slot(1, 2 * wave + 1) = b1;
-  }
-  v8bf st[kStageBF16][2];
+  v8bf wr[kPrefetchBF16][2];
 #pragma unroll
-  for (int d = 0; d < kStageBF16; ++d) {
-    // block 2 + d sits in entry (2 + d) % 4
-    st[(2 + d) % kStageBF16][0] = Q(2 + d, 0);
-    st[(2 + d) % kStageBF16][1] = Q(2 + d, 1);
+  for (int d = 0; d < kPrefetchBF16; ++d)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) wr[d][j] = S(d, j);
+  // layer-1 operands of this wavefront's queries (set = wave)
+  const float quarter_h = h ? 0.25f : 0.0f;
+#pragma unroll
+  for (int b = 0; b < kMaxGroups1BF16 * kPrefetchBF16; ++b) {
+    if (b < M.kb1b) {
+      typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+      v4u p;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        p[j] = pack_bf16(pair_feature_fast(8 * b + 2 * j, quarter_h, h, x),
+                         pair_feature_fast(8 * b + 2 * j + 1, quarter_h, h, x));
+      *op(bufA, wave, b) = __builtin_bit_cast(v8bf, p);
+    }
   }
   lds_block_sync();
-  v8bf wr[8], wn[8];
-#pragma unroll
-  for (int R = 0; R < 8; ++R) wr[R] = *slot(0, R);
-  // one K block of the stream (d = b % 4, static): steps (i)-(iv); the
-  // caller then issues the matrix instructions with wr and sets wr = wn
-  auto advance = [&](int b, int d) {
-    lds_block_sync();
-#pragma unroll
-    for (int R = 0; R < 8; ++R) wn[R] = *slot(b + 1, R);
-    const int e = (d + 2) % kStageBF16;
-    *slot(b + 2, 2 * wave) = st[e][0];
-    *slot(b + 2, 2 * wave + 1) = st[e][1];
-    st[e][0] = Q(b + 6, 0);
-    st[e][1] = Q(b + 6, 1);
-  };
   const v16f zacc = {};
-  v16f acc[8];
-  const float quarter_h = h ? 0.25f : 0.0f;
-  auto features = [&](int b) {
-    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
-    v4u p;
+  v16f acc[4][2];
+  // one K block of the stream: eight matrix instructions (4 sets x 2 tiles)
+  // with the weight slot d, the next block's operands read ahead
+  v8bf bo[4], bn[4];
+  auto kblock = [&](v8bf* in, int b, int nb, int d, bool first) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      p[j] = pack_bf16(pair_feature_fast(8 * b + 2 * j, quarter_h, h, x),
-                       pair_feature_fast(8 * b + 2 * j + 1, quarter_h, h, x));
-    return __builtin_bit_cast(v8bf, p);
+    for (int set = 0; set < 4; ++set) bn[set] = *op(in, set, nb);
+#pragma unroll
+    for (int set = 0; set < 4; ++set)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[set][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[d][j], bo[set],
+                                                              first ? zacc : acc[set][j], 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) wr[d][j] = S(b + kPrefetchBF16, j);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int set = 0; set < 4; ++set) bo[set] = bn[set];
   };
+  // layer 1
   const int ng = M.kb1b / kPrefetchBF16;
-  v8bf bv = features(0);
+#pragma unroll
+  for (int set = 0; set < 4; ++set) bo[set] = *op(bufA, set, 0);
 #pragma unroll
   for (int gi = 0; gi < kMaxGroups1BF16; ++gi) {
     if (gi == 0 || gi < ng) {
 #pragma unroll
       for (int d = 0; d < kPrefetchBF16; ++d) {
         const int b = gi * kPrefetchBF16 + d;
-        advance(b, d);
-#pragma unroll
-        for (int R = 0; R < 8; ++R)
-          acc[R] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[R], bv, b == 0 ? zacc : acc[R],
-                                                           0, 0, 0);
-        bv = features(b + 1);
-#pragma unroll
-        for (int R = 0; R < 8; ++R) wr[R] = wn[R];
+        kblock(bufA, b, b + 1 < M.kb1b ? b + 1 : b, d, b == 0);
       }
     }
   }
+  // hidden layers: this wavefront's share of layer l's operands from its
+  // accumulators and layer l - 1's bias, one barrier, layer l
+  const ODC_GLOBAL v4f* Bg = (const ODC_GLOBAL v4f*)gmem(M.bias) + h + zero;
+  v8bf* in = bufA;
+  v8bf* out = bufB;
   for (int l = 1; l < M.depth; ++l) {
-    // park layer l's pre-activations and biases; fetch layer l+1's biases
+    const ODC_GLOBAL v4f* Bl = Bg + (size_t)(l - 1) * 64;
 #pragma unroll
-    for (int T = 0; T < 8; ++T)
+    for (int j = 0; j < 2; ++j) {
+      const int T = 2 * wave + j;
 #pragma unroll
-      for (int g = 0; g < 4; ++g)
-        act4[(4 * T + g) * 64 + lane] =
-            (v4f){acc[T][4 * g], acc[T][4 * g + 1], acc[T][4 * g + 2], acc[T][4 * g + 3]};
-    tab4[lane] = tb;
-    tb = Bg[(size_t)l * 64];
+      for (int beta = 0; beta < 2; ++beta) {
+        const int b = 2 * T + beta;
+        const v4f t0 = Bl[4 * b], t1 = Bl[4 * b + 2];
+#pragma unroll
+        for (int set = 0; set < 4; ++set) {
+          const v16f& a = acc[set][j];
+          const v4f a0 = {a[8 * beta], a[8 * beta + 1], a[8 * beta + 2], a[8 * beta + 3]};
+          const v4f a1 = {a[8 * beta + 4], a[8 * beta + 5], a[8 * beta + 6], a[8 * beta + 7]};
+          *op(out, set, b) = bf16_operand(a0, a1, t0, t1);
+        }
+      }
+    }
+    lds_block_sync();
     const int base = M.kb1b + (l - 1) * kHiddenBlocksBF16;
-    bv = bf16_operand(act4[lane], act4[64 + lane], tab4[h], tab4[2 + h]);
+#pragma unroll
+    for (int set = 0; set < 4; ++set) bo[set] = *op(out, set, 0);
 #pragma unroll
     for (int b0 = 0; b0 < kHiddenBlocksBF16; b0 += kPrefetchBF16) {
 #pragma unroll
       for (int d = 0; d < kPrefetchBF16; ++d) {
         const int b = b0 + d;
-        advance(base + b, d);
-        const int bn = (b + 1) & (kHiddenBlocksBF16 - 1);
-        const v4f a0 = act4[(2 * bn) * 64 + lane], a1 = act4[(2 * bn + 1) * 64 + lane];
-        const v4f t0 = tab4[4 * bn + h], t1 = tab4[4 * bn + 2 + h];
-#pragma unroll
-        for (int R = 0; R < 8; ++R)
-          acc[R] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[R], bv, b == 0 ? zacc : acc[R],
-                                                           0, 0, 0);
-        bv = bf16_operand(a0, a1, t0, t1);
-#pragma unroll
-        for (int R = 0; R < 8; ++R) wr[R] = wn[R];
+        kblock(out, base + b, (b + 1) & (kHiddenBlocksBF16 - 1), d, b == 0);
       }
     }
+    v8bf* t = in;
+    in = out;
+    out = t;
   }
-  return mlp_output(M, acc, h, zero, x);
+  // every wavefront's reads of the last operands are done before the park
+  lds_block_sync();
+  v4f* park = reinterpret_cast<v4f*>(lds);  // [set][tile][group][lane]
+#pragma unroll
+  for (int set = 0; set < 4; ++set)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        park[((set * 8 + 2 * wave + j) * 4 + g) * 64 + lane] =
+            (v4f){acc[set][j][4 * g], acc[set][j][4 * g + 1], acc[set][j][4 * g + 2],
+                  acc[set][j][4 * g + 3]};
+  lds_block_sync();
+  v16f mine[8];
+#pragma unroll
+  for (int T = 0; T < 8; ++T)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const v4f v = park[((wave * 8 + T) * 4 + g) * 64 + lane];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) mine[T][4 * g + e] = v[e];
+    }
+  return mlp_output(M, mine, h, zero, x);
 }
 
 }  // namespace odc
