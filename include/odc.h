@@ -94,9 +94,13 @@ typedef struct {
   int32_t lin2, bin2;    /* step-2 line-binary searches (3, 12) */
   float range1, range2;  /* search ranges in cell widths (0.8, sqrt(2)/2) */
   float qef_tau;         /* QEF eigenvalue truncation relative to the largest (1e-2) */
-  double fp64_cond;      /* QEF redone in binary64 above this condition number (1e6) */
+  double fp64_cond;      /* QEF redone in binary64 above this condition number (1e6); > 0 */
   int32_t precision;     /* ODC_PREC_* */
-  float guard_logit;     /* bf16 guard band on z: 2 atanh(0.02) for |phi - 0.5| < 0.01 */
+  float guard_logit;     /* bf16 guard band on z: 2 atanh(0.02) for |phi - 0.5| < 0.01;
+                          * finite and > 0.  The guarded labels equal the fp32 path's
+                          * when the bf16 logit error stays below the band; that is
+                          * measured for the fields of this library's tests (< half the
+                          * band), not known for arbitrary weights */
   int32_t ablation;      /* 0 = the method; ODC_ABL_* bits select Table 3's baselines */
   int32_t clamp_vertices; /* 1: clamp each 3D point into its cell.  The paper is silent
                           * and the method leaves them where the QEF puts them (0);
@@ -222,9 +226,31 @@ int32_t odc_set_launch_config(odc_context* ctx, const int32_t* grid_elem_mlp_blo
  *  9 emission case        int32 per crossing edge: 0 none, 1, 2, 3
  * 10 edge gradients       3 floats per crossing edge: dz/dx at the 1D point (world
  *                         units; ODC_ABL_GRAD_NORMALS only, else 0 elements)
+ * 11 1D decision trace    uint32 per crossing edge: bit i = the label (1 inside) that
+ *                         query i of its bisection returned (Sec. 5.1)
+ * 12 2D decision trace    2 x uint64 per pair: [0] bit q = the label of query q of its
+ *                         search, [1] bit q set when query q was evaluated.  Queries in
+ *                         order: q = 0 the midpoint m, then step 1's ray (lin1 samples,
+ *                         bin1 halvings), then step 2's ray towards the pair's first
+ *                         1D point and the opposite ray (lin2 + bin2 each) (Sec. 5.2,
+ *                         App. A.1.3).  A linear sample that cannot move any bracket of
+ *                         the wavefront's pairs may be skipped (bit clear in [1]).
+ * 11 and 12 exist only when odc_context_set_trace was on for the extract (else
+ * INVALID_ARG); 12 only for searches of at most 64 queries (else UNSUPPORTED).
  * Errors: INVALID_ARG for an unknown `which`; CAPACITY when cap_bytes is too small. */
 int32_t odc_get_intermediate(odc_context* ctx, int32_t which, void* dst, int64_t cap_bytes,
                              int64_t* n);
+/* The same for job `job` (0-based) of the last batch.  INVALID_ARG when job is
+ * outside the last batch. */
+int32_t odc_get_job_intermediate(odc_context* ctx, int32_t job, int32_t which, void* dst,
+                                 int64_t cap_bytes, int64_t* n);
+
+/* Decision traces.  When enabled, later extracts on this context also record
+ * the label of every occupancy query of the 1D and 2D searches (intermediates
+ * 11 and 12), so that a checker can replay the searches' branches.  Costs
+ * 4 bytes of scratch per crossing edge and 16 per pair, and one store per
+ * element; off by default.  Server lanes never record them. */
+int32_t odc_context_set_trace(odc_context* ctx, int32_t enable);
 
 /* Self-intersections of a triangle mesh (the quality metric of Sec. 6 and
  * Table 3): the number of pairs of triangles that share no vertex and whose

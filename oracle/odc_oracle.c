@@ -273,9 +273,72 @@ static int label_grid(const orc_field* f, const orc_params* p, const float g[3],
   return orc_label_world(f, x, tie, NULL);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Replay of an implementation under test (see orc_trace).                  */
+/* ------------------------------------------------------------------------ */
+
+/* One decision: the oracle's own label `own` (*tie set when it is a
+ * near-tie) against the recorded label `theirs` when `have`.  A near-tie
+ * follows the recorded branch and is then fixed (*tie cleared); any other
+ * decision stays the oracle's and a disagreement is counted. */
+static int decide(orc_trace* tr, int own, int* tie, int have, int theirs) {
+  if (!tr || !have) return own;
+  if (*tie) {
+    *tie = 0;
+#pragma omp atomic
+    tr->adopted += 1;
+    return theirs;
+  }
+  if (own != theirs) {
+#pragma omp atomic
+    tr->mismatched += 1;
+  }
+  return own;
+}
+
+static void count_unmatched(orc_trace* tr) {
+#pragma omp atomic
+  tr->unmatched += 1;
+}
+
+/* index of v in the ascending array a[n], or -1 */
+static int64_t find_sorted(const int32_t* a, int64_t n, int64_t v) {
+  int64_t lo = 0, hi = n - 1;
+  while (lo <= hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (a[mid] == v) return mid;
+    if (a[mid] < v) lo = mid + 1;
+    else hi = mid - 1;
+  }
+  return -1;
+}
+
+/* the implementation's slot of crossing edge eid, or -1 */
+static int64_t trace_edge_slot(const orc_trace* tr, int64_t eid) {
+  if (!tr || !tr->edge_id) return -1;
+  return find_sorted(tr->edge_id, tr->n_edges, eid);
+}
+
+/* the implementation's slot of pair `slot` of face fid, or -1 */
+static int64_t trace_pair_slot(const orc_trace* tr, int64_t fid, int slot) {
+  if (!tr || !tr->pair_rec) return -1;
+  return find_sorted(tr->pair_rec, tr->n_pairs, fid * 2 + slot);
+}
+
 int orc_corner_label(const orc_field* f, const orc_params* p, int i, int j, int k, int* tie) {
+  orc_trace* tr = p->trace;
+  int64_t c = corner_id(p->res, i, j, k);
+  int theirs = tr && tr->label_words ? (int)((tr->label_words[c >> 5] >> (c & 31)) & 1u) : 0;
+  if (tr && tr->label_words && tr->labels_given) {
+    if (tie) *tie = 0;
+    return theirs;
+  }
   float g[3] = {(float)i, (float)j, (float)k};
-  return label_grid(f, p, g, tie);
+  int t = 0;
+  int lab = label_grid(f, p, g, &t);
+  lab = decide(tr, lab, &t, tr && tr->label_words, theirs);
+  if (tie) *tie = t;
+  return lab;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -285,9 +348,18 @@ int orc_corner_label(const orc_field* f, const orc_params* p, int i, int j, int 
 /* ------------------------------------------------------------------------ */
 
 static double bisect_edge(const orc_field* f, const orc_params* p, int a, const int pos[3],
-                          int label0, int* tie_step) {
+                          int label0, int* tie_step, uint32_t* own_bits) {
   double lo_t = 0.0, hi_t = 1.0;
   *tie_step = 0;
+  if (own_bits) *own_bits = 0u;
+  /* the implementation's recorded labels for this edge, when replaying */
+  orc_trace* tr = p->trace;
+  const uint32_t* rec = NULL;
+  if (tr && tr->edge_bits) {
+    int64_t x = trace_edge_slot(tr, edge_id(p->res, a, pos));
+    if (x >= 0) rec = tr->edge_bits + x;
+    else count_unmatched(tr);
+  }
   for (int it = 1; it <= p->iters_1d; ++it) {
     double mid = 0.5 * (lo_t + hi_t);
     float g[3] = {(float)pos[0], (float)pos[1], (float)pos[2]};
@@ -295,6 +367,8 @@ static double bisect_edge(const orc_field* f, const orc_params* p, int a, const 
     g[a] = (float)pos[a] + fm;
     int tie = 0;
     int lab = label_grid(f, p, g, &tie);
+    lab = decide(tr, lab, &tie, rec != NULL, rec ? (int)((*rec >> (it - 1)) & 1u) : 0);
+    if (own_bits) *own_bits |= (uint32_t)lab << (it - 1);
     if (tie && *tie_step == 0) *tie_step = it;
     if (lab == label0) lo_t = mid;
     else hi_t = mid;
@@ -326,12 +400,12 @@ static double linear_edge(const orc_field* f, const orc_params* p, int a, const 
 }
 
 static double edge_point_mode(const orc_field* f, const orc_params* p, int a, const int pos[3],
-                              int label0, int* tie_step) {
+                              int label0, int* tie_step, uint32_t* own_bits) {
   if (p->ablation & ORC_ABL_LINEAR_1D) {
     *tie_step = 0;
     return linear_edge(f, p, a, pos);
   }
-  return bisect_edge(f, p, a, pos, label0, tie_step);
+  return bisect_edge(f, p, a, pos, label0, tie_step, own_bits);
 }
 
 double orc_edge_point(const orc_field* f, const orc_params* p, int64_t eid, int* tie_step) {
@@ -342,7 +416,7 @@ double orc_edge_point(const orc_field* f, const orc_params* p, int64_t eid, int*
   int l0 = orc_corner_label(f, p, pos[0], pos[1], pos[2], NULL);
   int l1 = orc_corner_label(f, p, up[0], up[1], up[2], NULL);
   if (l0 == l1) return -1.0;
-  return edge_point_mode(f, p, a, pos, l0, tie_step);
+  return edge_point_mode(f, p, a, pos, l0, tie_step, NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -579,17 +653,41 @@ static void ray_point(const float p0[2], const float d[2], float s, float out[2]
 /* Samples p_i = p0 + (R i / N) d, i = 1..N; the first i whose label differs
  * from s0 (or N if none) bounds [p_{i-1}, p_i]; then n_bin halvings compare
  * the middle with the near end.  Returns the near parameter. */
+/* A recorded 2D search (replay): its two trace words and the index of this
+ * search's first query in them. */
+typedef struct {
+  const uint64_t* w; /* [0] labels, [1] evaluated mask; NULL when not replaying */
+  int q0;
+  uint64_t own[2];   /* the oracle's own decisions, in the same encoding */
+} pair_rec_t;
+
+static int recorded(const pair_rec_t* r, int q, int* theirs) {
+  if (!r || !r->w || q >= 64 || !((r->w[1] >> q) & 1u)) return 0;
+  *theirs = (int)((r->w[0] >> q) & 1u);
+  return 1;
+}
+
+static void record_own(pair_rec_t* r, int q, int lab) {
+  if (!r || q >= 64) return;
+  r->own[0] |= (uint64_t)lab << q;
+  r->own[1] |= 1ull << q;
+}
+
 static float line_binary(const orc_field* f, const orc_params* p, const face_geom* g,
                          const float p0[2], const float d[2], int s0, float R, int n_lin,
-                         int n_bin, float q[2], int* tie_any) {
-  int istar = n_lin, found = 0;
+                         int n_bin, float q[2], int* tie_any, pair_rec_t* rec) {
+  int istar = n_lin, found = 0, theirs = 0, have;
   for (int i = 1; i <= n_lin; ++i) {
     float s = (R * (float)i) / (float)n_lin;
     float P[2];
     ray_point(p0, d, s, P);
     int tie = 0;
     int lab = label_face_point(f, p, g, P, &tie);
-    if (tie) *tie_any = 1;
+    have = recorded(rec, rec ? rec->q0 + i - 1 : 0, &theirs);
+    lab = decide(p->trace, lab, &tie, have, theirs);
+    record_own(rec, rec ? rec->q0 + i - 1 : 0, lab);
+    /* samples after the first label change cannot move the bracket */
+    if (tie && !found) *tie_any = 1;
     if (lab != s0 && !found) { istar = i; found = 1; }
   }
   float near_s = (istar == 1) ? 0.0f : (R * (float)(istar - 1)) / (float)n_lin;
@@ -600,6 +698,9 @@ static float line_binary(const orc_field* f, const orc_params* p, const face_geo
     ray_point(p0, d, mid, P);
     int tie = 0;
     int lab = label_face_point(f, p, g, P, &tie);
+    have = recorded(rec, rec ? rec->q0 + n_lin + it : 0, &theirs);
+    lab = decide(p->trace, lab, &tie, have, theirs);
+    record_own(rec, rec ? rec->q0 + n_lin + it : 0, lab);
     if (tie) *tie_any = 1;
     if (lab == s0) near_s = mid;
     else far_s = mid;
@@ -613,7 +714,7 @@ float orc_line_binary(const orc_field* f, const orc_params* p, int64_t fid, cons
                       int* tie) {
   face_geom g = face_geometry(p->res, fid);
   int t = 0;
-  float s = line_binary(f, p, &g, p0, dir, s0, range, n_lin, n_bin, q, &t);
+  float s = line_binary(f, p, &g, p0, dir, s0, range, n_lin, n_bin, q, &t, NULL);
   if (tie) *tie = t;
   return s;
 }
@@ -631,17 +732,23 @@ typedef struct {
   double pf[2];
   int qm;        /* q coincided with m */
   int tie;
+  uint64_t bits[2]; /* the decisions taken: labels, queried mask (as a trace) */
   double sinang; /* |sin| of the angle between l1 and l2 */
 } pair_result;
 
 /* The three steps of Sec. 5.2 for the pair (P1 on fe_a, P2 on fe_b). */
 static pair_result search_pair(const orc_field* f, const orc_params* p, const face_geom* g,
-                               const int L[4], const float P1[2], const float P2[2]) {
+                               const int L[4], const float P1[2], const float P2[2],
+                               const uint64_t* trace_words) {
   pair_result r;
-  int tie_any = 0, tie = 0;
+  int tie_any = 0, tie = 0, theirs = 0;
+  pair_rec_t rec = {trace_words, 0, {0, 0}};
   /* Step 1: m, its label, and the ray from m orthogonal to l. */
   float m[2] = {(P1[0] + P2[0]) * 0.5f, (P1[1] + P2[1]) * 0.5f};
   int sm = label_face_point(f, p, g, m, &tie);
+  int have = recorded(&rec, 0, &theirs);
+  sm = decide(p->trace, sm, &tie, have, theirs);
+  record_own(&rec, 0, sm);
   if (tie) tie_any = 1;
   float du = P2[0] - P1[0], dv = P2[1] - P1[1];
   float len = sqrtf(du * du + dv * dv);
@@ -658,10 +765,12 @@ static pair_result search_pair(const orc_field* f, const orc_params* p, const fa
   else go_left = nleft <= nright; /* both qualify: the cut-off corner's side */
   float d[2] = {go_left ? perp[0] : -perp[0], go_left ? perp[1] : -perp[1]};
   float q[2];
-  float s1 = line_binary(f, p, g, m, d, sm, p->range1, p->lin1, p->bin1, q, &tie_any);
+  rec.q0 = 1;
+  float s1 = line_binary(f, p, g, m, d, sm, p->range1, p->lin1, p->bin1, q, &tie_any, &rec);
   if (s1 == 0.0f) {
     r.pf[0] = m[0]; r.pf[1] = m[1];
     r.qm = 1; r.tie = tie_any; r.sinang = 1.0;
+    r.bits[0] = rec.own[0]; r.bits[1] = rec.own[1];
     return r;
   }
   /* Step 2: rays from q parallel to l, towards P1 and towards P2. */
@@ -670,14 +779,18 @@ static pair_result search_pair(const orc_field* f, const orc_params* p, const fa
   float uh[2] = {wu / lw, wv / lw};
   float un[2] = {-uh[0], -uh[1]};
   float q1[2], q2[2];
-  line_binary(f, p, g, q, uh, sm, p->range2, p->lin2, p->bin2, q1, &tie_any);
-  line_binary(f, p, g, q, un, sm, p->range2, p->lin2, p->bin2, q2, &tie_any);
+  rec.q0 = 1 + p->lin1 + p->bin1;
+  line_binary(f, p, g, q, uh, sm, p->range2, p->lin2, p->bin2, q1, &tie_any, &rec);
+  rec.q0 = 1 + p->lin1 + p->bin1 + p->lin2 + p->bin2;
+  line_binary(f, p, g, q, un, sm, p->range2, p->lin2, p->bin2, q2, &tie_any, &rec);
   /* Step 3: intersection of line(P1,q1) and line(P2,q2). */
   double Au = (double)q1[0] - P1[0], Av = (double)q1[1] - P1[1];
   double Bu = (double)q2[0] - P2[0], Bv = (double)q2[1] - P2[1];
   double det = Au * Bv - Av * Bu;
   r.qm = 0;
   r.tie = tie_any;
+  r.bits[0] = rec.own[0];
+  r.bits[1] = rec.own[1];
   if (det == 0.0) {
     r.pf[0] = q[0]; r.pf[1] = q[1];
     r.sinang = 0.0;
@@ -831,6 +944,36 @@ int orc_ic_case(const double q[4][3], const double pin[3], const double pout[3],
 /* neighbouring 2D points inside this cell, then the QEF per partition.     */
 /* ------------------------------------------------------------------------ */
 
+/* The recorded trace words of pair `slot` of face fid (replay), or NULL. */
+static const uint64_t* trace_pair_words(orc_trace* tr, int64_t fid, int slot) {
+  if (!tr || !tr->pair_bits) return NULL;
+  int64_t x = trace_pair_slot(tr, fid, slot);
+  if (x < 0) {
+    count_unmatched(tr);
+    return NULL;
+  }
+  return tr->pair_bits + 2 * x;
+}
+
+/* Staged inputs: the implementation's 1D point of edge eid (returns 1), or 0. */
+static int staged_edge_t(const orc_trace* tr, int64_t eid, double* t) {
+  if (!tr || !tr->staged || !tr->edge_t) return 0;
+  int64_t x = trace_edge_slot(tr, eid);
+  if (x < 0) return 0;
+  *t = tr->edge_t[x];
+  return 1;
+}
+
+/* Staged inputs: the implementation's 2D point of pair `slot` of face fid. */
+static int staged_pair_pf(const orc_trace* tr, int64_t fid, int slot, double pf[2]) {
+  if (!tr || !tr->staged || !tr->pair_pf) return 0;
+  int64_t x = trace_pair_slot(tr, fid, slot);
+  if (x < 0) return 0;
+  pf[0] = tr->pair_pf[2 * x];
+  pf[1] = tr->pair_pf[2 * x + 1];
+  return 1;
+}
+
 typedef struct {
   /* lookups the cell needs; the full pipeline supplies tables, single-cell
    * queries compute on demand */
@@ -847,6 +990,11 @@ typedef struct {
 } cell_ctx;
 
 static double ctx_edge_t(const cell_ctx* cx, int64_t eid, int* tie) {
+  double st;
+  if (staged_edge_t(cx->p->trace, eid, &st)) {
+    *tie = 0;
+    return st;
+  }
   if (cx->edge_index) {
     int32_t ix = cx->edge_index[eid];
     *tie = cx->edge_tie[ix] != 0;
@@ -874,12 +1022,14 @@ static pair_result compute_pair(const orc_field* f, const orc_params* p, const u
   int np = face_pairs(L, flipped, pairs);
   int fa = pairs[slot][0], fb = pairs[slot][1];
   int ta = 0, tb = 0;
-  double t1 = orc_edge_point(f, p, face_edge_global(N, &g, fa), &ta);
-  double t2 = orc_edge_point(f, p, face_edge_global(N, &g, fb), &tb);
+  int64_t ea = face_edge_global(N, &g, fa), eb = face_edge_global(N, &g, fb);
+  double t1, t2;
+  if (!staged_edge_t(p->trace, ea, &t1)) t1 = orc_edge_point(f, p, ea, &ta);
+  if (!staged_edge_t(p->trace, eb, &t2)) t2 = orc_edge_point(f, p, eb, &tb);
   float P1[2], P2[2];
   face_edge_point(fa, (float)t1, P1);
   face_edge_point(fb, (float)t2, P2);
-  pair_result r = search_pair(f, p, &g, L, P1, P2);
+  pair_result r = search_pair(f, p, &g, L, P1, P2, trace_pair_words(p->trace, fid, slot));
   if (info)
     *info = slot | (fa << 4) | (fb << 8) | (flipped << 12) | (r.qm << 13) | ((np == 2) << 14);
   if (edge_ties) *edge_ties = (ta != 0) || (tb != 0);
@@ -887,6 +1037,10 @@ static pair_result compute_pair(const orc_field* f, const orc_params* p, const u
 }
 
 static void ctx_pair_pf(const cell_ctx* cx, int64_t fid, int slot, double pf[2], int* tie) {
+  if (staged_pair_pf(cx->p->trace, fid, slot, pf)) {
+    *tie = 0;
+    return;
+  }
   if (cx->face_first_pair) {
     int32_t ix = cx->face_first_pair[fid] + slot;
     pf[0] = cx->pair_pf[2 * ix];
@@ -1111,14 +1265,16 @@ int orc_mesh_extract(const orc_field* f, const orc_params* p, orc_mesh* m) {
   ALLOC(m->edge_id, ne);
   ALLOC(m->edge_t, ne);
   ALLOC(m->edge_tie_step, ne);
+  ALLOC(m->edge_bits, ne);
   for (int64_t e = 0; e < NE; ++e)
     if (eidx[e] >= 0) m->edge_id[eidx[e]] = (int32_t)e;
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t x = 0; x < ne; ++x) {
+    if (p->topology_only) continue;
     int a, pos[3], ts = 0;
     edge_decode(N, m->edge_id[x], &a, pos);
     int l0 = lab[corner_id(N, pos[0], pos[1], pos[2])];
-    m->edge_t[x] = edge_point_mode(f, p, a, pos, l0, &ts);
+    m->edge_t[x] = edge_point_mode(f, p, a, pos, l0, &ts, m->edge_bits + x);
     m->edge_tie_step[x] = ts;
   }
 
@@ -1149,6 +1305,7 @@ int orc_mesh_extract(const orc_field* f, const orc_params* p, orc_mesh* m) {
   ALLOC(m->pair_pf, 2 * np);
   ALLOC(m->pair_tie, np);
   ALLOC(m->pair_sin, np);
+  ALLOC(m->pair_bits, 2 * np);
   for (int64_t fid = 0; fid < NF; ++fid)
     for (int s = 0; s < fcount[fid]; ++s) m->pair_face[ffirst[fid] + s] = (int32_t)fid;
   free(fcount);
@@ -1161,17 +1318,21 @@ int orc_mesh_extract(const orc_field* f, const orc_params* p, orc_mesh* m) {
     face_labels_global(f, p, lab, &g, L);
     int npf = face_pairs(L, fflip[fid], pairs);
     int fa = pairs[slot][0], fb = pairs[slot][1];
-    int32_t ia = eidx[face_edge_global(N, &g, fa)], ib = eidx[face_edge_global(N, &g, fb)];
+    int64_t ga = face_edge_global(N, &g, fa), gb = face_edge_global(N, &g, fb);
+    int32_t ia = eidx[ga], ib = eidx[gb];
+    double t1 = m->edge_t[ia], t2 = m->edge_t[ib];
+    staged_edge_t(p->trace, ga, &t1); /* the implementation's 1D points when staged */
+    staged_edge_t(p->trace, gb, &t2);
     float P1[2], P2[2];
-    face_edge_point(fa, (float)m->edge_t[ia], P1);
-    face_edge_point(fb, (float)m->edge_t[ib], P2);
+    face_edge_point(fa, (float)t1, P1);
+    face_edge_point(fb, (float)t2, P2);
     pair_result r;
-    if (p->ablation & ORC_ABL_GRAD_NORMALS) {
+    if (p->topology_only || (p->ablation & ORC_ABL_GRAD_NORMALS)) {
       /* gradient normals need no 2D points */
       memset(&r, 0, sizeof(r));
       r.pf[0] = r.pf[1] = NAN;
     } else {
-      r = search_pair(f, p, &g, L, P1, P2);
+      r = search_pair(f, p, &g, L, P1, P2, trace_pair_words(p->trace, fid, slot));
     }
     m->pair_pf[2 * x] = r.pf[0];
     m->pair_pf[2 * x + 1] = r.pf[1];
@@ -1183,6 +1344,8 @@ int orc_mesh_extract(const orc_field* f, const orc_params* p, orc_mesh* m) {
     }
     m->pair_tie[x] = (uint8_t)(r.tie || ctie || m->edge_tie_step[ia] || m->edge_tie_step[ib]);
     m->pair_sin[x] = r.sinang;
+    m->pair_bits[2 * x] = r.bits[0];
+    m->pair_bits[2 * x + 1] = r.bits[1];
     m->pair_info[x] = slot | (fa << 4) | (fb << 8) | (fflip[fid] << 12) | (r.qm << 13) |
                       ((npf == 2) << 14);
   }
@@ -1231,8 +1394,19 @@ int orc_mesh_extract(const orc_field* f, const orc_params* p, orc_mesh* m) {
   for (int64_t x = 0; x < nc; ++x) {
     int64_t cid = m->cell_id[x];
     int c[3] = {(int)(cid % N), (int)((cid / N) % N), (int)(cid / ((int64_t)N * N))};
-    int pm, fm, tie = 0;
-    int npart = cell_solve(&cx, c, cverts + 12 * x, &pm, &fm, &tie, ckap + 4 * x, cgap + 4 * x);
+    int pm, fm, tie = 0, npart;
+    if (p->topology_only) {
+      /* partitions only: the cell's configuration, its faces' flips, cycles */
+      fm = 0;
+      for (int lf = 0; lf < 6; ++lf) {
+        int a = lf / 2, sd = lf % 2, pos[3] = {c[0], c[1], c[2]};
+        pos[a] += sd;
+        if (fflip[face_id(N, a, pos)]) fm |= 1 << lf;
+      }
+      npart = orc_cube_partitions(cell_config(f, p, lab, c), fm, &pm);
+    } else {
+      npart = cell_solve(&cx, c, cverts + 12 * x, &pm, &fm, &tie, ckap + 4 * x, cgap + 4 * x);
+    }
     m->cell_npart[x] = npart;
     m->cell_partmap[x] = pm;
     m->cell_flipmask[x] = fm;
@@ -1255,6 +1429,7 @@ int orc_mesh_extract(const orc_field* f, const orc_params* p, orc_mesh* m) {
   quad = calloc((size_t)(ne > 0 ? ne : 1), sizeof(*quad));
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t x = 0; x < ne; ++x) {
+    if (p->topology_only) { m->edge_case[x] = 0; continue; }
     int a, pos[3];
     edge_decode(N, m->edge_id[x], &a, pos);
     int b = (a + 1) % 3, cc = (a + 2) % 3;
@@ -1339,8 +1514,10 @@ int orc_mesh_extract(const orc_field* f, const orc_params* p, orc_mesh* m) {
     } else {
       int a, pos[3];
       edge_decode(N, m->edge_id[x], &a, pos);
+      double te = m->edge_t[x];
+      staged_edge_t(p->trace, m->edge_id[x], &te);
       for (int y = 0; y < 3; ++y) m->vert[3 * v3 + y] = pos[y];
-      m->vert[3 * v3 + a] += m->edge_t[x];
+      m->vert[3 * v3 + a] += te;
       m->vert_tie[v3] = (uint8_t)(m->edge_tie_step[x] != 0);
       m->vert_kappa[v3] = 0.0;
       m->vert_gap[v3] = INFINITY;
@@ -1368,6 +1545,7 @@ int orc_mesh_extract(const orc_field* f, const orc_params* p, orc_mesh* m) {
 
 void orc_mesh_free(orc_mesh* m) {
   void* ptrs[] = {m->corner_label, m->corner_tie, m->edge_id, m->edge_t, m->edge_tie_step,
+                  m->edge_bits, m->pair_bits,
                   m->pair_face, m->pair_info, m->pair_pf, m->pair_tie, m->pair_sin,
                   m->cell_id, m->cell_npart, m->cell_partmap, m->cell_flipmask, m->cell_vbase,
                   m->cell_tie, m->vert, m->vert_tie, m->vert_kappa, m->vert_gap, m->edge_case,

@@ -60,6 +60,48 @@ typedef struct {
   double mlp_tie_eps;       /* |logit| below this is a near-tie */
 } orc_field;
 
+/* Replay of an implementation under test (staged parity).  The paper fixes
+ * no precision, so where the oracle's own occupancy decision is a near-tie
+ * (|logit| < mlp_tie_eps) both branches are correct; an implementation that
+ * records the branch it took at every query lets the oracle follow that
+ * branch there and check every other decision against it.  Orders are the
+ * canonical ones above; arrays are host memory owned by the caller; any
+ * array may be NULL (no trace for that stage).
+ *   label_words   corner labels, bit c%32 of word c/32 (1 = inside)
+ *   labels_given  1: take label_words as the corner labels without evaluating
+ *                 the field (for topology from labels checked elsewhere)
+ *   edge_id[n_edges]   crossing edges, ascending; edge_bits[x] bit i = the
+ *                 label of bisection query i (Sec. 5.1)
+ *   pair_rec[n_pairs]  face id << 1 | slot, ascending; pair_bits[2x] bit q =
+ *                 the label of 2D-search query q, pair_bits[2x+1] bit q = query
+ *                 q was evaluated.  q = 0 is m, then step 1's lin1 samples and
+ *                 bin1 halvings, then step 2's ray towards the first 1D point
+ *                 and the opposite ray, lin2 + bin2 each (Sec. 5.2, App. A.1.3);
+ *                 queries past the 64th are untraced.
+ *   staged        1: the 2D searches start from edge_t (the implementation's
+ *                 1D points) and the QEF takes edge_t and pair_pf (its 2D
+ *                 points) instead of the oracle's own; the outputs still hold
+ *                 the oracle's own 1D and 2D points.
+ * Counters (outputs, accumulated over calls): adopted = near-tie decisions
+ * that took the recorded branch; mismatched = decisions away from a near-tie
+ * that differ from the recorded one (a failure of the implementation);
+ * unmatched = oracle elements with no trace entry (their decisions stay the
+ * oracle's own). */
+typedef struct {
+  const uint32_t* label_words;
+  int labels_given;
+  int64_t n_edges;
+  const int32_t* edge_id;
+  const uint32_t* edge_bits;
+  const float* edge_t;
+  int64_t n_pairs;
+  const int32_t* pair_rec;
+  const uint64_t* pair_bits;
+  const double* pair_pf;
+  int staged;
+  int64_t adopted, mismatched, unmatched;
+} orc_trace;
+
 typedef struct {
   double lo[3];
   double size;              /* edge length of the cubic domain */
@@ -72,6 +114,9 @@ typedef struct {
   int n_threads;            /* 0 = all */
   int ablation;             /* 0 = the method; else ORC_ABL_* bits (Table 3 baselines) */
   int clamp;                /* 1: clamp each 3D point into its cell (the method leaves it) */
+  int topology_only;        /* 1: labels, crossing edges, pairs, flips, cells, partitions and
+                             * vertex numbering only (no searches, 3D points or triangles) */
+  orc_trace* trace;         /* NULL, or the replay above */
 } orc_params;
 
 /* Ablation baselines (Sec. 4 / Table 3), each replacing one step of the
@@ -96,6 +141,7 @@ typedef struct {
   int32_t* edge_id;
   double* edge_t;           /* parameter from the lower corner, in (0,1) */
   int32_t* edge_tie_step;   /* first bisection step that was a near-tie, 0 = none */
+  uint32_t* edge_bits;      /* bit i: the label taken at bisection query i (as orc_trace) */
   /* face pairs, ascending (face id, slot) */
   int64_t n_pairs;
   int32_t* pair_face;
@@ -103,6 +149,7 @@ typedef struct {
   double* pair_pf;          /* face-local (u,v) */
   uint8_t* pair_tie;        /* own decisions or an input 1D point had a near-tie */
   double* pair_sin;         /* |sin| of the angle between l1 and l2 (1 when q == m) */
+  uint64_t* pair_bits;      /* per pair: labels taken, queried mask (as orc_trace) */
   int64_t n_flipped_faces;
   /* active cells, ascending id */
   int64_t n_cells;
@@ -126,7 +173,10 @@ typedef struct {
   int32_t* tris;
 } orc_mesh;
 
-/* Full pipeline.  Returns 0 on success, <0 on invalid input. */
+/* Near-tie flags (corner_tie, edge_tie_step, pair_tie, cell_tie, vert_tie,
+ * edge_case_tie) mark decisions the oracle could not fix: with a trace, a
+ * near-tie that took the recorded branch is fixed and not flagged.
+ * Full pipeline.  Returns 0 on success, <0 on invalid input. */
 int orc_mesh_extract(const orc_field* f, const orc_params* p, orc_mesh* out);
 void orc_mesh_free(orc_mesh* m);
 

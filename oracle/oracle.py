@@ -36,12 +36,69 @@ class _Field(C.Structure):
                 ("mlp_tie_eps", C.c_double)]
 
 
+class _Trace(C.Structure):
+    _fields_ = [("label_words", C.POINTER(C.c_uint32)), ("labels_given", C.c_int),
+                ("n_edges", C.c_int64), ("edge_id", C.POINTER(C.c_int32)),
+                ("edge_bits", C.POINTER(C.c_uint32)), ("edge_t", C.POINTER(C.c_float)),
+                ("n_pairs", C.c_int64), ("pair_rec", C.POINTER(C.c_int32)),
+                ("pair_bits", C.POINTER(C.c_uint64)), ("pair_pf", C.POINTER(C.c_double)),
+                ("staged", C.c_int), ("adopted", C.c_int64), ("mismatched", C.c_int64),
+                ("unmatched", C.c_int64)]
+
+
 class _Params(C.Structure):
     _fields_ = [("lo", C.c_double * 3), ("size", C.c_double), ("res", C.c_int),
                 ("iters_1d", C.c_int), ("lin1", C.c_int), ("bin1", C.c_int), ("lin2", C.c_int),
                 ("bin2", C.c_int), ("range1", C.c_float), ("range2", C.c_float),
                 ("qef_tau", C.c_double), ("ic_tie_tol", C.c_double), ("n_threads", C.c_int),
-                ("ablation", C.c_int), ("clamp", C.c_int)]
+                ("ablation", C.c_int), ("clamp", C.c_int), ("topology_only", C.c_int),
+                ("trace", C.POINTER(_Trace))]
+
+
+class Trace:
+    """An implementation's recorded occupancy decisions for a replayed oracle
+    run (orc_trace in odc_oracle.h): its corner label words, its crossing
+    edges with the bisection labels, its pairs with the 2D-search labels and
+    evaluated masks, and (staged) its 1D and 2D points.  Where the oracle's
+    own decision is a near-tie it follows the recorded branch; elsewhere it
+    counts disagreements (`mismatched`, which must stay 0)."""
+
+    def __init__(self, label_words=None, edge_ids=None, edge_bits=None, edge_t=None,
+                 pair_rec=None, pair_bits=None, pair_pf=None, staged=False,
+                 labels_given=False):
+        def keep(a, dt):
+            return None if a is None else np.ascontiguousarray(a, dt)
+        self._a = {"label_words": keep(label_words, np.uint32),
+                   "edge_id": keep(edge_ids, np.int32), "edge_bits": keep(edge_bits, np.uint32),
+                   "edge_t": keep(edge_t, np.float32), "pair_rec": keep(pair_rec, np.int32),
+                   "pair_bits": keep(pair_bits, np.uint64), "pair_pf": keep(pair_pf, np.float64)}
+        t = _Trace()
+        ctypes_of = {"label_words": C.c_uint32, "edge_id": C.c_int32, "edge_bits": C.c_uint32,
+                     "edge_t": C.c_float, "pair_rec": C.c_int32, "pair_bits": C.c_uint64,
+                     "pair_pf": C.c_double}
+        for k, a in self._a.items():
+            if a is not None:
+                setattr(t, k, a.ctypes.data_as(C.POINTER(ctypes_of[k])))
+        t.labels_given = int(bool(labels_given))
+        t.staged = int(bool(staged))
+        t.n_edges = 0 if self._a["edge_id"] is None else len(self._a["edge_id"])
+        t.n_pairs = 0 if self._a["pair_rec"] is None else len(self._a["pair_rec"])
+        self.t = t
+
+    @property
+    def adopted(self):
+        return int(self.t.adopted)
+
+    @property
+    def mismatched(self):
+        return int(self.t.mismatched)
+
+    @property
+    def unmatched(self):
+        return int(self.t.unmatched)
+
+    def reset(self):
+        self.t.adopted = self.t.mismatched = self.t.unmatched = 0
 
 
 _P = C.POINTER
@@ -49,9 +106,10 @@ _MESH_FIELDS = [
     ("res", C.c_int),
     ("n_corners", C.c_int64), ("corner_label", _P(C.c_uint8)), ("corner_tie", _P(C.c_uint8)),
     ("n_edges", C.c_int64), ("edge_id", _P(C.c_int32)), ("edge_t", _P(C.c_double)),
-    ("edge_tie_step", _P(C.c_int32)),
+    ("edge_tie_step", _P(C.c_int32)), ("edge_bits", _P(C.c_uint32)),
     ("n_pairs", C.c_int64), ("pair_face", _P(C.c_int32)), ("pair_info", _P(C.c_int32)),
     ("pair_pf", _P(C.c_double)), ("pair_tie", _P(C.c_uint8)), ("pair_sin", _P(C.c_double)),
+    ("pair_bits", _P(C.c_uint64)),
     ("n_flipped_faces", C.c_int64),
     ("n_cells", C.c_int64), ("cell_id", _P(C.c_int32)), ("cell_npart", _P(C.c_int32)),
     ("cell_partmap", _P(C.c_int32)), ("cell_flipmask", _P(C.c_int32)),
@@ -118,7 +176,7 @@ class Oracle:
     """Holds one field and one grid; keeps the numpy buffers alive."""
 
     def __init__(self, field, grid, mlp_tie_eps: float = 1e-4, ic_tie_tol: float = 1e-5,
-                 n_threads: int = 0):
+                 n_threads: int = 0, trace: "Trace | None" = None, topology_only: bool = False):
         self.field = field
         self.grid = grid
         self._prims = None if field.prims is None else np.ascontiguousarray(field.prims, np.float32)
@@ -132,7 +190,9 @@ class Oracle:
         self.p = _Params((C.c_double * 3)(*grid.lo), grid.size, grid.res, grid.iters_1d,
                          grid.lin1, grid.bin1, grid.lin2, grid.bin2, grid.range1, grid.range2,
                          grid.qef_tau, ic_tie_tol, n_threads, getattr(grid, "ablation", 0),
-                         getattr(grid, "clamp", 0))
+                         getattr(grid, "clamp", 0), int(bool(topology_only)),
+                         C.pointer(trace.t) if trace is not None else None)
+        self.trace = trace
 
     def mesh(self) -> dict:
         m = _Mesh()
@@ -153,8 +213,10 @@ class Oracle:
 
             out["corner_label"] = grab("corner_label", m.n_corners)
             out["corner_tie"] = grab("corner_tie", m.n_corners)
-            for k in ("edge_id", "edge_t", "edge_tie_step", "edge_case", "edge_case_tie"):
+            for k in ("edge_id", "edge_t", "edge_tie_step", "edge_case", "edge_case_tie",
+                      "edge_bits"):
                 out[k] = grab(k, m.n_edges)
+            out["pair_bits"] = grab("pair_bits", m.n_pairs, 2)
             for k in ("pair_face", "pair_info", "pair_tie", "pair_sin"):
                 out[k] = grab(k, m.n_pairs)
             out["pair_pf"] = grab("pair_pf", m.n_pairs, 2)

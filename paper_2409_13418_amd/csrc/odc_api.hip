@@ -209,6 +209,10 @@ int32_t odc::validate_job(odc_context* ctx, const odc_field* f, const odc_params
     return fail(ctx, ODC_ERR_INVALID_ARG, "qef_tau outside [0,1)");
   if (p->precision != ODC_PREC_FP32 && p->precision != ODC_PREC_BF16_GUARDED)
     return fail(ctx, ODC_ERR_INVALID_ARG, "unknown precision %d", p->precision);
+  if (!(p->guard_logit > 0.0f) || !isfinite(p->guard_logit))
+    return fail(ctx, ODC_ERR_INVALID_ARG, "guard_logit must be finite and positive");
+  if (!(p->fp64_cond > 0.0) || isnan(p->fp64_cond))
+    return fail(ctx, ODC_ERR_INVALID_ARG, "fp64_cond must be positive");
   if (p->ablation &
       ~(ODC_ABL_LINEAR_1D | ODC_ABL_GRAD_NORMALS | ODC_ABL_MDC_SPLIT | ODC_ABL_SDF_INPUT))
     return fail(ctx, ODC_ERR_INVALID_ARG, "unknown ablation bits 0x%x", p->ablation);
@@ -289,7 +293,7 @@ void job_scalars(Job& J, const odc_field* f, const odc_params* p, int ce) {
 // Byte sizes of a job's scratch regions (each a multiple of 256).
 struct Layout {
   size_t grid[13];
-  size_t active[17];
+  size_t active[19];
   size_t grid_total = 0, active_total = 0;
   size_t mlpw = 0, guard = 0, status = 0;
   int guard_cap = 0;
@@ -297,7 +301,7 @@ struct Layout {
   size_t total() const { return grid_total + active_total + mlpw + guard + status; }
 };
 
-Layout job_layout(const Job& J, const odc_field* f, bool guard_full) {
+Layout job_layout(const Job& J, const odc_field* f, bool guard_full, bool trace) {
   Layout L;
   int nscan = J.nw_e;
   const int others[4] = {J.nw_f, J.nw_cell, J.cap_edges + 1, J.cap_cells + 1};
@@ -325,7 +329,9 @@ Layout job_layout(const Job& J, const odc_field* f, bool guard_full) {
     L.active_total += asz[i];
   }
   L.active[16] = (J.ablation & kAblGradNormals) ? align_up(ne * 3 * sizeof(float)) : 0;
-  L.active_total += L.active[16];
+  L.active[17] = trace ? align_up(ne * 4) : 0;
+  L.active[18] = trace ? align_up(np * 16) : 0;
+  L.active_total += L.active[16] + L.active[17] + L.active[18];
   L.status = align_up(4 * sizeof(unsigned long long));
   if (f->kind == ODC_FIELD_MLP) {
     const int kb1f = kb1_fp32(f->in_dim), kb1b = kb1_bf16(f->in_dim), d = f->depth;
@@ -356,17 +362,20 @@ void job_bind(Job& J, const Layout& L, const odc_field* f, char* grid, char* act
     *gp[i] = (uint32_t*)(grid + off);
     off += L.grid[i];
   }
-  void** ap[17] = {(void**)&J.elist,    (void**)&J.et,    (void**)&J.ecase, (void**)&J.ntri,
+  void** ap[19] = {(void**)&J.elist,    (void**)&J.et,    (void**)&J.ecase, (void**)&J.ntri,
                    (void**)&J.n3,       (void**)&J.tprefix, (void**)&J.c3prefix,
                    (void**)&J.quad,     (void**)&J.plist, (void**)&J.pf,    (void**)&J.clist,
                    (void**)&J.cpm,      (void**)&J.cnf,   (void**)&J.npart, (void**)&J.vbase,
-                   (void**)&J.vloc,     (void**)&J.egrad};
+                   (void**)&J.vloc,     (void**)&J.egrad, (void**)&J.etrace,
+                   (void**)&J.ptrace};
   off = 0;
-  for (int i = 0; i < 17; ++i) {
+  for (int i = 0; i < 19; ++i) {
     *ap[i] = active + off;
     off += L.active[i];
   }
   if (!(J.ablation & kAblGradNormals)) J.egrad = nullptr;
+  if (!L.active[17]) J.etrace = nullptr;
+  if (!L.active[18]) J.ptrace = nullptr;
   J.status = (unsigned long long*)status;
   if (f->kind == ODC_FIELD_MLP) {
     const int d = f->depth;
@@ -405,7 +414,7 @@ size_t odc::job_scratch_bytes(const odc_field* f, const odc_params* p, int cap_e
                               bool guard_full) {
   Job J;
   job_scalars(J, f, p, cap_edges);
-  return job_layout(J, f, guard_full).total();
+  return job_layout(J, f, guard_full, false).total();
 }
 
 // Fills job k (host mirror) and points it into its slot's scratch: the
@@ -426,7 +435,7 @@ static int32_t setup_job(odc_context* ctx, int k, const odc_field* f, const odc_
     S.cap_edges = ce;
   }
   job_scalars(J, f, p, ce);
-  const Layout L = job_layout(J, f, S.guard_full);
+  const Layout L = job_layout(J, f, S.guard_full, ctx->trace && !S.ext);
   if (S.ext) {
     if (L.total() > S.ext_bytes)
       return fail(ctx, ODC_ERR_OUT_OF_MEMORY, "job needs %zu bytes of scratch, block has %zu",
@@ -658,13 +667,16 @@ extern "C" int32_t odc_mesh_sync(odc_context* ctx, odc_mesh_counts* c) {
   return rc;
 }
 
-extern "C" int32_t odc_get_intermediate(odc_context* ctx, int32_t which, void* dst,
-                                        int64_t cap_bytes, int64_t* n) {
+extern "C" int32_t odc_get_job_intermediate(odc_context* ctx, int32_t job, int32_t which,
+                                            void* dst, int64_t cap_bytes, int64_t* n) {
   if (!ctx || !n) return ODC_ERR_INVALID_ARG;
   if (!ctx->pending) return fail(ctx, ODC_ERR_INVALID_ARG, "no extract yet");
+  if (job < 0 || job >= ctx->pending)
+    return fail(ctx, ODC_ERR_INVALID_ARG, "job %d outside the last batch of %d", job,
+                ctx->pending);
   TRY(finish(ctx));
-  const Job& J = ctx->hjobs[0];
-  const unsigned long long* o = ctx->hgather;
+  const Job& J = ctx->hjobs[job];
+  const unsigned long long* o = ctx->hgather + kGatherWords * job;
   const void* src = nullptr;
   int64_t count = 0, elem = 4;
   switch (which) {
@@ -683,6 +695,16 @@ extern "C" int32_t odc_get_intermediate(odc_context* ctx, int32_t which, void* d
       count = J.egrad ? (int64_t)o[0] : 0;
       elem = 12;
       break;
+    case 11:
+    case 12:
+      if (which == 11 ? !J.etrace : !J.ptrace)
+        return fail(ctx, ODC_ERR_INVALID_ARG, "decision traces were not recorded");
+      if (which == 12 && 1 + (J.lin1 + J.bin1) + 2 * (J.lin2 + J.bin2) > 64)
+        return fail(ctx, ODC_ERR_UNSUPPORTED, "2D searches of more than 64 queries are not traced");
+      src = which == 11 ? (const void*)J.etrace : (const void*)J.ptrace;
+      count = (int64_t)o[which == 11 ? 0 : 1];
+      elem = which == 11 ? 4 : 16;
+      break;
     default: return fail(ctx, ODC_ERR_INVALID_ARG, "unknown intermediate %d", which);
   }
   *n = count;
@@ -695,6 +717,22 @@ extern "C" int32_t odc_get_intermediate(odc_context* ctx, int32_t which, void* d
                                 ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   }
+  return ODC_OK;
+}
+
+extern "C" int32_t odc_get_intermediate(odc_context* ctx, int32_t which, void* dst,
+                                        int64_t cap_bytes, int64_t* n) {
+  return odc_get_job_intermediate(ctx, 0, which, dst, cap_bytes, n);
+}
+
+extern "C" int32_t odc_context_set_trace(odc_context* ctx, int32_t enable) {
+  if (!ctx) return ODC_ERR_INVALID_ARG;
+  if ((enable != 0) != ctx->trace) {
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    drop_graph(ctx);  // the job layout changes
+  }
+  ctx->trace = enable != 0;
   return ODC_OK;
 }
 

@@ -52,6 +52,7 @@ struct odc_context {
   unsigned long long* hgather = nullptr;   // pinned, kGatherWords per job
   odc::LaunchCfg cfg;
   double cap_scale = 1.0;
+  bool trace = false;  // record decision traces of the searches
   // timing
   bool timing = false;
   hipEvent_t ev[9] = {};

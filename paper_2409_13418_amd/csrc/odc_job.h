@@ -72,6 +72,11 @@ struct Job {
   uint32_t* vbase;
   float* vloc;
   float* egrad;  // dz/dx at each crossing edge's 1D point (gradient-normal ablation)
+  // decision traces (NULL unless the context records them): the label of
+  // every bisection query per crossing edge, and per pair the labels and the
+  // evaluated-query mask of its 2D search
+  uint32_t* etrace;
+  unsigned long long* ptrace;
 
   // outputs (caller memory)
   float* out_v;

@@ -602,17 +602,23 @@ struct MlpLabel {
 // ------------------------------------------------------------ (b) 1D points
 // Bisection (Sec. 5.1): k halvings of [0,1] keeping distinct end labels; the
 // point is the middle of the final bracket.
+// `bits` receives the label of every query (bit it for halving it), the
+// decision trace that a checker can replay.
 template <class Lab>
-__device__ __forceinline__ float bisect_edge(const Job& j, const Lab& lab, int id) {
+__device__ __forceinline__ float bisect_edge(const Job& j, const Lab& lab, int id,
+                                             uint32_t& bits) {
   int a, p[3];
   edge_pos(j.g, id, a, p);
   const int l0 = bit_of(j.labels, corner_index(j.g, p[0], p[1], p[2]));
   float lo = 0.0f, hi = 1.0f;
+  bits = 0u;
   for (int it = 0; it < j.iters_1d; ++it) {
     const float mid = (lo + hi) * 0.5f;
     float gp[3] = {(float)p[0], (float)p[1], (float)p[2]};
     gp[a] = (float)p[a] + mid;
-    if (lab(gp) == l0) lo = mid;
+    const int l = lab(gp);
+    bits |= (uint32_t)l << it;
+    if (l == l0) lo = mid;
     else hi = mid;
   }
   return (lo + hi) * 0.5f;
@@ -628,7 +634,9 @@ __global__ __launch_bounds__(256) void k_bisect_csg(const Job* __restrict__ jobs
                 return;
               }
               CsgLabel lab{&J.g, J.prims, J.n_prims};
-              J.et[x] = bisect_edge(J, lab, J.elist[x]);
+              uint32_t bits;
+              J.et[x] = bisect_edge(J, lab, J.elist[x], bits);
+              if (J.etrace) J.etrace[x] = bits;
             });
 }
 
@@ -663,13 +671,17 @@ __global__ __launch_bounds__(256) void k_bisect_mlp(const Job* __restrict__ jobs
               const bool valid = x < ne;
               const int e = J.elist[valid ? x : ne - 1];
               float tt;
+              uint32_t bits = 0u;
               if (J.ablation & kAblLinear1D) {
                 tt = linear_edge_mlp(J, e, act);
               } else {
                 MlpLabel lab{&J.g, &J.mlp, act};
-                tt = bisect_edge(J, lab, e);
+                tt = bisect_edge(J, lab, e, bits);
               }
-              if (valid && lane < 32) J.et[x] = tt;
+              if (valid && lane < 32) {
+                J.et[x] = tt;
+                if (J.etrace) J.etrace[x] = bits;
+              }
             });
 }
 
@@ -776,8 +788,13 @@ struct LineBinary {
 // sequence of 1 + (lin1 + bin1) + 2 (lin2 + bin2) occupancy queries so that a
 // wavefront can batch each query across its lanes.  `lab` is called from
 // exactly one place.
+//
+// Query q of the sequence (0 = m, then step 1's ray, then step 2's two rays)
+// sets bit q of `evald` when it is evaluated and bit q of `bits` to its
+// label: the decision trace that a checker can replay.
 template <class Lab>
-__device__ double2 search_pair(const Job& j, const Lab& lab, int face, int slot, int& skipped) {
+__device__ double2 search_pair(const Job& j, const Lab& lab, int face, int slot, int& skipped,
+                               uint64_t& bits, uint64_t& evald) {
   const Grid& g = j.g;
   FaceFrame fr;
   face_pos(g, face, fr.a, fr.p);
@@ -798,6 +815,8 @@ __device__ double2 search_pair(const Job& j, const Lab& lab, int face, int slot,
   LineBinary lb;
   int sm = 0;
   skipped = 0;
+  bits = 0ull;
+  evald = 0ull;
   float q[2] = {m[0], m[1]}, q1[2] = {0, 0}, s1 = 0.0f;
   for (int step = 0; step < total; ++step) {
     // the query of this step
@@ -807,9 +826,8 @@ __device__ double2 search_pair(const Job& j, const Lab& lab, int face, int slot,
       P[0] = m[0];
       P[1] = m[1];
     } else {
-      k = step - 1;
-      if (k >= n1) k -= n1;
-      if (k >= n2) k -= n2;
+      // index of the query within its own ray
+      k = step <= n1 ? step - 1 : (step <= n1 + n2 ? step - 1 - n1 : step - 1 - n1 - n2);
       s = lb.param(k);
       lb.point(s, P);
     }
@@ -822,6 +840,10 @@ __device__ double2 search_pair(const Job& j, const Lab& lab, int face, int slot,
       add_at3(gp, fr.u, P[0]);
       add_at3(gp, fr.v, P[1]);
       l = lab(gp);
+      if (step < 64) {  // sequences longer than 64 queries are not traced
+        evald |= 1ull << step;
+        bits |= (uint64_t)l << step;
+      }
     } else {
       ++skipped;
     }
@@ -898,7 +920,12 @@ __global__ __launch_bounds__(256) void k_search2d_csg(const Job* __restrict__ jo
               CsgLabel lab{&J.g, J.prims, J.n_prims};
               const int rec = J.plist[x];
               int skipped;
-              J.pf[x] = search_pair(J, lab, rec >> 1, rec & 1, skipped);
+              uint64_t bits, evald;
+              J.pf[x] = search_pair(J, lab, rec >> 1, rec & 1, skipped, bits, evald);
+              if (J.ptrace) {
+                J.ptrace[2 * x] = bits;
+                J.ptrace[2 * x + 1] = evald;
+              }
             });
 }
 
@@ -918,8 +945,15 @@ __global__ __launch_bounds__(256) void k_search2d_mlp(const Job* __restrict__ jo
               MlpLabel lab{&J.g, &J.mlp, act};
               const int rec = J.plist[valid ? x : np - 1];
               int skipped;  // wave-uniform
-              const double2 r = search_pair(J, lab, rec >> 1, rec & 1, skipped);
-              if (valid && lane < 32) J.pf[x] = r;
+              uint64_t bits, evald;
+              const double2 r = search_pair(J, lab, rec >> 1, rec & 1, skipped, bits, evald);
+              if (valid && lane < 32) {
+                J.pf[x] = r;
+                if (J.ptrace) {
+                  J.ptrace[2 * x] = bits;
+                  J.ptrace[2 * x + 1] = evald;
+                }
+              }
               if (lane == 0 && skipped)
                 atomicAdd(&J.status[3],
                           (unsigned long long)skipped * (unsigned long long)min(32, np - t * 32));

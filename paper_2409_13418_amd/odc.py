@@ -22,7 +22,10 @@ INTERMEDIATES = {"labels": (0, np.uint32), "edge_ids": (1, np.int32), "edge_t": 
                  "pairs": (3, np.int32), "pair_pf": (4, np.float64), "cell_ids": (5, np.int32),
                  "cell_partmap": (6, np.uint32), "cell_nf": (7, np.uint32),
                  "vertex_base": (8, np.int32), "edge_case": (9, np.int32),
-                 "edge_grad": (10, np.float32)}
+                 "edge_grad": (10, np.float32), "edge_trace": (11, np.uint32),
+                 "pair_trace": (12, np.uint64)}
+_ELEM_BYTES = {"pair_pf": 16, "edge_grad": 12, "pair_trace": 16}
+_COLS = {"pair_pf": 2, "edge_grad": 3, "pair_trace": 2}
 
 
 class OdcError(RuntimeError):
@@ -96,7 +99,8 @@ EXPORTS = ("odc_status_string", "odc_last_error", "odc_context_create", "odc_con
            "odc_autotune", "odc_set_launch_config", "odc_server_create", "odc_server_destroy",
            "odc_server_last_error", "odc_server_footprint", "odc_server_submit",
            "odc_server_poll", "odc_server_wait", "odc_server_get_stats",
-           "odc_server_reset_stats", "odc_count_self_intersections")
+           "odc_server_reset_stats", "odc_count_self_intersections",
+           "odc_get_job_intermediate", "odc_context_set_trace")
 STAGES = ("labels", "classify", "compact", "bisect", "search2d", "cell_count", "cell_qef", "emit")
 
 _lib = None
@@ -131,6 +135,11 @@ def load(path: str = LIB_PATH):
     L.odc_get_intermediate.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64,
                                        C.POINTER(C.c_int64)]
     L.odc_get_intermediate.restype = C.c_int32
+    L.odc_get_job_intermediate.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                           C.c_int64, C.POINTER(C.c_int64)]
+    L.odc_get_job_intermediate.restype = C.c_int32
+    L.odc_context_set_trace.argtypes = [C.c_void_p, C.c_int32]
+    L.odc_context_set_trace.restype = C.c_int32
     L.odc_context_set_timing.argtypes = [C.c_void_p, C.c_int32]
     L.odc_context_set_timing.restype = C.c_int32
     L.odc_get_stage_times.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_int32,
@@ -425,24 +434,28 @@ class Context:
         self._check(load().odc_get_stage_times(self.h, ms, 8, C.byref(n)), "stage_times")
         return {STAGES[i]: float(ms[i]) for i in range(n.value)}
 
-    def intermediate(self, name: str) -> np.ndarray:
-        """A copy of one intermediate array of the last extraction (host numpy)."""
+    def intermediate(self, name: str, job: int = 0) -> np.ndarray:
+        """A copy of one intermediate array of job `job` of the last extraction
+        (host numpy)."""
         which, dt = INTERMEDIATES[name]
         L = load()
         n = C.c_int64()
-        rc = L.odc_get_intermediate(self.h, which, None, 0, C.byref(n))
+        rc = L.odc_get_job_intermediate(self.h, job, which, None, 0, C.byref(n))
         if rc not in (OK, ERR_CAPACITY):
-            self._check(rc, "odc_get_intermediate")
+            self._check(rc, "odc_get_job_intermediate")
         count = int(n.value)
-        elem = {"pair_pf": 16, "edge_grad": 12}.get(name, 4)
+        elem = _ELEM_BYTES.get(name, 4)
         t = self.torch.empty(max(count * elem, 4), dtype=self.torch.uint8, device=self.device)
-        rc = L.odc_get_intermediate(self.h, which, C.c_void_p(t.data_ptr()), count * elem,
-                                    C.byref(n))
-        self._check(rc, "odc_get_intermediate")
+        rc = L.odc_get_job_intermediate(self.h, job, which, C.c_void_p(t.data_ptr()),
+                                        count * elem, C.byref(n))
+        self._check(rc, "odc_get_job_intermediate")
         a = t[:count * elem].cpu().numpy().view(dt)
-        if name == "pair_pf":
-            return a.reshape(count, 2)
-        return a.reshape(count, 3) if name == "edge_grad" else a
+        return a.reshape(count, _COLS[name]) if name in _COLS else a
+
+    def set_trace(self, enable: bool):
+        """Record decision traces of the searches (intermediates edge_trace,
+        pair_trace) in later extractions."""
+        self._check(load().odc_context_set_trace(self.h, int(bool(enable))), "set_trace")
 
 
 class OutputBuffers:

@@ -7,10 +7,20 @@ import numpy as np
 import odc_inputs as I
 
 
-def gpu_run(field, grid, precision=0, ctx=None, want_local=True):
+VERT_TOL = 1e-5   # cell widths: the stated bar for 3D points
+MLP_TIE = 1e-5    # |logit| band the oracle treats as a near-tie (fp32 error < 2.4e-6)
+
+INTERMEDIATE_NAMES = ("labels", "edge_ids", "edge_t", "pairs", "pair_pf", "cell_ids",
+                      "cell_partmap", "cell_nf", "vertex_base", "edge_case", "edge_grad")
+
+
+def gpu_run(field, grid, precision=0, ctx=None, want_local=True, trace=True):
+    """Meshes one field through the C ABI and copies every intermediate back;
+    with trace, also the searches' decision traces (for a replayed oracle)."""
     from paper_2409_13418_amd import odc
     if ctx is None:
         ctx = odc.Context(0)
+    ctx.set_trace(trace)
     df = odc.DeviceField(field)
     params = odc.default_params(grid, precision)
     out = ctx.extract(df, params, want_local=want_local)
@@ -20,8 +30,7 @@ def gpu_run(field, grid, precision=0, ctx=None, want_local=True):
     if want_local:
         r["vertices_local"] = out["vertices_local"].cpu().numpy()
         r["vertex_ref"] = out["vertex_ref"].cpu().numpy()
-    for name in ("labels", "edge_ids", "edge_t", "pairs", "pair_pf", "cell_ids",
-                 "cell_partmap", "cell_nf", "vertex_base", "edge_case", "edge_grad"):
+    for name in INTERMEDIATE_NAMES + (("edge_trace", "pair_trace") if trace else ()):
         r[name] = ctx.intermediate(name)
     N = grid.res
     nc = (N + 1) ** 3
@@ -103,23 +112,6 @@ def edge_corners(e, N):
     return c0, p[0] + n1 * (p[1] + n1 * p[2])
 
 
-def sampled_labels(r, g, o, rng, n_uniform, n_edges):
-    """GPU corner labels against the oracle at uniform corners and at both ends
-    of sampled crossing edges; returns the number of near-ties skipped."""
-    n1 = g.res + 1
-    cs = list(rng.integers(0, n1 ** 3, n_uniform))
-    for e in r["edge_ids"][rng.integers(0, len(r["edge_ids"]), n_edges)]:
-        cs.extend(edge_corners(e, g.res))
-    ties = 0
-    for c in cs:
-        lab, tie = o.corner_label(*corner_ijk(int(c), n1))
-        if tie:
-            ties += 1
-            continue
-        assert r["corner_label"][c] == lab, int(c)
-    return len(cs), ties
-
-
 def interior_edge_count(edge_ids, N):
     """Crossing edges with all four cells inside the grid."""
     n1 = N + 1
@@ -138,3 +130,70 @@ def interior_edge_count(edge_ids, N):
                 inner &= (ijk[o] > 0) & (ijk[o] < N)
         interior[sel] = inner
     return int(interior.sum())
+
+
+def trace_of(O, r, staged=False, labels_given=False):
+    """The GPU run's recorded decisions (and, staged, its 1D and 2D points)
+    as an oracle replay trace."""
+    return O.Trace(label_words=r["labels"], edge_ids=r["edge_ids"], edge_bits=r["edge_trace"],
+                   edge_t=r["edge_t"], pair_rec=r["pairs"], pair_bits=r["pair_trace"],
+                   pair_pf=r["pair_pf"], staged=staged, labels_given=labels_given)
+
+
+def check_replayed(r, m, tr, res, label, vert_tol=VERT_TOL):
+    """The bar once the oracle has followed the GPU's branches at its own
+    near-ties: no other decision differs; integer structure, 1D points and 2D
+    points bit-identical; every vertex within vert_tol cell widths; quad
+    splits identical except where the binary64 triple product sits within its
+    error band.  Returns the largest vertex error."""
+    assert tr.mismatched == 0, (label, "decisions away from a near-tie differ", tr.mismatched)
+    assert tr.unmatched == 0, (label, tr.unmatched)
+    assert compare_discrete(r, m) == [], label
+    assert np.array_equal(r["edge_t"].astype(np.float64), m["edge_t"]), label
+    dp = np.abs(r["pair_pf"] - m["pair_pf"])
+    assert np.array_equal(r["pair_pf"], m["pair_pf"]), (label, float(dp.max()), int(np.argmax(dp) // 2))
+    nv = min(len(m["vert"]), r["n_vertices"])
+    dv = np.max(np.abs(vertex_grid_coords(r, res)[:nv] - m["vert"][:nv]), axis=1) if nv else np.zeros(0)
+    assert np.all(dv <= vert_tol), (label, float(dv.max()), int(np.argmax(dv)))
+    tie = m["edge_case_tie"] != 0
+    same = r["edge_case"] == m["edge_case"]
+    assert np.all(same | tie), (label, int(np.sum(~same & ~tie)))
+    if np.all(same):
+        assert len(r["vertices"]) == len(m["vert"]), label
+        assert np.array_equal(r["triangles"], m["tris"]), label
+    return float(dv.max()) if nv else 0.0
+
+
+def check_sampled_replayed(r, g, O, f, rng, n_corners, n_edges, n_pairs, n_cells, label):
+    """Seeded samples of a large grid, each recomputed one by one by the
+    replayed oracle (single-element calls that read the GPU's trace): corner
+    labels equal, 1D and 2D points bit-identical, partitions exact and
+    vertices within VERT_TOL.  Elements are drawn from the oracle-checked
+    label set's crossing lists; returns the adopted near-tie count."""
+    tr = trace_of(O, r)
+    o = O.Oracle(f, g, mlp_tie_eps=MLP_TIE, trace=tr)
+    n1 = g.res + 1
+    cs = list(rng.integers(0, n1 ** 3, n_corners))
+    for e in r["edge_ids"][rng.integers(0, len(r["edge_ids"]), n_corners // 2)]:
+        cs.extend(edge_corners(e, g.res))
+    for c in cs:
+        lab, tie = o.corner_label(*corner_ijk(int(c), n1))
+        assert tie == 0 and r["corner_label"][c] == lab, (label, int(c))
+    for x in rng.integers(0, len(r["edge_ids"]), n_edges):
+        t, ts = o.edge_point(int(r["edge_ids"][x]))
+        assert ts == 0 and float(r["edge_t"][x]) == t, (label, int(x), t)
+    for x in rng.integers(0, len(r["pairs"]), n_pairs):
+        rec = int(r["pairs"][x])
+        n, pf, info, tie = o.pair_point(rec >> 1, rec & 1)
+        assert n >= 1 and tie == 0, (label, int(x))
+        assert np.array_equal(r["pair_pf"][x], pf), (label, int(x), r["pair_pf"][x], pf)
+    vg = vertex_grid_coords(r, g.res)
+    for x in rng.integers(0, len(r["cell_ids"]), n_cells):
+        cid = int(r["cell_ids"][x])
+        n, verts, pm, tie = o.cell_vertices(cid)
+        assert n == int(r["cell_nf"][x] & 15) and pm == int(r["cell_partmap"][x]), (label, cid)
+        base = int(r["vertex_base"][x])
+        dv = np.max(np.abs(vg[base:base + n] - verts))
+        assert tie == 0 and dv <= VERT_TOL, (label, cid, dv, tie)
+    assert tr.mismatched == 0 and tr.unmatched == 0, (label, tr.mismatched, tr.unmatched)
+    return tr.adopted

@@ -5,8 +5,9 @@
   element by element, exactly as in the small parity tests.
 * MLP field at 256^3, bf16-guarded, default context (the configuration the
   benchmark times): the oracle evaluates the network in binary64, which is
-  too slow for the whole grid, so seeded samples of corners, crossing edges,
-  face pairs and active cells are recomputed one by one and compared, and
+  too slow for every search of the grid, so seeded samples of corners,
+  crossing edges, face pairs and active cells are recomputed one by one by
+  the oracle replaying the GPU's decision traces, at the small tests' bar;
   the properties that hold at any size are checked on the whole mesh.  The
   fp32 path on the same grid must give the same mesh bit for bit.
 """
@@ -15,12 +16,9 @@ import pytest
 
 import odc_inputs as I
 import meshcheck as M
-from gpu_common import compare_discrete, gpu_run, vertex_grid_coords
+from gpu_common import MLP_TIE, check_replayed, check_sampled_replayed, gpu_run, trace_of
 
 pytestmark = pytest.mark.gpu
-
-VERT_TOL = 1e-5   # cell widths
-MLP_TIE = 1e-5    # binary64 logit band treated as a near-tie (fp32 error < 2e-6)
 
 
 @pytest.fixture(scope="module")
@@ -35,20 +33,10 @@ def test_csg128_full_parity(ctx, oracle_mod):
     f = I.csg_random_field(2)
     g = I.unit_grid(128, 15)
     r, _ = gpu_run(f, g, ctx=ctx)
-    m = oracle_mod.Oracle(f, g).mesh()
-    assert compare_discrete(r, m) == []
-    assert np.array_equal(r["edge_t"].astype(np.float64), m["edge_t"])
-    pf = r["pair_pf"].astype(np.float64)
-    d = np.linalg.norm(pf - m["pair_pf"], axis=1)
-    tol = 1e-5 * (1 + np.linalg.norm(m["pair_pf"], axis=1)) / np.maximum(m["pair_sin"], 1e-3)
-    assert np.all(d <= tol), float(d.max())
-    nvp = int(m["cell_npart"].sum())
-    dv = np.max(np.abs(vertex_grid_coords(r, 128)[:nvp] - m["vert"][:nvp]), axis=1)
-    assert np.all((dv <= VERT_TOL) | (m["vert_tie"][:nvp] != 0)), float(dv.max())
-    tie = m["edge_case_tie"] != 0
-    assert np.all((r["edge_case"] == m["edge_case"]) | tie)
-    if np.all(r["edge_case"] == m["edge_case"]):
-        assert np.array_equal(r["triangles"], m["tris"])
+    tr = trace_of(oracle_mod, r)
+    m = oracle_mod.Oracle(f, g, trace=tr).mesh()
+    dvmax = check_replayed(r, m, tr, 128, "csg128")
+    assert tr.adopted == 0
     ok, why = M.is_closed_oriented_manifold(r["triangles"], r["n_vertices"])
     assert ok, why
     # Chamfer distance to the oracle's mesh: vertices within 1e-5 h bound it by 1e-10 h^2
@@ -56,7 +44,7 @@ def test_csg128_full_parity(ctx, oracle_mod):
     ch = M.chamfer_h2(r["vertices"], r["triangles"], vo, m["tris"], g.h, n=20000)
     assert ch <= 1e-10, ch
     print(f"csg128: {len(m['cell_id'])} cells, {len(m['tris'])} triangles, "
-          f"max vertex error {dv.max():.2e} cells, Chamfer vs oracle {ch:.2e} h^2")
+          f"max vertex error {dvmax:.2e} cells, Chamfer vs oracle {ch:.2e} h^2")
 
 
 @pytest.fixture(scope="module")
@@ -67,78 +55,15 @@ def mlp256(ctx):
     return f, g, r
 
 
-def _corner_ijk(c, n1):
-    return c % n1, (c // n1) % n1, c // (n1 * n1)
-
-
-def test_mlp256_sampled_labels(mlp256, oracle_mod):
+def test_mlp256_sampled_replayed(mlp256, oracle_mod):
+    """Seeded samples in the benchmark's configuration: 3,000 corners (half at
+    the ends of crossing edges), 150 crossing edges, 60 pairs and 40 cells,
+    each recomputed by the oracle replaying the GPU's traces."""
     f, g, r = mlp256
-    o = oracle_mod.Oracle(f, g, mlp_tie_eps=MLP_TIE)
-    n1 = g.res + 1
     rng = np.random.default_rng(11)
-    # uniform corners, and corners at the ends of crossing edges (next to the surface)
-    cs = list(rng.integers(0, n1 ** 3, 1500))
-    eids = r["edge_ids"][rng.integers(0, len(r["edge_ids"]), 1500)]
-    ea = g.res * n1 * n1
-    for e in eids:
-        a, loc = int(e) // ea, int(e) % ea
-        dims = [n1, n1, n1]
-        dims[a] = g.res
-        i = loc % dims[0]
-        j = (loc // dims[0]) % dims[1]
-        k = loc // (dims[0] * dims[1])
-        p = [i, j, k]
-        cs.append(p[0] + n1 * (p[1] + n1 * p[2]))
-        p[a] += 1
-        cs.append(p[0] + n1 * (p[1] + n1 * p[2]))
-    ties = 0
-    for c in cs:
-        lab, tie = o.corner_label(*_corner_ijk(int(c), n1))
-        if tie:
-            ties += 1
-            continue
-        assert r["corner_label"][c] == lab, int(c)
-    print(f"mlp256 labels: {len(cs)} sampled corners, {ties} near-ties")
-
-
-def test_mlp256_sampled_edges_pairs_cells(mlp256, oracle_mod):
-    f, g, r = mlp256
-    o = oracle_mod.Oracle(f, g, mlp_tie_eps=MLP_TIE)
-    rng = np.random.default_rng(12)
-    # 1D points: equal when the oracle's bisection met no near-tie, otherwise
-    # inside the bracket reached before the first near-tie step
-    ne = len(r["edge_ids"])
-    for x in rng.integers(0, ne, 150):
-        t, ts = o.edge_point(int(r["edge_ids"][x]))
-        d = abs(float(r["edge_t"][x]) - t)
-        assert d <= (0.0 if ts == 0 else 2.0 ** -(ts - 1)), (int(x), t, ts)
-    # 2D points: within the stated tolerance without a near-tie in the cone,
-    # within a quarter cell otherwise
-    npairs = len(r["pairs"])
-    clean = 0
-    for x in rng.integers(0, npairs, 60):
-        rec = int(r["pairs"][x])
-        n, pf, info, tie = o.pair_point(rec >> 1, rec & 1)
-        assert n >= 1
-        d = float(np.linalg.norm(r["pair_pf"][x] - pf))
-        if tie == 0:
-            clean += 1
-            # the binary32 bound of the small parity tests at the smallest
-            # admitted line angle (sin 1e-3)
-            assert d <= 1e-5 * (1 + np.linalg.norm(pf)) / 1e-3, (int(x), d)
-        assert d <= 0.25, (int(x), d)
-    # cells: partition structure exact; vertices within tolerance
-    nc = len(r["cell_ids"])
-    vg = vertex_grid_coords(r, g.res)
-    for x in rng.integers(0, nc, 40):
-        cid = int(r["cell_ids"][x])
-        n, verts, pm, tie = o.cell_vertices(cid)
-        assert n == int(r["cell_nf"][x] & 15), cid
-        assert pm == int(r["cell_partmap"][x]), cid
-        base = int(r["vertex_base"][x])
-        dv = np.max(np.abs(vg[base:base + n] - verts))
-        assert dv <= (VERT_TOL if tie == 0 else 0.25), (cid, dv, tie)
-    print(f"mlp256: 150 edges, 60 pairs ({clean} without near-tie), 40 cells checked")
+    adopted = check_sampled_replayed(r, g, oracle_mod, f, rng, 2000, 150, 60, 40, "mlp256")
+    print(f"mlp256: sampled elements at the small tests' bar; {adopted} near-tie "
+          f"decisions followed")
 
 
 def test_mlp256_mesh_properties(mlp256):

@@ -14,13 +14,11 @@ import pytest
 
 import odc_inputs as I
 import meshcheck as M
-from gpu_common import gpu_run, interior_edge_count, sampled_labels, vertex_grid_coords
+from gpu_common import check_sampled_replayed, gpu_run, interior_edge_count
 
 pytestmark = pytest.mark.gpu
 
 RES = 512
-VERT_TOL = 1e-5   # cell widths
-MLP_TIE = 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -41,56 +39,27 @@ def _mesh_properties(r, g):
     assert np.all(np.isfinite(r["vertices"]))
 
 
-def _sampled_elements(r, g, o, rng, exact_edges):
-    for x in rng.integers(0, len(r["edge_ids"]), 100):
-        t, ts = o.edge_point(int(r["edge_ids"][x]))
-        d = abs(float(r["edge_t"][x]) - t)
-        bound = 0.0 if (exact_edges or ts == 0) else 2.0 ** -(ts - 1)
-        assert d <= bound, (int(x), t, ts)
-    for x in rng.integers(0, len(r["pairs"]), 40):
-        rec = int(r["pairs"][x])
-        n, pf, info, tie = o.pair_point(rec >> 1, rec & 1)
-        assert n >= 1
-        d = float(np.linalg.norm(r["pair_pf"][x] - pf))
-        if tie == 0:
-            assert d <= 1e-5 * (1 + np.linalg.norm(pf)) / 1e-3, (int(x), d)
-        assert d <= 0.25, (int(x), d)
-    vg = vertex_grid_coords(r, g.res)
-    for x in rng.integers(0, len(r["cell_ids"]), 30):
-        cid = int(r["cell_ids"][x])
-        n, verts, pm, tie = o.cell_vertices(cid)
-        assert n == int(r["cell_nf"][x] & 15), cid
-        assert pm == int(r["cell_partmap"][x]), cid
-        base = int(r["vertex_base"][x])
-        dv = np.max(np.abs(vg[base:base + n] - verts))
-        assert dv <= (VERT_TOL if tie == 0 else 0.25), (cid, dv, tie)
-
-
 def test_mlp512(ctx, oracle_mod):
     f = I.mlp_field(3)
     g = I.unit_grid(RES, 15)
     r, _ = gpu_run(f, g, precision=1, ctx=ctx)
-    o = oracle_mod.Oracle(f, g, mlp_tie_eps=MLP_TIE)
     rng = np.random.default_rng(21)
-    n, ties = sampled_labels(r, g, o, rng, 1500, 750)
-    _sampled_elements(r, g, o, rng, exact_edges=False)
+    adopted = check_sampled_replayed(r, g, oracle_mod, f, rng, 1500, 100, 40, 30, "mlp512")
     _mesh_properties(r, g)
     assert r["n_guard_corners"] > 0
     print(f"mlp512: {len(r['cell_ids'])} cells, {len(r['triangles'])} triangles; "
-          f"{n} sampled corners ({ties} near-ties)")
+          f"{adopted} near-tie decisions followed in the samples")
 
 
 def test_csg512(ctx, oracle_mod):
     f = I.csg_random_field(2)
     g = I.unit_grid(RES, 15)
     r, _ = gpu_run(f, g, ctx=ctx)
-    o = oracle_mod.Oracle(f, g)
     rng = np.random.default_rng(22)
-    n, ties = sampled_labels(r, g, o, rng, 1500, 750)
-    assert ties == 0
-    _sampled_elements(r, g, o, rng, exact_edges=True)
+    adopted = check_sampled_replayed(r, g, oracle_mod, f, rng, 1500, 100, 40, 30, "csg512")
+    assert adopted == 0
     _mesh_properties(r, g)
-    print(f"csg512: {len(r['cell_ids'])} cells, {len(r['triangles'])} triangles; {n} sampled corners")
+    print(f"csg512: {len(r['cell_ids'])} cells, {len(r['triangles'])} triangles")
 
 
 def test_past_the_limit_is_rejected(ctx):

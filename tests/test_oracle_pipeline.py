@@ -94,7 +94,8 @@ def test_oracle_struct_layouts_match_its_header(tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
-    mirrors = {"orc_field": O._Field, "orc_params": O._Params, "orc_mesh": O._Mesh}
+    mirrors = {"orc_field": O._Field, "orc_params": O._Params, "orc_mesh": O._Mesh,
+               "orc_trace": O._Trace}
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "odc_oracle.h"',
              "int main(void) {"]
     for cname, cls in mirrors.items():
