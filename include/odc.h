@@ -186,6 +186,25 @@ int32_t odc_mesh_extract(odc_context* ctx, const odc_field* field, const odc_par
  * returning (the scratch estimate then grows for later calls). */
 int32_t odc_mesh_sync(odc_context* ctx, odc_mesh_counts* counts);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid it): odc_mesh_extract whose
+ * scratch (bit sets, active sets, packed weights, guard queue, counters)
+ * lives in one fixed device array of 192 MiB per GPU, held from library load
+ * until the process ends.  No hipMalloc, hipFree or allocating library call
+ * is made, and no graph is captured.  The crossing-edge capacity is the
+ * planned estimate, cut to what the array holds (a 256^3 grid fits; 512^3
+ * does not: OUT_OF_MEMORY with the sizes, before anything is launched).
+ * Asynchronous; wait with odc_mesh_sync, which then never regrows or reruns:
+ * active sets or a bf16 guard queue that outgrow the array give
+ * OUT_OF_MEMORY (the counts still hold what was found), and
+ * n_flipped_faces is -1.  Every call on a GPU shares that GPU's array and
+ * leaves its contents there until the next call: calls on one GPU that
+ * overlap (several contexts or streams) race, and an earlier extract's
+ * intermediates are gone after the next one.  Same arguments and errors as
+ * odc_mesh_extract otherwise. */
+int32_t odc_mesh_extract_noalloc(odc_context* ctx, const odc_field* field,
+                                 const odc_params* params, const odc_mesh_buffers* out);
+
 /* Batched meshing: n fields (each with its own params and output buffers) in
  * one launch per stage -- persistent kernels walk all jobs of the batch, so
  * many small or uneven shapes fill the GPU together.  Asynchronous; results

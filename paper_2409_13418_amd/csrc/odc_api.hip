@@ -8,6 +8,8 @@
 #include <string>
 #include <vector>
 
+#include <mutex>
+
 #include "odc_context.h"
 
 using namespace odc;
@@ -15,6 +17,17 @@ using namespace odc;
 namespace {
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Scratch of odc_mesh_extract_noalloc: one fixed array per GPU, alive until
+// the process ends.  Host code never uses its name as an address: each
+// device's copy is resolved once (fixed_scratch_of) and that pointer is what
+// kernels and copies get.
+constexpr size_t kFixedScratchBytes = size_t(192) << 20;
+static __device__ __align__(256) char scratch[kFixedScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;
+void* g_fixed_ptr[kMaxDevices] = {};
 
 }  // namespace
 
@@ -110,6 +123,22 @@ extern "C" void odc_params_default(odc_params* p, int32_t res) {
   p->guard_logit = (float)(2.0 * atanh(0.02));
 }
 
+// The device address of this device's fixed scratch array, looked up once
+// per device (with that device current) and kept.
+static int32_t fixed_scratch_of(odc_context* ctx) {
+  if (ctx->device < 0 || ctx->device >= kMaxDevices)
+    return fail(ctx, ODC_ERR_UNSUPPORTED, "device index %d above %d", ctx->device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_fixed_mu);
+  if (!g_fixed_ptr[ctx->device]) {
+    void* ptr = nullptr;
+    HIP_TRY(ctx, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(ctx, ODC_ERR_HIP, "fixed scratch array has no device address");
+    g_fixed_ptr[ctx->device] = ptr;
+  }
+  ctx->fixed_scratch = g_fixed_ptr[ctx->device];
+  return ODC_OK;
+}
+
 extern "C" int32_t odc_context_create(int32_t device, void* stream, odc_context** out) {
   if (!out) return ODC_ERR_INVALID_ARG;
   *out = nullptr;
@@ -149,6 +178,12 @@ extern "C" int32_t odc_context_create(int32_t device, void* stream, odc_context*
   if (rc == ODC_OK) rc = ensure(ctx, ctx->dgather, kMaxJobs * kGatherWords * sizeof(unsigned long long));
   if (rc == ODC_OK && launch_partition_table(P<uint32_t>(ctx->table), ctx->stream) != hipSuccess)
     rc = ODC_ERR_HIP;
+  // only odc_mesh_extract_noalloc needs the fixed array: a failed lookup is
+  // kept as its error instead of failing the context
+  if (rc == ODC_OK && fixed_scratch_of(ctx) != ODC_OK) {
+    ctx->fixed_err = ctx->err;
+    (void)hipGetLastError();
+  }
   if (rc == ODC_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) rc = ODC_ERR_HIP;
   if (rc != ODC_OK) {
     odc_context_destroy(ctx);
@@ -552,6 +587,7 @@ int32_t odc::enqueue_batch(odc_context* ctx, int n, const odc_field* fields,
   for (int k = 0; k < n; ++k) TRY(setup_job(ctx, k, &fields[k], &params[k], &outs[k], 0));
   TRY(run_batch(ctx, n));
   ctx->pending = n;
+  ctx->pending_fixed = false;
   ctx->p_fields.assign(fields, fields + n);
   ctx->p_params.assign(params, params + n);
   ctx->p_outs.assign(outs, outs + n);
@@ -561,6 +597,78 @@ int32_t odc::enqueue_batch(odc_context* ctx, int n, const odc_field* fields,
 extern "C" int32_t odc_mesh_extract(odc_context* ctx, const odc_field* field,
                                     const odc_params* params, const odc_mesh_buffers* out) {
   return enqueue_batch(ctx, 1, field, params, out);
+}
+
+// The allocation-free variant: the job's scratch is carved out of the
+// device's fixed array, no graph is captured, and an overflow is reported
+// rather than regrown.  Nothing here allocates: the job record goes through
+// the context's pinned mirror into its device job array (both made at
+// context creation).
+extern "C" int32_t odc_mesh_extract_noalloc(odc_context* ctx, const odc_field* f,
+                                            const odc_params* p, const odc_mesh_buffers* o) {
+  if (!ctx) return ODC_ERR_INVALID_ARG;
+  TRY(validate_job(ctx, f, p, o));
+  if (!ctx->fixed_scratch)
+    return fail(ctx, ODC_ERR_HIP, "fixed scratch unavailable: %s", ctx->fixed_err.c_str());
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if (ctx->pending) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->pending = 0;
+  // crossing-edge capacity: the planned estimate, cut to what the array holds
+  Job& J = ctx->hjobs[0];
+  const int N = p->res;
+  int ce = estimate_edges(ctx->cap_scale, N);
+  job_scalars(J, f, p, ce);
+  Layout L = job_layout(J, f, false, false);
+  if (L.total() > kFixedScratchBytes) {
+    job_scalars(J, f, p, 64);
+    const Layout L0 = job_layout(J, f, false, false);
+    job_scalars(J, f, p, 65536 + 64);
+    const Layout L1 = job_layout(J, f, false, false);
+    const double per_edge = (double)(L1.total() - L0.total()) / 65536.0;
+    const double room = (double)kFixedScratchBytes - (double)L0.total();
+    ce = room > per_edge * 4096 ? 64 + (int)(room / per_edge) - 256 : 0;
+    if (ce < 4096)
+      return fail(ctx, ODC_ERR_OUT_OF_MEMORY,
+                  "res %d needs %zu bytes of scratch beyond the active sets; the fixed array "
+                  "holds %zu",
+                  N, L0.total(), kFixedScratchBytes);
+    job_scalars(J, f, p, ce);
+    L = job_layout(J, f, false, false);
+    while (L.total() > kFixedScratchBytes && ce > 4096) {
+      ce -= 1024;
+      job_scalars(J, f, p, ce);
+      L = job_layout(J, f, false, false);
+    }
+    if (L.total() > kFixedScratchBytes)
+      return fail(ctx, ODC_ERR_OUT_OF_MEMORY, "res %d does not fit the fixed scratch of %zu bytes",
+                  N, kFixedScratchBytes);
+  }
+  char* b = (char*)ctx->fixed_scratch;
+  job_bind(J, L, f, b, b + L.grid_total, b + L.grid_total + L.active_total,
+           b + L.grid_total + L.active_total + L.mlpw,
+           b + L.grid_total + L.active_total + L.mlpw + L.guard);
+  J.out_v = o->vertices;
+  J.cap_v = o->cap_vertices;
+  J.out_t = o->triangles;
+  J.cap_t = o->cap_triangles;
+  J.out_vloc = o->vertices_local;
+  J.out_vref = o->vertex_ref;
+  ctx->hweights[0] = f->kind == ODC_FIELD_MLP ? f->weights : nullptr;
+  hipStream_t s = ctx->stream;
+  HIP_TRY(ctx, hipMemcpyAsync(P<Job>(ctx->djobs), ctx->hjobs, sizeof(Job),
+                              hipMemcpyHostToDevice, s));
+  HIP_TRY(ctx, hipMemcpyAsync(P<const float*>(ctx->dweights), ctx->hweights, sizeof(float*),
+                              hipMemcpyHostToDevice, s));
+  const PipelineShape sh = shape_of(ctx, 1);
+  HIP_TRY(ctx, launch_pipeline(P<Job>(ctx->djobs), 1, sh, P<const float*>(ctx->dweights),
+                               P<uint32_t>(ctx->table), ctx->cfg,
+                               ctx->timing ? ctx->ev : nullptr, s));
+  HIP_TRY(ctx, launch_gather(P<Job>(ctx->djobs), 1, P<unsigned long long>(ctx->dgather), s));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->hgather, P<unsigned long long>(ctx->dgather),
+                              kGatherWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  ctx->pending = 1;
+  ctx->pending_fixed = true;
+  return ODC_OK;
 }
 
 extern "C" int32_t odc_mesh_extract_batch(odc_context* ctx, int32_t n, const odc_field* fields,
@@ -594,6 +702,14 @@ static int32_t finish(odc_context* ctx) {
     bool over = false;
     for (int k = 0; k < n; ++k) over |= job_overflowed(ctx, k);
     if (!over) return ODC_OK;
+    if (ctx->pending_fixed) {
+      bool gover = false;
+      const int need = needed_edges(ctx, 0, &gover);
+      return fail(ctx, ODC_ERR_OUT_OF_MEMORY,
+                  gover ? "the bf16 guard queue in the fixed scratch overflowed"
+                        : "active sets need %d crossing edges; the fixed scratch held %d",
+                  need, ctx->hjobs[0].cap_edges);
+    }
     if (attempt >= 2) return fail(ctx, ODC_ERR_OUT_OF_MEMORY, "scratch overflow persists");
     for (int k = 0; k < n; ++k) {
       bool gover = false;
@@ -663,7 +779,8 @@ extern "C" int32_t odc_mesh_sync(odc_context* ctx, odc_mesh_counts* c) {
   if (!ctx || !c) return ODC_ERR_INVALID_ARG;
   if (ctx->pending != 1) return fail(ctx, ODC_ERR_INVALID_ARG, "no single extract pending");
   int32_t rc = odc_mesh_sync_batch(ctx, 1, c);
-  if (rc == ODC_OK || rc == ODC_ERR_CAPACITY) TRY(count_flips(ctx, 0, &c->n_flipped_faces));
+  if ((rc == ODC_OK || rc == ODC_ERR_CAPACITY) && !ctx->pending_fixed)
+    TRY(count_flips(ctx, 0, &c->n_flipped_faces));
   return rc;
 }
 
@@ -780,6 +897,7 @@ extern "C" int32_t odc_field_eval(odc_context* ctx, const odc_field* f, int32_t 
   if (n == 0) return ODC_OK;
   if (ctx->pending) TRY(finish(ctx));
   ctx->pending = 0;
+  ctx->pending_fixed = false;
   if (ctx->slots.empty()) ctx->slots.resize(1);
   TRY(setup_job(ctx, 0, f, &p, &o, 0));
   HIP_TRY(ctx, hipMemcpyAsync(P<Job>(ctx->djobs), ctx->hjobs, sizeof(Job),

@@ -53,6 +53,11 @@ struct odc_context {
   odc::LaunchCfg cfg;
   double cap_scale = 1.0;
   bool trace = false;  // record decision traces of the searches
+  // the device's fixed scratch array (odc_mesh_extract_noalloc), and whether
+  // the pending extract lives in it (then it is never regrown or rerun)
+  void* fixed_scratch = nullptr;
+  std::string fixed_err;
+  bool pending_fixed = false;
   // timing
   bool timing = false;
   hipEvent_t ev[9] = {};
