@@ -1096,7 +1096,13 @@ static int cell_solve(const cell_ctx* cx, const int c[3], double* verts, int* pa
         g[axis] = (float)gpos[axis] + (float)t;
         grid_to_world(p, g, xw);
         double xd[3] = {xw[0], xw[1], xw[2]}, gr[3];
-        mlp_eval(cx->f, xd, gr);
+        const orc_trace* st = p->trace;
+        int64_t sx = st && st->staged && st->edge_grad ? trace_edge_slot(st, edge_id(N, axis, gpos))
+                                                       : -1;
+        if (sx >= 0)  /* staged: the implementation's gradient */
+          for (int q = 0; q < 3; ++q) gr[q] = st->edge_grad[3 * sx + q];
+        else
+          mlp_eval(cx->f, xd, gr);
         double gl = sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
         for (int q = 0; q < 3; ++q) {
           row[q] = gl > 0.0 ? gr[q] / gl : 0.0;
@@ -1226,7 +1232,14 @@ int orc_mesh_extract(const orc_field* f, const orc_params* p, orc_mesh* m) {
   if (!valid_params(f, p)) return -1;
   if (f->kind == ORC_FIELD_MLP && 3 + 6 * f->n_bands != f->in_dim) return -1;
 #ifdef _OPENMP
-  if (p->n_threads > 0) omp_set_num_threads(p->n_threads);
+  /* n_threads = 0: the process default (OMP_NUM_THREADS or all cores), also
+   * after an earlier call asked for fewer */
+  static int default_threads = 0;
+#pragma omp critical(orc_threads)
+  {
+    if (default_threads == 0) default_threads = omp_get_max_threads();
+  }
+  omp_set_num_threads(p->n_threads > 0 ? p->n_threads : default_threads);
 #endif
   int N = p->res;
   m->res = N;

@@ -80,8 +80,10 @@ typedef struct {
  *                 queries past the 64th are untraced.
  *   staged        1: the 2D searches start from edge_t (the implementation's
  *                 1D points) and the QEF takes edge_t and pair_pf (its 2D
- *                 points) instead of the oracle's own; the outputs still hold
- *                 the oracle's own 1D and 2D points.
+ *                 points), and with gradient normals edge_grad (its dz/dx at
+ *                 each 1D point, 3 per crossing edge), instead of the
+ *                 oracle's own; the outputs still hold the oracle's own 1D
+ *                 and 2D points.
  * Counters (outputs, accumulated over calls): adopted = near-tie decisions
  * that took the recorded branch; mismatched = decisions away from a near-tie
  * that differ from the recorded one (a failure of the implementation);
@@ -98,6 +100,7 @@ typedef struct {
   const int32_t* pair_rec;
   const uint64_t* pair_bits;
   const double* pair_pf;
+  const float* edge_grad;
   int staged;
   int64_t adopted, mismatched, unmatched;
 } orc_trace;

@@ -42,7 +42,7 @@ class _Trace(C.Structure):
                 ("edge_bits", C.POINTER(C.c_uint32)), ("edge_t", C.POINTER(C.c_float)),
                 ("n_pairs", C.c_int64), ("pair_rec", C.POINTER(C.c_int32)),
                 ("pair_bits", C.POINTER(C.c_uint64)), ("pair_pf", C.POINTER(C.c_double)),
-                ("staged", C.c_int), ("adopted", C.c_int64), ("mismatched", C.c_int64),
+                ("edge_grad", C.POINTER(C.c_float)), ("staged", C.c_int), ("adopted", C.c_int64), ("mismatched", C.c_int64),
                 ("unmatched", C.c_int64)]
 
 
@@ -65,17 +65,18 @@ class Trace:
 
     def __init__(self, label_words=None, edge_ids=None, edge_bits=None, edge_t=None,
                  pair_rec=None, pair_bits=None, pair_pf=None, staged=False,
-                 labels_given=False):
+                 labels_given=False, edge_grad=None):
         def keep(a, dt):
             return None if a is None else np.ascontiguousarray(a, dt)
         self._a = {"label_words": keep(label_words, np.uint32),
                    "edge_id": keep(edge_ids, np.int32), "edge_bits": keep(edge_bits, np.uint32),
                    "edge_t": keep(edge_t, np.float32), "pair_rec": keep(pair_rec, np.int32),
-                   "pair_bits": keep(pair_bits, np.uint64), "pair_pf": keep(pair_pf, np.float64)}
+                   "pair_bits": keep(pair_bits, np.uint64), "pair_pf": keep(pair_pf, np.float64),
+                   "edge_grad": keep(edge_grad, np.float32)}
         t = _Trace()
         ctypes_of = {"label_words": C.c_uint32, "edge_id": C.c_int32, "edge_bits": C.c_uint32,
                      "edge_t": C.c_float, "pair_rec": C.c_int32, "pair_bits": C.c_uint64,
-                     "pair_pf": C.c_double}
+                     "pair_pf": C.c_double, "edge_grad": C.c_float}
         for k, a in self._a.items():
             if a is not None:
                 setattr(t, k, a.ctypes.data_as(C.POINTER(ctypes_of[k])))

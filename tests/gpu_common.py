@@ -135,9 +135,11 @@ def interior_edge_count(edge_ids, N):
 def trace_of(O, r, staged=False, labels_given=False):
     """The GPU run's recorded decisions (and, staged, its 1D and 2D points)
     as an oracle replay trace."""
+    grad = r.get("edge_grad")
     return O.Trace(label_words=r["labels"], edge_ids=r["edge_ids"], edge_bits=r["edge_trace"],
                    edge_t=r["edge_t"], pair_rec=r["pairs"], pair_bits=r["pair_trace"],
-                   pair_pf=r["pair_pf"], staged=staged, labels_given=labels_given)
+                   pair_pf=r["pair_pf"], staged=staged, labels_given=labels_given,
+                   edge_grad=grad if grad is not None and len(grad) else None)
 
 
 def check_replayed(r, m, tr, res, label, vert_tol=VERT_TOL):
@@ -152,15 +154,18 @@ def check_replayed(r, m, tr, res, label, vert_tol=VERT_TOL):
     assert np.array_equal(r["edge_t"].astype(np.float64), m["edge_t"]), label
     dp = np.abs(r["pair_pf"] - m["pair_pf"])
     assert np.array_equal(r["pair_pf"], m["pair_pf"]), (label, float(dp.max()), int(np.argmax(dp) // 2))
-    nv = min(len(m["vert"]), r["n_vertices"])
-    dv = np.max(np.abs(vertex_grid_coords(r, res)[:nv] - m["vert"][:nv]), axis=1) if nv else np.zeros(0)
-    assert np.all(dv <= vert_tol), (label, float(dv.max()), int(np.argmax(dv)))
     tie = m["edge_case_tie"] != 0
     same = r["edge_case"] == m["edge_case"]
     assert np.all(same | tie), (label, int(np.sum(~same & ~tie)))
+    # partition vertices, then (when the quad splits agree, so that the lists
+    # align) the case-3 vertices appended after them
+    nv = int(m["cell_npart"].sum())
     if np.all(same):
         assert len(r["vertices"]) == len(m["vert"]), label
         assert np.array_equal(r["triangles"], m["tris"]), label
+        nv = len(m["vert"])
+    dv = np.max(np.abs(vertex_grid_coords(r, res)[:nv] - m["vert"][:nv]), axis=1) if nv else np.zeros(0)
+    assert np.all(dv <= vert_tol), (label, float(dv.max()), int(np.argmax(dv)))
     return float(dv.max()) if nv else 0.0
 
 

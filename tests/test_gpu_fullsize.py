@@ -11,12 +11,15 @@
   the properties that hold at any size are checked on the whole mesh.  The
   fp32 path on the same grid must give the same mesh bit for bit.
 """
+import os
+
 import numpy as np
 import pytest
 
 import odc_inputs as I
 import meshcheck as M
-from gpu_common import MLP_TIE, check_replayed, check_sampled_replayed, gpu_run, trace_of
+from gpu_common import (MLP_TIE, check_replayed, check_sampled_replayed, compare_discrete,
+                        gpu_run, trace_of)
 
 pytestmark = pytest.mark.gpu
 
@@ -53,6 +56,35 @@ def mlp256(ctx):
     g = I.unit_grid(256, 15)
     r, _ = gpu_run(f, g, precision=1, ctx=ctx)
     return f, g, r
+
+
+GOLDEN_LABELS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                             "mlp256_labels.npz")
+
+
+def test_mlp256_whole_grid_topology(mlp256, oracle_mod):
+    """Every one of the 16,974,593 corner labels of the benchmark's grid
+    against the oracle's (tests/golden/mlp256_labels.npz, written by
+    make_mlp256_labels.py from the binary64 network): equal except at the
+    oracle's near-ties, where either label is a correct binary32 evaluation.
+    Then the oracle's topology from those labels (crossing edges, face
+    pairs, manifold flips, active cells, partitions, vertex numbering)
+    against the GPU's whole active sets, bit for bit."""
+    f, g, r = mlp256
+    gold = np.load(GOLDEN_LABELS)
+    assert int(gold["res"]) == g.res and int(gold["seed"]) == 3
+    nc = (g.res + 1) ** 3
+    lab = np.unpackbits(gold["label_bits"], bitorder="little")[:nc]
+    diff = np.nonzero(r["corner_label"] != lab)[0]
+    ties = gold["tie_corners"]
+    assert np.all(np.isin(diff, ties)), diff[~np.isin(diff, ties)][:10]
+    tr = oracle_mod.Trace(label_words=r["labels"], labels_given=True)
+    m = oracle_mod.Oracle(f, g, trace=tr, topology_only=True).mesh()
+    assert compare_discrete(r, m) == []
+    assert len(m["edge_id"]) == r["n_active_edges"] and len(m["cell_id"]) == r["n_active_cells"]
+    print(f"mlp256 whole grid: {nc} corners ({len(ties)} oracle near-ties, {len(diff)} taken the "
+          f"other way), {len(m['edge_id'])} crossing edges, {len(m['pair_face'])} pairs, "
+          f"{len(m['cell_id'])} cells, {m['n_flipped_faces']} flipped faces: all equal")
 
 
 def test_mlp256_sampled_replayed(mlp256, oracle_mod):
