@@ -8,6 +8,14 @@ occupancy queries included) of that field with its inputs resident in HBM.
 Metric: active cells meshed per second.
 
 Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+Besides the timed steps, the line carries (all outside the timed region):
+the dominant kernel's roofline; the plain fp32 path's throughput on the same
+grid and whether its mesh equals the guarded path's (fp32_path); the paper's
+quality measures of the mesh; a short Poisson serving trace through the
+continuous-batching server (serve: p50/p99 latency, cells/s; --serve-requests-
+default requests after --serve-warmup-default-s seconds of arrivals); the
+Chamfer distance of both paths' meshes to the oracle's on sub-boxes; and the
+oracle's own rate on all host threads and on one (cpu_baseline).
 
 Other modes (not run by default):
   --mode batch  64 seeded shapes (32 CSG, 32 MLP fields; res uniform over
@@ -79,13 +87,15 @@ def measured_traffic(kernel: str):
     return value if sha == kernel_sources_sha256() else None
 
 
-def cpu_baseline(field, grid, seconds: float, sub: int = 16, seed: int = 0, chamfer=None) -> dict:
+def cpu_baseline(field, grid, seconds: float, sub: int = 16, seed: int = 0, chamfer=None,
+                 threads: int = 0) -> dict:
     """The oracle, untuned, on sub-boxes of the same grid (same h, same field)
     centred on seeded points of the sdf spheres' surfaces, until `seconds` of
-    CPU time have been spent.  Returns active cells per second.  With
-    `chamfer` = (context, device field, precision), the first sub-boxes are
-    also meshed on the GPU and the Chamfer distance to the oracle's mesh is
-    reported (outside the timed part)."""
+    wall time have been spent, on `threads` host threads (0 = all).  Returns
+    active cells per second.  With `chamfer` = (context, device field,
+    {name: precision}), the first sub-boxes are also meshed on the GPU at each
+    precision and the Chamfer distance to the oracle's mesh is reported
+    (outside the timed part)."""
     from oracle import oracle as O
     O.build()
     rng = np.random.default_rng(seed)
@@ -93,7 +103,7 @@ def cpu_baseline(field, grid, seconds: float, sub: int = 16, seed: int = 0, cham
     cells = 0
     spent = 0.0
     boxes = 0
-    cham = []
+    cham = {}
     while spent < seconds:
         s = field.spheres[rng.integers(len(field.spheres))].astype(np.float64)
         d = rng.standard_normal(3)
@@ -104,28 +114,32 @@ def cpu_baseline(field, grid, seconds: float, sub: int = 16, seed: int = 0, cham
         lo = tuple(float(grid.lo[a] + origin[a] * h) for a in range(3))
         g2 = I.Grid(lo=lo, size=sub * h, res=sub, iters_1d=grid.iters_1d)
         t0 = time.perf_counter()
-        m = O.Oracle(field, g2, mlp_tie_eps=1e-5).mesh()
+        m = O.Oracle(field, g2, mlp_tie_eps=1e-5, n_threads=threads).mesh()
         spent += time.perf_counter() - t0
         cells += len(m["cell_id"])
         boxes += 1
-        if chamfer is not None and len(cham) < 4 and len(m["tris"]):
+        if chamfer is not None and boxes <= 4 and len(m["tris"]):
             from paper_2409_13418_amd import odc
             sys.path.insert(0, os.path.join(ROOT, "tests"))
             from meshcheck import chamfer_h2
-            ctx, df, prec = chamfer
-            r = ctx.extract(df, odc.default_params(g2, prec))
+            ctx, df, precs = chamfer
             vo = np.asarray(g2.lo) + m["vert"] * h
-            cham.append(chamfer_h2(r["vertices"].cpu().numpy(), r["triangles"].cpu().numpy(),
-                                   vo, m["tris"], h, n=20000, seed=boxes))
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    out = {"value": cells / spent, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            for name, prec in precs.items():
+                r = ctx.extract(df, odc.default_params(g2, prec))
+                cham.setdefault(name, []).append(
+                    chamfer_h2(r["vertices"].cpu().numpy(), r["triangles"].cpu().numpy(), vo,
+                               m["tris"], h, n=20000, seed=boxes))
+    used = threads or int(os.environ.get("OMP_NUM_THREADS", "0")) or \
+        len(os.sched_getaffinity(0))
+    out = {"value": cells / spent, "unit": "cells/s", "cores": used, "kind": "oracle",
            "sample": f"{boxes} sub-boxes of {sub}^3 cells at the benchmark's h around seeded "
                      f"sphere-surface points, {cells} active cells in {spent:.1f} s"}
     if cham:
         out["chamfer_vs_oracle"] = {
-            "value": max(cham), "unit": "h^2", "boxes": len(cham),
+            **{name: max(v) for name, v in cham.items()}, "unit": "h^2",
+            "boxes": len(next(iter(cham.values()))),
             "method": "symmetric mean squared point-to-surface distance, 20k area samples per "
-                      "mesh, GPU mesh of the same sub-box at the benchmark's precision; max over boxes"}
+                      "mesh, GPU mesh of the same sub-box at each precision; max over boxes"}
     return out
 
 
@@ -203,15 +217,21 @@ def _batch_mode(args):
 
 def _serve_mode(args):
     """Poisson request trace through the serving loop."""
+    print(json.dumps(serve_run(args, args.serve_requests, args.serve_warmup_s)), flush=True)
+
+
+def serve_run(args, n_requests: int, warm_s: float) -> dict:
+    """Replays a seeded Poisson trace of n_requests (after warm_s seconds of
+    warm-up arrivals) through the continuous-batching server; returns the
+    latency percentiles (completion - submission) and active cells/s."""
     import threading
 
     import torch
     from paper_2409_13418_amd import odc
 
-    warm_s = args.serve_warmup_s
     rate = args.serve_rate
     n_warm = int(round(warm_s * rate))
-    trace = I.serve_trace(n_warm + args.serve_requests, rate, 5)
+    trace = I.serve_trace(n_warm + n_requests, rate, 5)
     prec = odc.PREC_BF16_GUARDED if args.precision == "bf16" else odc.PREC_FP32
     # a pool of seeded fields per kind (the trace's field seed modulo the pool)
     pool = 16
@@ -294,10 +314,10 @@ def _serve_mode(args):
     out = {
         "metric": "serve latency p50/p99 and active cells/sec",
         "value": st["cells_per_s"], "unit": "cells/s", "n_gpus": 1,
-        "steps": args.serve_requests, "warmup": n_warm, "ms_per_step": None,
+        "steps": n_requests, "warmup": n_warm, "ms_per_step": None,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16+fp32" if prec == odc.PREC_BF16_GUARDED else "fp32", "data": "synthetic",
-        "config": {"workload": "serve_poisson", "rate_per_s": rate, "requests": args.serve_requests,
+        "config": {"workload": "serve_poisson", "rate_per_s": rate, "requests": n_requests,
                    "warmup_s": warm_s, "mix": "50/50 CSG/MLP", "res_weights":
                    {"64": 0.4, "128": 0.3, "256": 0.2, "512": 0.1}, "lanes": args.serve_lanes,
                    "budget_gib": args.serve_budget_gib, "field_pool": pool,
@@ -311,7 +331,7 @@ def _serve_mode(args):
         "p50_ms_by_res": {str(k): float(np.percentile(v, 50)) for k, v in sorted(by_res.items())},
         "p99_ms_by_res": {str(k): float(np.percentile(v, 99)) for k, v in sorted(by_res.items())},
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def _ablation_mode(args):
@@ -415,6 +435,12 @@ def main():
     ap.add_argument("--precision", choices=("bf16", "fp32"), default="bf16")
     ap.add_argument("--res", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds-1core", type=float, default=10.0)
+    ap.add_argument("--fp32-steps", type=int, default=4,
+                    help="timed steps of the plain fp32 path after the guarded path's")
+    ap.add_argument("--serve-requests-default", type=int, default=300,
+                    help="requests of the Poisson trace served after the timed steps (0: none)")
+    ap.add_argument("--serve-warmup-default-s", type=float, default=3.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -518,10 +544,39 @@ def main():
         "roofline": roofline,
         "roofline_stages": roofline_stages,
     }
+    # the plain fp32 path on the same grid (every query on fp32 matrix cores),
+    # outside the timed region above: its throughput and whether its mesh is
+    # the guarded path's
+    if prec == odc.PREC_BF16_GUARDED and args.fp32_steps > 0:
+        mesh_g = ctx.extract(df, params)["triangles"].cpu().numpy().copy()
+        params32 = odc.default_params(grid, odc.PREC_FP32)
+        ctx.extract(df, params32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.fp32_steps):
+            ctx.extract_async(df, params32, cap_hint=(ctx.cap_v, ctx.cap_t))
+            c32 = ctx.sync()
+        torch.cuda.synchronize()
+        ms32 = (time.perf_counter() - t0) * 1e3 / args.fp32_steps
+        same = np.array_equal(ctx.extract(df, params32)["triangles"].cpu().numpy(), mesh_g)
+        out["fp32_path"] = {"value": c32["n_active_cells"] / (ms32 / 1e3), "unit": "cells/s",
+                            "ms_per_step": ms32, "steps": args.fp32_steps,
+                            "stages_ms": ctx.stage_times(), "same_mesh_as_bf16": bool(same)}
     out["quality"] = mesh_quality(ctx, df, grid, params=params)
+    if args.serve_requests_default > 0:
+        sv = serve_run(args, args.serve_requests_default, args.serve_warmup_default_s)
+        out["serve"] = {k: sv[k] for k in ("p50_ms", "p99_ms", "mean_ms", "max_ms", "completed",
+                                          "failed", "batches", "window_s", "p50_ms_by_res",
+                                          "p99_ms_by_res")}
+        out["serve"].update({"cells_per_s": sv["value"], "config": sv["config"]})
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(field, grid, args.cpu_seconds, chamfer=(ctx, df, prec))
+        precs = {"bf16": prec}
+        if prec == odc.PREC_BF16_GUARDED:
+            precs["fp32"] = odc.PREC_FP32
+        cb = cpu_baseline(field, grid, args.cpu_seconds, chamfer=(ctx, df, precs))
         cham = cb.pop("chamfer_vs_oracle", None)
+        one = cpu_baseline(field, grid, args.cpu_seconds_1core, seed=1, threads=1)
+        cb["one_core"] = {k: one[k] for k in ("value", "unit", "cores", "sample")}
         out["cpu_baseline"] = cb
         if cham is not None:
             out["chamfer_vs_oracle"] = cham

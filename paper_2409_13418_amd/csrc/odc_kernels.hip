@@ -1119,10 +1119,15 @@ __device__ __forceinline__ bool edge_plane(const Job& j, const int c[3], int fm,
 // one pseudo-inverse application plus one refinement step on the binary64
 // residual, x += A^+_tau (b - A x): the retained eigenvalues can be as small
 // as tau * max, which would amplify the binary32 rounding of the
-// decomposition ~1/tau-fold, and the refinement removes that.  Returns
-// false when T is float and the normal matrix's condition number exceeds
-// fp64_cond (including a singular matrix); the caller then redoes the
-// decomposition in binary64.
+// decomposition ~1/tau-fold, and the refinement removes that.  The
+// refinement cannot repair the kept subspace itself, which a binary32
+// decomposition resolves only to ~2^-24 lambda_max / gap (Davis-Kahan; gap =
+// smallest kept minus largest dropped eigenvalue): measured errors reach
+// 3 * 2^-24 / gap cell widths.  Returns false when T is float and either the
+// normal matrix's condition number exceeds fp64_cond (including a singular
+// matrix) or, with an eigenvalue dropped, gap < kQefMinGap lambda_max (error
+// bound 3.6e-6 cell widths); the caller then redoes the decomposition in
+// binary64.
 // The gradient-normal ablation's plane at crossing edge le of cell c: the
 // 1D point and the normalised logit gradient there (binary64 from the
 // binary32 gradient).  Returns false for a zero gradient.
@@ -1148,6 +1153,8 @@ __device__ __forceinline__ bool edge_grad_plane(const Job& j, const int c[3], in
   for (int k = 0; k < 3; ++k) n[k] /= nl;
   return true;
 }
+
+constexpr float kQefMinGap = 0.05f;
 
 template <typename T>
 __device__ bool qef_partition(const Job& j, const int c[3], int cfg, int fm, uint32_t pm,
@@ -1208,6 +1215,15 @@ __device__ bool qef_partition(const Job& j, const int c[3], int cfg, int fm, uin
   const T lmin = fmin(ev[0], fmin(ev[1], ev[2]));
   if (sizeof(T) == 4 && (lmin <= T(0) || (double)lmax > j.fp64_cond * (double)lmin)) return false;
   const T thr = (T)j.qef_tau * lmax;
+  if (sizeof(T) == 4) {
+    T kept_min = lmax, dropped_max = T(-1);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (ev[k] >= thr) kept_min = fmin(kept_min, ev[k]);
+      else dropped_max = fmax(dropped_max, ev[k]);
+    }
+    if (dropped_max >= T(0) && kept_min - dropped_max < T(kQefMinGap) * lmax) return false;
+  }
   double y[3] = {0, 0, 0};
   for (int pass = 0; pass < 2; ++pass) {
     double r[3];
