@@ -205,6 +205,23 @@ int32_t odc_mesh_sync(odc_context* ctx, odc_mesh_counts* counts);
 int32_t odc_mesh_extract_noalloc(odc_context* ctx, const odc_field* field,
                                  const odc_params* params, const odc_mesh_buffers* out);
 
+/* Device scratch that an extraction of this field and grid needs, computed on
+ * the host alone (no device, no context): *bytes = what odc_mesh_extract
+ * allocates for it at the planned crossing-edge capacity (bit sets over the
+ * grid, active sets, packed weights, guard queue); *fits_fixed (may be NULL)
+ * = 1 when odc_mesh_extract_noalloc accepts it.  For planning a server's
+ * arena or a caller's memory.  Errors: the argument checks of
+ * odc_mesh_extract; INVALID_ARG for a NULL bytes. */
+int32_t odc_plan_scratch(const odc_field* field, const odc_params* params, int64_t* bytes,
+                         int32_t* fits_fixed);
+
+/* Failure injection for tests of the error paths: after `after` more device
+ * allocations by the library (context scratch, server arenas), every further
+ * one fails as if the device were out of memory, until called again with
+ * after < 0 (no limit, the default).  The calls that needed the memory return
+ * OUT_OF_MEMORY and leave their context usable.  Process-wide. */
+int32_t odc_inject_alloc_failures(int32_t after);
+
 /* Batched meshing: n fields (each with its own params and output buffers) in
  * one launch per stage -- persistent kernels walk all jobs of the batch, so
  * many small or uneven shapes fill the GPU together.  Asynchronous; results

@@ -18,8 +18,12 @@ _CFLAGS = ["-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-
            "-Wall", "-Wextra"]
 
 
-def build(force: bool = False) -> str:
-    """Compile liboracle.so with gcc (always when force)."""
+def build(force: bool = False, out: str = _LIB, extra=()) -> str:
+    """Compile liboracle.so with gcc (always when force); `out` and `extra`
+    flags build another copy (the sanitizer test's)."""
+    if out != _LIB:
+        subprocess.check_call(["gcc", *_CFLAGS, *extra, "-o", out, _SRC, "-lm"])
+        return out
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(
             os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "odc_oracle.h"))):
         tmp = _LIB + ".tmp"
@@ -133,7 +137,9 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        _lib = C.CDLL(build())
+        # ODC_ORACLE_LIB: a differently built copy (the sanitizer test's)
+        path = os.environ.get("ODC_ORACLE_LIB") or build()
+        _lib = C.CDLL(path)
         L = _lib
         L.orc_mesh_extract.argtypes = [_P(_Field), _P(_Params), _P(_Mesh)]
         L.orc_mesh_extract.restype = C.c_int

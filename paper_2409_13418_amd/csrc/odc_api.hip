@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include <atomic>
 #include <mutex>
 
 #include "odc_context.h"
@@ -29,7 +30,28 @@ constexpr int kMaxDevices = 64;
 std::mutex g_fixed_mu;
 void* g_fixed_ptr[kMaxDevices] = {};
 
+// Failure injection for tests of the error paths (odc_inject_alloc_failures):
+// the number of device allocations still allowed, or -1 for no limit.
+std::atomic<long long> g_alloc_allowed{-1};
+
 }  // namespace
+
+hipError_t odc::device_alloc(void** p, size_t bytes) {
+  long long left = g_alloc_allowed.load();
+  while (left >= 0) {
+    if (left == 0) {
+      *p = nullptr;
+      return hipErrorOutOfMemory;
+    }
+    if (g_alloc_allowed.compare_exchange_weak(left, left - 1)) break;
+  }
+  return hipMalloc(p, bytes);
+}
+
+extern "C" int32_t odc_inject_alloc_failures(int32_t after) {
+  g_alloc_allowed.store(after < 0 ? -1 : after);
+  return ODC_OK;
+}
 
 int32_t odc::ctx_fail(odc_context* ctx, int32_t code, const char* fmt, ...) {
   if (ctx) {
@@ -73,7 +95,7 @@ static int32_t ensure(odc_context* ctx, DevBuf& b, size_t bytes) {
   b.p = nullptr;
   b.bytes = 0;
   const size_t want = bytes + bytes / 4;
-  if (hipMalloc(&b.p, want) != hipSuccess) {
+  if (device_alloc(&b.p, want) != hipSuccess) {
     (void)hipGetLastError();
     b.p = nullptr;
     return fail(ctx, ODC_ERR_OUT_OF_MEMORY, "hipMalloc of %zu bytes failed", want);
@@ -584,6 +606,9 @@ int32_t odc::enqueue_batch(odc_context* ctx, int n, const odc_field* fields,
   // the host mirrors are reused: wait for the previous batch's uploads
   if (ctx->pending) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   if ((int)ctx->slots.size() < n) ctx->slots.resize(n);
+  // the host job mirrors are rewritten from here on: a failure abandons the
+  // previous batch too (nothing of it is pending any more)
+  ctx->pending = 0;
   for (int k = 0; k < n; ++k) TRY(setup_job(ctx, k, &fields[k], &params[k], &outs[k], 0));
   TRY(run_batch(ctx, n));
   ctx->pending = n;
@@ -599,6 +624,57 @@ extern "C" int32_t odc_mesh_extract(odc_context* ctx, const odc_field* field,
   return enqueue_batch(ctx, 1, field, params, out);
 }
 
+// The job record and scratch layout of the allocation-free variant: the
+// planned crossing-edge capacity, cut to what the fixed array holds; fails
+// (OUT_OF_MEMORY) when even 4096 crossing edges do not fit.  Host only.
+static int32_t plan_fixed(odc_context* ctx, const odc_field* f, const odc_params* p,
+                          double cap_scale, Job& J, Layout& L) {
+  const int N = p->res;
+  int ce = estimate_edges(cap_scale, N);
+  job_scalars(J, f, p, ce);
+  L = job_layout(J, f, false, false);
+  if (L.total() <= kFixedScratchBytes) return ODC_OK;
+  job_scalars(J, f, p, 64);
+  const Layout L0 = job_layout(J, f, false, false);
+  job_scalars(J, f, p, 65536 + 64);
+  const Layout L1 = job_layout(J, f, false, false);
+  const double per_edge = (double)(L1.total() - L0.total()) / 65536.0;
+  const double room = (double)kFixedScratchBytes - (double)L0.total();
+  ce = room > per_edge * 4096 ? 64 + (int)(room / per_edge) - 256 : 0;
+  if (ce < 4096)
+    return fail(ctx, ODC_ERR_OUT_OF_MEMORY,
+                "res %d needs %zu bytes of scratch beyond the active sets; the fixed array "
+                "holds %zu",
+                N, L0.total(), kFixedScratchBytes);
+  job_scalars(J, f, p, ce);
+  L = job_layout(J, f, false, false);
+  while (L.total() > kFixedScratchBytes && ce > 4096) {
+    ce -= 1024;
+    job_scalars(J, f, p, ce);
+    L = job_layout(J, f, false, false);
+  }
+  if (L.total() > kFixedScratchBytes)
+    return fail(ctx, ODC_ERR_OUT_OF_MEMORY, "res %d does not fit the fixed scratch of %zu bytes",
+                N, kFixedScratchBytes);
+  return ODC_OK;
+}
+
+extern "C" int32_t odc_plan_scratch(const odc_field* f, const odc_params* p, int64_t* bytes,
+                                    int32_t* fits_fixed) {
+  if (!bytes) return ODC_ERR_INVALID_ARG;
+  odc_mesh_buffers o;
+  memset(&o, 0, sizeof(o));
+  TRY(validate_job(nullptr, f, p, &o));
+  Job J;
+  job_scalars(J, f, p, estimate_edges(1.0, p->res));
+  *bytes = (int64_t)job_layout(J, f, false, false).total();
+  if (fits_fixed) {
+    Layout L;
+    *fits_fixed = plan_fixed(nullptr, f, p, 1.0, J, L) == ODC_OK;
+  }
+  return ODC_OK;
+}
+
 // The allocation-free variant: the job's scratch is carved out of the
 // device's fixed array, no graph is captured, and an overflow is reported
 // rather than regrown.  Nothing here allocates: the job record goes through
@@ -610,39 +686,12 @@ extern "C" int32_t odc_mesh_extract_noalloc(odc_context* ctx, const odc_field* f
   TRY(validate_job(ctx, f, p, o));
   if (!ctx->fixed_scratch)
     return fail(ctx, ODC_ERR_HIP, "fixed scratch unavailable: %s", ctx->fixed_err.c_str());
+  Job& J = ctx->hjobs[0];
+  Layout L;
+  TRY(plan_fixed(ctx, f, p, ctx->cap_scale, J, L));
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   if (ctx->pending) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   ctx->pending = 0;
-  // crossing-edge capacity: the planned estimate, cut to what the array holds
-  Job& J = ctx->hjobs[0];
-  const int N = p->res;
-  int ce = estimate_edges(ctx->cap_scale, N);
-  job_scalars(J, f, p, ce);
-  Layout L = job_layout(J, f, false, false);
-  if (L.total() > kFixedScratchBytes) {
-    job_scalars(J, f, p, 64);
-    const Layout L0 = job_layout(J, f, false, false);
-    job_scalars(J, f, p, 65536 + 64);
-    const Layout L1 = job_layout(J, f, false, false);
-    const double per_edge = (double)(L1.total() - L0.total()) / 65536.0;
-    const double room = (double)kFixedScratchBytes - (double)L0.total();
-    ce = room > per_edge * 4096 ? 64 + (int)(room / per_edge) - 256 : 0;
-    if (ce < 4096)
-      return fail(ctx, ODC_ERR_OUT_OF_MEMORY,
-                  "res %d needs %zu bytes of scratch beyond the active sets; the fixed array "
-                  "holds %zu",
-                  N, L0.total(), kFixedScratchBytes);
-    job_scalars(J, f, p, ce);
-    L = job_layout(J, f, false, false);
-    while (L.total() > kFixedScratchBytes && ce > 4096) {
-      ce -= 1024;
-      job_scalars(J, f, p, ce);
-      L = job_layout(J, f, false, false);
-    }
-    if (L.total() > kFixedScratchBytes)
-      return fail(ctx, ODC_ERR_OUT_OF_MEMORY, "res %d does not fit the fixed scratch of %zu bytes",
-                  N, kFixedScratchBytes);
-  }
   char* b = (char*)ctx->fixed_scratch;
   job_bind(J, L, f, b, b + L.grid_total, b + L.grid_total + L.active_total,
            b + L.grid_total + L.active_total + L.mlpw,

@@ -77,6 +77,8 @@ struct odc_context {
 
 namespace odc {
 
+// hipMalloc unless failure injection (odc_inject_alloc_failures) refuses it.
+hipError_t device_alloc(void** p, size_t bytes);
 // Sets ctx->err (when ctx is not NULL) and returns code.
 int32_t ctx_fail(odc_context* ctx, int32_t code, const char* fmt, ...);
 // Argument checks of one job.

@@ -3,10 +3,11 @@
 //
 // Requests are queued by odc_server_submit.  A scheduler thread owns a few
 // lanes, each an extraction context with its own stream.  Whenever a lane is
-// idle it takes jobs from the head of the queue, in arrival order, as long as
-// their device scratch fits in what is free of one arena of hbm_budget_bytes
+// idle it takes queued jobs (in the configured order) as long as their
+// device scratch fits in what is free of one arena of hbm_budget_bytes
 // (admission by footprint) and the batch stays within its size limits, and
-// launches them as one job-major batch.  Jobs that arrive while other
+// launches them as one job-major batch; the launch itself runs outside the
+// server lock.  Jobs that arrive while other
 // batches run are admitted as soon as a lane and arena memory free up, so
 // their work overlaps on the device.  Every job's bit sets and active sets
 // live in its arena block for the job's lifetime; only the 64-byte counts
@@ -216,17 +217,17 @@ static double job_cost(const odc_field& f, const odc_params& p) {
   return f.kind == ODC_FIELD_MLP ? 100.0 * queries : queries;
 }
 
-// Admits queued jobs into an idle lane (lock held): in arrival order
-// (FIFO), or cheapest first with aged jobs ahead of all (SHORTEST, BANDED;
-// BANDED also leaves out jobs estimated at more than `band` times the
-// batch's first job).  Returns true when a batch was launched.
-static bool admit(odc_server* s, Lane& L) {
+// Picks queued jobs for an idle lane and reserves their arena blocks (lock
+// held): in arrival order (FIFO), or cheapest first with aged jobs ahead of
+// all (SHORTEST, BANDED; BANDED also leaves out jobs estimated at more than
+// `band` times the batch's first job).  The picked jobs leave the queue.
+static std::vector<Request*> pick(odc_server* s) {
   std::vector<Request*> batch;
   int64_t corners = 0;
   std::vector<size_t> order(s->queue.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  const double now = ms_since(s->t0);
   if (s->conf.policy != ODC_SERVE_FIFO) {
-    const double now = ms_since(s->t0);
     auto aged = [&](const Request* r) { return now - r->res.submit_ms > s->conf.age_ms; };
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
       const Request* ra = s->queue[a];
@@ -244,7 +245,7 @@ static bool admit(odc_server* s, Lane& L) {
     const int64_t n1 = r->params.res + 1;
     const int64_t c = n1 * n1 * n1;
     const bool fifo = s->conf.policy == ODC_SERVE_FIFO;
-    const bool must = fifo || ms_since(s->t0) - r->res.submit_ms > s->conf.age_ms;
+    const bool must = fifo || now - r->res.submit_ms > s->conf.age_ms;
     if (!batch.empty() && corners + c > s->conf.max_batch_corners) {
       if (must) break;
       continue;
@@ -260,17 +261,28 @@ static bool admit(odc_server* s, Lane& L) {
     batch.push_back(r);
     taken.push_back(i);
   }
-  if (batch.empty()) return false;
   std::sort(taken.begin(), taken.end());
   for (auto it = taken.rbegin(); it != taken.rend(); ++it) s->queue.erase(s->queue.begin() + *it);
-  const int n = (int)batch.size();
+  for (Request* r : batch) {
+    r->res.admit_ms = now;
+    ++r->res.attempts;
+  }
+  return batch;
+}
+
+// Sets up and launches the lane's picked batch (odc_mesh_extract_batch
+// semantics) without the server lock: host job records, uploads and kernel
+// launches touch only the lane's own context and the jobs' arena blocks,
+// which no other thread uses while the batch is in flight, so submit, poll
+// and wait are never held up by them.
+static int32_t launch_lane(odc_server* s, Lane& L, std::string* why) {
+  const int n = (int)L.batch.size();
   if ((int)L.ctx->slots.size() < n) L.ctx->slots.resize(n);
   std::vector<odc_field> f(n);
   std::vector<odc_params> p(n);
   std::vector<odc_mesh_buffers> o(n);
-  const double now = ms_since(s->t0);
   for (int k = 0; k < n; ++k) {
-    Request* r = batch[k];
+    const Request* r = L.batch[k];
     Slot& S = L.ctx->slots[k];
     S.ext = (char*)s->arena_base + r->off;
     S.ext_bytes = r->bytes;
@@ -279,25 +291,18 @@ static bool admit(odc_server* s, Lane& L) {
     f[k] = r->field;
     p[k] = r->params;
     o[k] = r->out;
-    r->res.admit_ms = now;
-    ++r->res.attempts;
   }
-  L.batch = batch;
   int32_t rc = enqueue_batch(L.ctx, n, f.data(), p.data(), o.data());
-  hipError_t he = hipSuccess;
-  if (rc == ODC_OK) he = hipEventRecord(L.done, L.ctx->stream);
-  if (rc != ODC_OK || he != hipSuccess) {
-    s->err = rc != ODC_OK ? L.ctx->err : std::string(hipGetErrorString(he));
-    for (Request* r : batch) {
-      s->arena.release(r->off, r->bytes);
-      finish_request(s, r, rc != ODC_OK ? rc : ODC_ERR_HIP);
-    }
-    L.batch.clear();
-    s->cv_done.notify_all();
-    return false;
+  if (rc != ODC_OK) {
+    *why = L.ctx->err;
+    return rc;
   }
-  ++s->batches;
-  return true;
+  const hipError_t he = hipEventRecord(L.done, L.ctx->stream);
+  if (he != hipSuccess) {
+    *why = hipGetErrorString(he);
+    return ODC_ERR_HIP;
+  }
+  return ODC_OK;
 }
 
 static void scheduler(odc_server* s) {
@@ -317,10 +322,24 @@ static void scheduler(odc_server* s) {
     }
     for (Lane& L : s->lanes) {
       if (!L.batch.empty() || s->queue.empty()) continue;
-      if (admit(s, L)) {
-        busy = true;
-        progressed = true;
+      L.batch = pick(s);
+      if (L.batch.empty()) continue;
+      std::string why;
+      lk.unlock();
+      const int32_t rc = launch_lane(s, L, &why);
+      lk.lock();
+      if (rc != ODC_OK) {
+        s->err = why;
+        for (Request* r : L.batch) {
+          s->arena.release(r->off, r->bytes);
+          finish_request(s, r, rc);
+        }
+        L.batch.clear();
+        s->cv_done.notify_all();
+        continue;
       }
+      ++s->batches;
+      busy = progressed = true;
     }
     if (progressed) continue;
     if (busy)
@@ -383,7 +402,7 @@ extern "C" int32_t odc_server_create(odc_context* ctx, const odc_server_config* 
   s->t0 = Clock::now();
   int32_t rc = ODC_OK;
   if (hipSetDevice(s->device) != hipSuccess ||
-      hipMalloc(&s->arena_base, (size_t)c.hbm_budget_bytes) != hipSuccess) {
+      device_alloc(&s->arena_base, (size_t)c.hbm_budget_bytes) != hipSuccess) {
     (void)hipGetLastError();
     s->arena_base = nullptr;
     rc = ctx_fail(ctx, ODC_ERR_OUT_OF_MEMORY, "arena of %lld bytes could not be allocated",

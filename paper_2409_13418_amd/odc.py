@@ -100,7 +100,8 @@ EXPORTS = ("odc_status_string", "odc_last_error", "odc_context_create", "odc_con
            "odc_server_last_error", "odc_server_footprint", "odc_server_submit",
            "odc_server_poll", "odc_server_wait", "odc_server_get_stats",
            "odc_server_reset_stats", "odc_count_self_intersections",
-           "odc_get_job_intermediate", "odc_context_set_trace", "odc_mesh_extract_noalloc")
+           "odc_get_job_intermediate", "odc_context_set_trace", "odc_mesh_extract_noalloc",
+           "odc_plan_scratch", "odc_inject_alloc_failures")
 STAGES = ("labels", "classify", "compact", "bisect", "search2d", "cell_count", "cell_qef", "emit")
 
 _lib = None
@@ -143,6 +144,11 @@ def load(path: str = LIB_PATH):
     L.odc_mesh_extract_noalloc.argtypes = [C.c_void_p, C.POINTER(Field), C.POINTER(Params),
                                            C.POINTER(MeshBuffers)]
     L.odc_mesh_extract_noalloc.restype = C.c_int32
+    L.odc_plan_scratch.argtypes = [C.POINTER(Field), C.POINTER(Params), C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_int32)]
+    L.odc_plan_scratch.restype = C.c_int32
+    L.odc_inject_alloc_failures.argtypes = [C.c_int32]
+    L.odc_inject_alloc_failures.restype = C.c_int32
     L.odc_context_set_timing.argtypes = [C.c_void_p, C.c_int32]
     L.odc_context_set_timing.restype = C.c_int32
     L.odc_get_stage_times.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_int32,

@@ -132,6 +132,24 @@ def interior_edge_count(edge_ids, N):
     return int(interior.sum())
 
 
+def batch_results(ctx, outs, grids, trace=True):
+    """Per-job results of the last batch on ctx (outputs of extract_batch with
+    want_local, plus every intermediate of each job), shaped as gpu_run's."""
+    rs = []
+    names = INTERMEDIATE_NAMES + (("edge_trace", "pair_trace") if trace else ())
+    for k, g in enumerate(grids):
+        o = outs[k]
+        r = {n: v for n, v in o.items() if not hasattr(v, "cpu")}
+        for n in ("vertices", "triangles", "vertices_local", "vertex_ref"):
+            r[n] = o[n].cpu().numpy()
+        for n in names:
+            r[n] = ctx.intermediate(n, job=k)
+        nc = (g.res + 1) ** 3
+        r["corner_label"] = np.unpackbits(r["labels"].view(np.uint8), bitorder="little")[:nc]
+        rs.append(r)
+    return rs
+
+
 def trace_of(O, r, staged=False, labels_given=False):
     """The GPU run's recorded decisions (and, staged, its 1D and 2D points)
     as an oracle replay trace."""

@@ -92,3 +92,31 @@ def test_stage_timing(env):
     st = ctx.stage_times()
     ctx.set_timing(False)
     assert set(st) == set(odc.STAGES) and all(v >= 0 for v in st.values())
+
+
+def test_allocation_failure_is_reported(env):
+    """Device allocations refused by the library's failure injection: the
+    extraction (first or second scratch buffer) and a server arena report
+    OUT_OF_MEMORY with a message, and the context works again afterwards."""
+    odc, _ = env
+    L = odc.load()
+    f, g = I.csg_random_field(2), I.unit_grid(32, 15)
+    ctx = odc.Context(0)  # fresh: no job scratch allocated yet
+    df = odc.DeviceField(f)
+    p = odc.default_params(g)
+    try:
+        for allowed in (0, 1):
+            L.odc_inject_alloc_failures(allowed)
+            with pytest.raises(odc.OdcError) as e:
+                ctx.extract(df, p)
+            assert e.value.status == odc.ERR_OUT_OF_MEMORY, allowed
+            assert "failed" in str(e.value) or "refused" in str(e.value)
+        L.odc_inject_alloc_failures(0)
+        with pytest.raises(odc.OdcError) as e:
+            odc.Server(ctx, 1 << 26)
+        assert e.value.status == odc.ERR_OUT_OF_MEMORY
+    finally:
+        L.odc_inject_alloc_failures(-1)
+    r = ctx.extract(df, p)
+    assert r["n_triangles"] > 0
+    ctx.close()

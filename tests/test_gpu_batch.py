@@ -1,11 +1,16 @@
 """Batched meshing: one launch per stage over many jobs, graph replay, and
 the scratch-overflow rerun.  Each job's mesh must be bit-identical to the mesh
-of the same field extracted alone."""
+of the same field extracted alone, and every job of a batch is checked
+against the oracle replaying that job's decision traces: CSG jobs and small
+MLP jobs element by element over the whole grid, large MLP jobs on seeded
+samples (the binary64 network is too slow for every search of a 256^3 grid)."""
 import numpy as np
 import pytest
 
 import odc_inputs as I
 import meshcheck as M
+from gpu_common import (MLP_TIE, batch_results, check_replayed, check_sampled_replayed,
+                        interior_edge_count, trace_of)
 
 pytestmark = pytest.mark.gpu
 
@@ -52,6 +57,66 @@ def test_batch_equals_alone(odc):
                 out[k]["n_guard_corners"]) == nc, k
         assert np.array_equal(out[k]["vertices"].cpu().numpy(), v), k
         assert np.array_equal(out[k]["triangles"].cpu().numpy(), t), k
+    ctx.close()
+
+
+def _check_job_against_oracle(O, f, g, r, label, sample_rng=None):
+    if sample_rng is None:
+        tr = trace_of(O, r)
+        m = O.Oracle(f, g, mlp_tie_eps=MLP_TIE, trace=tr).mesh()
+        dv = check_replayed(r, m, tr, g.res, label)
+        return f"{label}: whole grid, {tr.adopted} near-ties followed, max vertex error {dv:.1e}"
+    adopted = check_sampled_replayed(r, g, O, f, sample_rng, 600, 40, 20, 15, label)
+    ok, why = M.is_closed_oriented_manifold(r["triangles"], r["n_vertices"])
+    assert ok, (label, why)
+    assert r["n_vertices"] == int(np.sum(r["cell_nf"] & 15)) + r["n_case3"], label
+    assert len(r["triangles"]) == 2 * interior_edge_count(r["edge_ids"], g.res) + 2 * r["n_case3"]
+    return f"{label}: samples, {adopted} near-ties followed"
+
+
+def test_batch_jobs_against_oracle(odc, oracle_mod):
+    """Every job of a mixed batch (CSG, MLP fp32 and bf16-guarded, the sphere)
+    against the oracle, whole grids."""
+    jobs = _jobs()
+    ctx = odc.Context(0)
+    ctx.set_trace(True)
+    dfs = [odc.DeviceField(f) for f, _, _ in jobs]
+    ps = [odc.default_params(g, prec) for _, g, prec in jobs]
+    out = ctx.extract_batch(dfs, ps, want_local=True)
+    rs = batch_results(ctx, out, [g for _, g, _ in jobs])
+    for k, ((f, g, prec), r) in enumerate(zip(jobs, rs)):
+        print(_check_job_against_oracle(oracle_mod, f, g, r, f"job {k} {f.name} {g.res}^3"))
+    ctx.close()
+
+
+def test_batched_workload_slice_against_oracle(odc, oracle_mod):
+    """Nine shapes of the 64-shape batched workload (seeds 4000.., CSG and MLP
+    fields at 64, 96, 128, 192 and 256 cells per axis, MLP bf16-guarded) as
+    one autotuned, graph-replayed batch.  CSG jobs against the whole oracle
+    mesh; MLP jobs on seeded samples plus whole-mesh identities."""
+    cfgs = I.batch_configs(64, 4000)
+    pick = [0, 1, 2, 3, 4, 7, 10, 20, 39]
+    jobs = [cfgs[i] for i in pick]
+    assert {g.res for _, g in jobs} == {64, 96, 128, 192, 256}
+    ctx = odc.Context(0)
+    ctx.set_trace(True)
+    dfs = [odc.DeviceField(f) for f, _ in jobs]
+    ps = [odc.default_params(g, odc.PREC_BF16_GUARDED if f.kind == odc.FIELD_MLP else
+                             odc.PREC_FP32) for f, g in jobs]
+    big = max((k for k in range(len(jobs)) if jobs[k][0].kind == odc.FIELD_MLP),
+              key=lambda k: jobs[k][1].res)
+    ctx.autotune(dfs[big], ps[big])
+    ctx.set_graph(True)
+    first = ctx.extract_batch(dfs, ps, want_local=True)       # captured
+    tris0 = [o["triangles"].cpu().numpy().copy() for o in first]
+    out = ctx.extract_batch(dfs, ps, want_local=True)         # replayed
+    rs = batch_results(ctx, out, [g for _, g in jobs])
+    rng = np.random.default_rng(40)
+    for k, ((f, g), r) in enumerate(zip(jobs, rs)):
+        assert np.array_equal(r["triangles"], tris0[k]), k
+        label = f"seed {4000 + pick[k]} {f.name} {g.res}^3"
+        print(_check_job_against_oracle(oracle_mod, f, g, r, label,
+                                        rng if f.kind == odc.FIELD_MLP else None), flush=True)
     ctx.close()
 
 

@@ -92,6 +92,36 @@ def test_mix_equals_alone(odc):
     ctx.close()
 
 
+def test_served_jobs_against_oracle(odc, oracle_mod):
+    """Every job of a served mix against the oracle.  Server lanes keep no
+    decision traces, so each served mesh must equal, bit for bit, the same
+    job meshed alone with traces on, and that mesh is checked against the
+    oracle replaying them (whole grids)."""
+    from gpu_common import MLP_TIE, check_replayed, gpu_run, trace_of
+    jobs = _jobs()
+    ctx = odc.Context(0)
+    dfs = [odc.DeviceField(f) for f, _, _ in jobs]
+    ps = [odc.default_params(g, prec) for _, g, prec in jobs]
+    outs = [odc.OutputBuffers(8 * g.res ** 2 + 4096, 16 * g.res ** 2 + 8192, want_local=True)
+            for _, g, _ in jobs]
+    srv = odc.Server(ctx, 1 << 30, lanes=2, max_batch=3)
+    tickets = [srv.submit(d, p, o) for d, p, o in zip(dfs, ps, outs)]
+    served = [srv.wait(t) for t in tickets]
+    srv.close()
+    for k, ((f, g, prec), res) in enumerate(zip(jobs, served)):
+        assert res["status"] == odc.OK, (k, res)
+        got = {n: t.cpu().numpy() for n, t in outs[k].views(res).items()}
+        r, _ = gpu_run(f, g, precision=prec, ctx=ctx)
+        for n in ("vertices", "triangles", "vertices_local", "vertex_ref"):
+            assert np.array_equal(got[n], r[n]), (k, n)
+        tr = trace_of(oracle_mod, r)
+        m = oracle_mod.Oracle(f, g, mlp_tie_eps=MLP_TIE, trace=tr).mesh()
+        dv = check_replayed(r, m, tr, g.res, f"served job {k}")
+        print(f"served job {k} ({f.name} {g.res}^3): equals the traced mesh, which is "
+              f"within {dv:.1e} cells of the oracle; {tr.adopted} near-ties followed")
+    ctx.close()
+
+
 def test_overflow_is_requeued(odc):
     """A job whose active sets outgrow their planned capacity goes back to
     the queue with the capacity it needed and completes on the next try."""
@@ -160,8 +190,14 @@ def test_shortest_first_and_aging(odc):
                         (odc.SERVE_SHORTEST, 1e-3)):
         srv = odc.Server(ctx, 1 << 31, lanes=1, max_batch=1, policy=policy, age_ms=age)
         ob = odc.OutputBuffers(1 << 20, 1 << 21)
-        tb = srv.submit(blocker[0], blocker[1], ob)
         outs = {n: odc.OutputBuffers(len(ref[n][0]) + 16, len(ref[n][1]) + 16) for n in ref}
+        tb = srv.submit(blocker[0], blocker[1], ob)
+        # the blocker holds the only lane before the two others arrive (else
+        # the scheduler may wake to all three queued and order the blocker too)
+        t0 = time.perf_counter()
+        while srv.stats()["in_flight"] == 0:
+            assert time.perf_counter() - t0 < 10.0
+            time.sleep(0.0005)
         tg = srv.submit(big[0], big[1], outs["big"])
         ts = srv.submit(small[0], small[1], outs["small"])
         rb, rg, rs = srv.wait(tb), srv.wait(tg), srv.wait(ts)
@@ -200,8 +236,14 @@ def test_banded_keeps_large_jobs_out_of_small_batches(odc):
     for policy in (odc.SERVE_SHORTEST, odc.SERVE_BANDED):
         srv = odc.Server(ctx, 1 << 31, lanes=1, max_batch=16, policy=policy, age_ms=60000.0)
         ob = odc.OutputBuffers(1 << 20, 1 << 21)
-        tb = srv.submit(blocker[0], blocker[1], ob)
         outs = {n: odc.OutputBuffers(len(ref[n][0]) + 16, len(ref[n][1]) + 16) for n in ref}
+        tb = srv.submit(blocker[0], blocker[1], ob)
+        # the blocker holds the only lane before the two others arrive (else
+        # the scheduler may wake to all three queued and order the blocker too)
+        t0 = time.perf_counter()
+        while srv.stats()["in_flight"] == 0:
+            assert time.perf_counter() - t0 < 10.0
+            time.sleep(0.0005)
         tg = srv.submit(big[0], big[1], outs["big"])
         ts = srv.submit(small[0], small[1], outs["small"])
         rb, rg, rs = srv.wait(tb), srv.wait(tg), srv.wait(ts)
