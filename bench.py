@@ -10,7 +10,9 @@ Metric: active cells meshed per second.
 Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 Besides the timed steps, the line carries (all outside the timed region):
 the dominant kernel's roofline; the plain fp32 path's throughput on the same
-grid and whether its mesh equals the guarded path's (fp32_path); the paper's
+grid and whether its mesh equals the guarded path's (fp32_path); the same
+with split-bf16 searches (x3_path: corner signs and cells equal to the
+guarded path's, vertices to binary32 rounding of the searches); the paper's
 quality measures of the mesh; a short Poisson serving trace through the
 continuous-batching server (serve: p50/p99 latency, cells/s; --serve-requests-
 default requests after --serve-warmup-default-s seconds of arrivals); the
@@ -60,6 +62,14 @@ PEAK_FP32_MFMA = 157.3e12
 PEAK_BF16_MFMA = 2.5e15
 
 
+def _prec(odc, name: str) -> int:
+    return {"bf16": odc.PREC_BF16_GUARDED, "fp32": odc.PREC_FP32,
+            "x3": odc.PREC_BF16_X3}[name]
+
+
+DTYPE = {"bf16": "bf16+fp32", "fp32": "fp32", "x3": "bf16+fp32"}
+
+
 def kernel_sources_sha256() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -70,17 +80,22 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
+PROFILE_OF = {"k_search2d_mlp": "search2d_mlp256_bf16.md",
+              "k_search2d_x3": "search2d_x3_mlp256.md"}
+
+
 def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary
+    """HBM bytes per launch of `kernel` from its committed counter summary
     (FETCH_SIZE and WRITE_SIZE runs scaled by a plain copy), or None when
-    the kernel sources changed after the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "search2d_mlp256_bf16.md")
+    there is none or the kernel sources changed after the counters were
+    taken."""
+    path = os.path.join(ROOT, "profiles", PROFILE_OF.get(kernel, "-"))
     if not os.path.exists(path):
         return None
     value, sha = None, None
     with open(path) as fh:
         for line in fh:
-            if line.startswith(f"traffic_bytes_per_launch k_{kernel}_mlp:"):
+            if line.startswith(f"traffic_bytes_per_launch {kernel}:"):
                 value = float(line.split(":")[1])
             if line.startswith("kernel_sources_sha256:"):
                 sha = line.split(":", 1)[1].strip()
@@ -167,7 +182,7 @@ def _batch_mode(args):
     from paper_2409_13418_amd import odc
 
     cfgs = I.batch_configs(64, 4000)
-    prec = odc.PREC_BF16_GUARDED if args.precision == "bf16" else odc.PREC_FP32
+    prec = _prec(odc, args.precision)
     dfs = [odc.DeviceField(f) for f, _ in cfgs]
     ps = [odc.default_params(g, prec if f.kind == odc.FIELD_MLP else odc.PREC_FP32)
           for f, g in cfgs]
@@ -204,7 +219,7 @@ def _batch_mode(args):
         "metric": "active cells meshed/sec, 64-shape batch",
         "value": cells / (ms / 1e3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "bf16+fp32" if prec == odc.PREC_BF16_GUARDED else "fp32",
+        "vs_baseline": None, "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": {"workload": "batch64", "shapes": 64, "seeds": "4000..4063",
                    "res": [g.res for _, g in cfgs], "precision_mlp": args.precision,
@@ -232,7 +247,7 @@ def serve_run(args, n_requests: int, warm_s: float) -> dict:
     rate = args.serve_rate
     n_warm = int(round(warm_s * rate))
     trace = I.serve_trace(n_warm + n_requests, rate, 5)
-    prec = odc.PREC_BF16_GUARDED if args.precision == "bf16" else odc.PREC_FP32
+    prec = _prec(odc, args.precision)
     # a pool of seeded fields per kind (the trace's field seed modulo the pool)
     pool = 16
     fields = {}
@@ -316,7 +331,7 @@ def serve_run(args, n_requests: int, warm_s: float) -> dict:
         "value": st["cells_per_s"], "unit": "cells/s", "n_gpus": 1,
         "steps": n_requests, "warmup": n_warm, "ms_per_step": None,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16+fp32" if prec == odc.PREC_BF16_GUARDED else "fp32", "data": "synthetic",
+        "dtype": DTYPE[args.precision], "data": "synthetic",
         "config": {"workload": "serve_poisson", "rate_per_s": rate, "requests": n_requests,
                    "warmup_s": warm_s, "mix": "50/50 CSG/MLP", "res_weights":
                    {"64": 0.4, "128": 0.3, "256": 0.2, "512": 0.1}, "lanes": args.serve_lanes,
@@ -351,7 +366,7 @@ def _ablation_mode(args):
     sdf = args.ablation_field == "sdf"
     field = I.sdf_mlp_field(3) if sdf else I.mlp_field(3)
     mdc = 7 | (I.ABL_SDF_INPUT if sdf else 0)
-    prec = odc.PREC_BF16_GUARDED if args.precision == "bf16" else odc.PREC_FP32
+    prec = _prec(odc, args.precision)
     ctx = odc.Context(0)
     df = odc.DeviceField(field)
     rows = []
@@ -389,7 +404,7 @@ def _ablation_mode(args):
     print(json.dumps({
         "metric": f"Table 3 ablation rows on the {args.res}^3 MLP "
                   f"{'signed-distance' if sdf else 'occupancy'} field", "n_gpus": 1,
-        "dtype": "bf16+fp32" if prec == odc.PREC_BF16_GUARDED else "fp32", "data": "synthetic",
+        "dtype": DTYPE[args.precision], "data": "synthetic",
         "steps": args.steps,
         "config": {"workload": f"{'sdf' if sdf else 'mlp'}{args.res}_ablation", "res": args.res,
                    "samples": args.ablation_samples,
@@ -414,6 +429,78 @@ def _copy_mode(args):
                       "GB_per_s": 2 * n / dt / 1e9}), flush=True)
 
 
+COUNT_KEYS = ("n_active_cells", "n_active_edges", "n_pairs", "n_vertices", "n_triangles",
+              "n_queries", "n_search2d_queries", "n_search2d_needed", "n_guard_corners",
+              "n_fp64_cells")
+
+
+def _timed(ctx, df, params, steps: int, warmup: int):
+    """warmup untimed extractions, then `steps` timed ones (stage events on);
+    returns ms per step, the per-step wall times, mean stage ms, counts."""
+    import torch
+    from paper_2409_13418_amd import odc
+    for _ in range(warmup):
+        ctx.extract(df, params)
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    step_ms = []
+    stages = {k: 0.0 for k in odc.STAGES}
+    counts = None
+    t_start = time.perf_counter()
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        ctx.extract_async(df, params, cap_hint=(ctx.cap_v, ctx.cap_t))
+        counts = ctx.sync()
+        step_ms.append((time.perf_counter() - t0) * 1e3)
+        for k, v in ctx.stage_times().items():
+            stages[k] += v
+    torch.cuda.synchronize()
+    total_s = time.perf_counter() - t_start
+    ctx.set_timing(False)
+    return total_s * 1e3 / steps, step_ms, {k: v / steps for k, v in stages.items()}, counts
+
+
+def _roofline(odc, field, grid, counts, stages, prec):
+    """The dominant stage's kernel against its matrix-core peak, and every
+    query stage: algorithmic FLOP = queries the method needs x the network's
+    FLOP per query (corners: all of them, plus the fp32 re-evaluation of the
+    guard band; 1D: k per crossing edge; 2D: the per-pair count with early
+    exits).  bf16-guarded and fp32 searches run on the fp32 matrix peak;
+    split-bf16 searches on the bf16 peak, executing six bf16 products per
+    binary32-accurate one (reported as the executed fraction)."""
+    per_query = MLP_FLOP_PER_QUERY(field)
+    nc = (grid.res + 1) ** 3
+    x3 = prec == odc.PREC_BF16_X3
+    search_peak = PEAK_BF16_MFMA if x3 else PEAK_FP32_MFMA
+    corner_peak = PEAK_FP32_MFMA if prec == odc.PREC_FP32 else PEAK_BF16_MFMA
+    flop = {"labels": nc * per_query,
+            "bisect": counts["n_active_edges"] * grid.iters_1d * per_query,
+            "search2d": counts["n_search2d_needed"] * per_query}
+    guard = counts["n_guard_corners"] * per_query
+    at_peak = {"labels": flop["labels"] / corner_peak + guard / PEAK_FP32_MFMA,
+               "bisect": flop["bisect"] / search_peak,
+               "search2d": flop["search2d"] / search_peak}
+    stages_out = {k: {"ms": stages[k], "ms_at_peak": v * 1e3, "frac": v * 1e3 / stages[k]}
+                  for k, v in at_peak.items()}
+    stages_out["extraction"] = {
+        "ms": sum(stages.values()), "ms_at_peak": sum(at_peak.values()) * 1e3,
+        "frac": sum(at_peak.values()) * 1e3 / sum(stages.values())}
+    dom = max(("bisect", "search2d", "labels"), key=lambda k: stages[k])
+    peak = corner_peak if dom == "labels" else search_peak
+    kern = {"labels": "k_labels_mlp", "bisect": "k_bisect_x3" if x3 else "k_bisect_mlp",
+            "search2d": "k_search2d_x3" if x3 else "k_search2d_mlp"}[dom]
+    achieved = flop[dom] / (stages[dom] / 1e3)
+    rl = {"bound": "mfma", "kernel": kern, "achieved": achieved / 1e12, "peak": peak / 1e12,
+          "unit": "TFLOP/s", "frac": achieved / peak,
+          "traffic": measured_traffic(kern)}
+    if x3 and dom != "labels":
+        rl["bf16_products_per_flop"] = 6
+        rl["executed_frac"] = 6 * achieved / peak
+    if dom == "search2d":
+        rl["lockstep_queries_frac"] = counts["n_search2d_queries"] / counts["n_search2d_needed"]
+    return rl, stages_out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--mode", choices=("single", "batch", "serve", "copy", "ablation"),
@@ -432,12 +519,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", choices=("bf16", "fp32"), default="bf16")
+    ap.add_argument("--precision", choices=("bf16", "fp32", "x3"), default="bf16")
     ap.add_argument("--res", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-seconds-1core", type=float, default=10.0)
     ap.add_argument("--fp32-steps", type=int, default=4,
                     help="timed steps of the plain fp32 path after the guarded path's")
+    ap.add_argument("--x3-steps", type=int, default=6,
+                    help="timed steps with split-bf16 searches after the guarded path's")
     ap.add_argument("--serve-requests-default", type=int, default=300,
                     help="requests of the Poisson trace served after the timed steps (0: none)")
     ap.add_argument("--serve-warmup-default-s", type=float, default=3.0)
@@ -461,107 +550,55 @@ def main():
 
     field = I.mlp_field(3)
     grid = I.unit_grid(args.res, 15)
-    prec = odc.PREC_BF16_GUARDED if args.precision == "bf16" else odc.PREC_FP32
+    prec = _prec(odc, args.precision)
     ctx = odc.Context(0)
     df = odc.DeviceField(field)
     params = odc.default_params(grid, prec)
-    for _ in range(args.warmup):
-        ctx.extract(df, params)
-    ctx.set_timing(True)
-    torch.cuda.synchronize()
-    step_ms = []
-    stages = {k: 0.0 for k in odc.STAGES}
-    counts = None
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        t0 = time.perf_counter()
-        ctx.extract_async(df, params, cap_hint=(ctx.cap_v, ctx.cap_t))
-        counts = ctx.sync()
-        step_ms.append((time.perf_counter() - t0) * 1e3)
-        for k, v in ctx.stage_times().items():
-            stages[k] += v
-    torch.cuda.synchronize()
-    total_s = time.perf_counter() - t_start
-    ms_per_step = total_s * 1e3 / args.steps
-    cells = counts["n_active_cells"]
-    value = cells / (ms_per_step / 1e3)
-    for k in stages:
-        stages[k] /= args.steps
-
-    # roofline of the dominant kernel: the 2D-point search (fp32 matrix cores)
-    per_query = MLP_FLOP_PER_QUERY(field)
-    dom = max(("bisect", "search2d", "labels"), key=lambda k: stages[k])
-    if dom == "search2d":
-        # the queries the kernel evaluated for real pairs (linear samples that
-        # no pair of a wavefront needed are skipped)
-        flop = counts["n_search2d_queries"] * per_query
-        peak = PEAK_FP32_MFMA
-    elif dom == "bisect":
-        flop = counts["n_active_edges"] * grid.iters_1d * per_query
-        peak = PEAK_FP32_MFMA
-    else:
-        nc = (grid.res + 1) ** 3
-        flop = nc * per_query
-        peak = PEAK_BF16_MFMA if prec == odc.PREC_BF16_GUARDED else PEAK_FP32_MFMA
-    achieved = flop / (stages[dom] / 1e3) / 1e12
-    # every matrix-core stage against its own precision's peak, and the
-    # whole extraction: the time the stages would take at peak over the
-    # measured time of all stages (the classification, scan, QEF and
-    # emission passes count as time with no matrix work)
-    nc = (grid.res + 1) ** 3
-    bf16 = prec == odc.PREC_BF16_GUARDED
-    at_peak = {
-        "labels": nc * per_query / (PEAK_BF16_MFMA if bf16 else PEAK_FP32_MFMA)
-        + counts["n_guard_corners"] * per_query / PEAK_FP32_MFMA,
-        "bisect": counts["n_active_edges"] * grid.iters_1d * per_query / PEAK_FP32_MFMA,
-        "search2d": counts["n_search2d_queries"] * per_query / PEAK_FP32_MFMA,
-    }
-    roofline_stages = {k: {"ms": stages[k], "ms_at_peak": v * 1e3, "frac": v * 1e3 / stages[k]}
-                       for k, v in at_peak.items()}
-    roofline_stages["extraction"] = {
-        "ms": sum(stages.values()), "ms_at_peak": sum(at_peak.values()) * 1e3,
-        "frac": sum(at_peak.values()) * 1e3 / sum(stages.values())}
-    roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak / 1e12,
-                "unit": "TFLOP/s", "frac": achieved * 1e12 / peak,
-                "traffic": measured_traffic(dom) if prec == odc.PREC_BF16_GUARDED else None}
+    ms_per_step, step_ms, stages, counts = _timed(ctx, df, params, args.steps, args.warmup)
+    value = counts["n_active_cells"] / (ms_per_step / 1e3)
+    roofline, roofline_stages = _roofline(odc, field, grid, counts, stages, prec)
     out = {
         "metric": "active cells meshed/sec at 256^3 MLP occupancy",
         "value": value, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16+fp32" if prec == odc.PREC_BF16_GUARDED else "fp32",
+        "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": {"workload": f"mlp{args.res}_{args.precision}", "res": args.res,
                    "field": "sigmoid(-20 sdf + 0.3 MLP): 32 spheres, 6 bands, 4x256 ReLU, seed 3",
                    "iters_1d": grid.iters_1d, "precision": args.precision},
         "p50_step_ms": float(np.percentile(step_ms, 50)),
         "p99_step_ms": float(np.percentile(step_ms, 99)),
-        "counts": {k: counts[k] for k in ("n_active_cells", "n_active_edges", "n_pairs",
-                                          "n_vertices", "n_triangles", "n_queries",
-                                          "n_search2d_queries", "n_guard_corners",
-                                          "n_fp64_cells")},
+        "counts": {k: counts[k] for k in COUNT_KEYS},
         "stages_ms": stages,
         "roofline": roofline,
         "roofline_stages": roofline_stages,
     }
-    # the plain fp32 path on the same grid (every query on fp32 matrix cores),
-    # outside the timed region above: its throughput and whether its mesh is
-    # the guarded path's
-    if prec == odc.PREC_BF16_GUARDED and args.fp32_steps > 0:
-        mesh_g = ctx.extract(df, params)["triangles"].cpu().numpy().copy()
-        params32 = odc.default_params(grid, odc.PREC_FP32)
-        ctx.extract(df, params32)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.fp32_steps):
-            ctx.extract_async(df, params32, cap_hint=(ctx.cap_v, ctx.cap_t))
-            c32 = ctx.sync()
-        torch.cuda.synchronize()
-        ms32 = (time.perf_counter() - t0) * 1e3 / args.fp32_steps
-        same = np.array_equal(ctx.extract(df, params32)["triangles"].cpu().numpy(), mesh_g)
-        out["fp32_path"] = {"value": c32["n_active_cells"] / (ms32 / 1e3), "unit": "cells/s",
-                            "ms_per_step": ms32, "steps": args.fp32_steps,
-                            "stages_ms": ctx.stage_times(), "same_mesh_as_bf16": bool(same)}
+    # the other precisions on the same grid, outside the timed region above:
+    # the plain fp32 path (every query on fp32 matrix cores; its mesh must be
+    # the guarded path's bit for bit) and split-bf16 searches (same corner
+    # signs, hence the same topology)
+    if prec == odc.PREC_BF16_GUARDED:
+        ref = ctx.extract(df, params, want_local=True)
+        ref_tris = ref["triangles"].cpu().numpy().copy()
+        ref_labels = ctx.intermediate("labels").copy()
+        ref_cells = ctx.intermediate("cell_ids").copy()
+        for name, steps in (("fp32", args.fp32_steps), ("x3", args.x3_steps)):
+            if steps <= 0:
+                continue
+            p2 = odc.default_params(grid, _prec(odc, name))
+            ms2, _, st2, c2 = _timed(ctx, df, p2, steps, 1)
+            r2 = ctx.extract(df, p2, want_local=True)
+            same_topo = bool(np.array_equal(ctx.intermediate("labels"), ref_labels) and
+                             np.array_equal(ctx.intermediate("cell_ids"), ref_cells))
+            same = bool(np.array_equal(r2["triangles"].cpu().numpy(), ref_tris))
+            rl, rs = _roofline(odc, field, grid, c2, st2, _prec(odc, name))
+            out[f"{name}_path"] = {
+                "value": c2["n_active_cells"] / (ms2 / 1e3), "unit": "cells/s",
+                "ms_per_step": ms2, "steps": steps, "stages_ms": st2,
+                "counts": {k: c2[k] for k in COUNT_KEYS},
+                "same_labels_and_cells_as_bf16": same_topo, "same_mesh_as_bf16": same,
+                "roofline": rl, "roofline_stages": rs}
     out["quality"] = mesh_quality(ctx, df, grid, params=params)
     if args.serve_requests_default > 0:
         sv = serve_run(args, args.serve_requests_default, args.serve_warmup_default_s)
@@ -570,9 +607,10 @@ def main():
                                           "p99_ms_by_res")}
         out["serve"].update({"cells_per_s": sv["value"], "config": sv["config"]})
     if not args.no_cpu_baseline:
-        precs = {"bf16": prec}
+        precs = {args.precision: prec}
         if prec == odc.PREC_BF16_GUARDED:
             precs["fp32"] = odc.PREC_FP32
+            precs["x3"] = odc.PREC_BF16_X3
         cb = cpu_baseline(field, grid, args.cpu_seconds, chamfer=(ctx, df, precs))
         cham = cb.pop("chamfer_vs_oracle", None)
         one = cpu_baseline(field, grid, args.cpu_seconds_1core, seed=1, threads=1)

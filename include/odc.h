@@ -82,8 +82,20 @@ typedef struct {
  *                 accumulation; any corner whose bf16 logit lies within
  *                 guard_logit of zero is re-evaluated by the fp32 path, and the
  *                 searches of (b) and (c), whose queries sit at the surface,
- *                 use the fp32 path directly. */
-enum { ODC_PREC_FP32 = 0, ODC_PREC_BF16_GUARDED = 1 };
+ *                 use the fp32 path directly.
+ *  BF16_X3        corner queries and their guard exactly as BF16_GUARDED,
+ *                 so every corner sign, and with them the crossing edges,
+ *                 face pairs, active cells and faces, are the FP32 path's;
+ *                 every search query of (b) and (c) at binary32 accuracy on
+ *                 the bf16 matrix cores: weights and activations each split
+ *                 exactly into three bf16 terms, the six products of terms
+ *                 i + j <= 2 accumulated in binary32 (the three left out are
+ *                 each at most about 2^-24 of the product).  Search logits
+ *                 agree with the FP32 path's to binary32 rounding, not bit
+ *                 for bit, so 1D/2D points (and vertices) may differ from
+ *                 its at decisions within that rounding of the threshold.
+ *                 The method only (ablation bits: UNSUPPORTED). */
+enum { ODC_PREC_FP32 = 0, ODC_PREC_BF16_GUARDED = 1, ODC_PREC_BF16_X3 = 2 };
 
 typedef struct {
   double lo[3];          /* domain minimum corner */
@@ -154,7 +166,15 @@ typedef struct {
   int64_t n_queries;       /* occupancy queries issued */
   int64_t n_search2d_queries; /* of which in the 2D searches: n_pairs x (1 + lin1 + bin1 +
                                  2 (lin2 + bin2)), less the linear samples past the first
-                                 label change of every pair a wavefront holds (MLP) */
+                                 label change of every pair that one evaluation step holds
+                                 (MLP: 32 pairs of a wavefront; 128 of a workgroup for
+                                 ODC_PREC_BF16_X3) */
+  int64_t n_search2d_needed;  /* MLP fields: the 2D-search queries the method itself needs,
+                                 summed over pairs (m; per ray the linear samples up to
+                                 the first label change and the halvings; no step-2 rays
+                                 when step 1 ends at m); the rest of n_search2d_queries
+                                 is lockstep work.  -1 for CSG fields and gradient
+                                 normals (not counted). */
 } odc_mesh_counts;
 
 /* Status text (static storage). */
@@ -306,7 +326,8 @@ int32_t odc_count_self_intersections(odc_context* ctx, const float* vertices, in
  * (device, n floats): for MLP fields the logit z (inside iff z > 0) computed
  * by the same matrix-core code as the meshing path in the given precision
  * (ODC_PREC_BF16_GUARDED here means the plain bf16 evaluation, without the
- * fp32 re-check); for CSG fields +1 inside, -1 outside.  Synchronous.
+ * fp32 re-check; ODC_PREC_BF16_X3 the split-bf16 evaluation of the
+ * searches); for CSG fields +1 inside, -1 outside.  Synchronous.
  * Errors: INVALID_ARG, UNSUPPORTED (as for odc_mesh_extract), HIP. */
 int32_t odc_field_eval(odc_context* ctx, const odc_field* field, int32_t precision,
                        const float* xyz, int64_t n, float* z);

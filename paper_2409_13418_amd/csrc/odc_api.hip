@@ -264,8 +264,12 @@ int32_t odc::validate_job(odc_context* ctx, const odc_field* f, const odc_params
     return fail(ctx, ODC_ERR_INVALID_ARG, "search ranges must be positive");
   if (!(p->qef_tau >= 0.0f) || !(p->qef_tau < 1.0f))
     return fail(ctx, ODC_ERR_INVALID_ARG, "qef_tau outside [0,1)");
-  if (p->precision != ODC_PREC_FP32 && p->precision != ODC_PREC_BF16_GUARDED)
+  if (p->precision != ODC_PREC_FP32 && p->precision != ODC_PREC_BF16_GUARDED &&
+      p->precision != ODC_PREC_BF16_X3)
     return fail(ctx, ODC_ERR_INVALID_ARG, "unknown precision %d", p->precision);
+  if (p->precision == ODC_PREC_BF16_X3 && p->ablation)
+    return fail(ctx, ODC_ERR_UNSUPPORTED,
+                "the ablation baselines run on the fp32 and bf16-guarded precisions");
   if (!(p->guard_logit > 0.0f) || !isfinite(p->guard_logit))
     return fail(ctx, ODC_ERR_INVALID_ARG, "guard_logit must be finite and positive");
   if (!(p->fp64_cond > 0.0) || isnan(p->fp64_cond))
@@ -389,16 +393,18 @@ Layout job_layout(const Job& J, const odc_field* f, bool guard_full, bool trace)
   L.active[17] = trace ? align_up(ne * 4) : 0;
   L.active[18] = trace ? align_up(np * 16) : 0;
   L.active_total += L.active[16] + L.active[17] + L.active[18];
-  L.status = align_up(4 * sizeof(unsigned long long));
+  L.status = align_up(5 * sizeof(unsigned long long));
   if (f->kind == ODC_FIELD_MLP) {
     const int kb1f = kb1_fp32(f->in_dim), kb1b = kb1_bf16(f->in_dim), d = f->depth;
     L.n_w1f = (size_t)kb1f * 512;
     L.n_whf = ((size_t)(d - 1) * kHiddenBlocksF32 + kPrefetchF32) * 512;  // + ring overrun
     L.n_w1b = (size_t)kb1b * 512;
     L.n_whb = ((size_t)(d - 1) * kHiddenBlocksBF16 + kPrefetchBF16) * 512;  // + ring overrun
+    // the split-bf16 precision adds the second and third bf16 weight terms
+    const size_t x3 = J.precision == ODC_PREC_BF16_X3 ? 2 * (L.n_w1b + L.n_whb) * 16 : 0;
     L.mlpw = align_up((L.n_w1f + L.n_whf) * 4 + (L.n_w1b + L.n_whb) * 16 +
-                      (size_t)(d + 1) * kWidth * 4);
-    if (J.precision == ODC_PREC_BF16_GUARDED) {
+                      (size_t)(d + 1) * kWidth * 4 + x3);
+    if (J.precision == ODC_PREC_BF16_GUARDED || J.precision == ODC_PREC_BF16_X3) {
       // corners in the guard band are ~1% of a grid; the queue holds 1/16 of
       // the corners unless an earlier run of this job overflowed it
       L.guard_cap = guard_full ? J.g.nc : (J.g.nc / 16 > 4096 ? J.g.nc / 16 : J.g.nc);
@@ -458,7 +464,13 @@ void job_bind(Job& J, const Layout& L, const odc_field* f, char* grid, char* act
     m.in_dim = f->in_dim;
     m.kb1f = kb1_fp32(f->in_dim);
     m.kb1b = kb1_bf16(f->in_dim);
-    if (J.precision == ODC_PREC_BF16_GUARDED) {
+    m.wx1 = m.wx2 = nullptr;
+    if (J.precision == ODC_PREC_BF16_X3) {
+      v8bf* x1 = (v8bf*)(bias + (size_t)(d + 1) * kWidth);
+      m.wx1 = x1;
+      m.wx2 = x1 + L.n_w1b + L.n_whb;
+    }
+    if (J.precision == ODC_PREC_BF16_GUARDED || J.precision == ODC_PREC_BF16_X3) {
       J.guard_list = (uint32_t*)guard;
       J.guard_cap = L.guard_cap;
     }
@@ -530,7 +542,8 @@ static PipelineShape shape_of(odc_context* ctx, int n) {
     if (J.kind == 1) {
       sh.any_mlp = true;
       if (J.precision == 0) sh.any_mlp_fp32 = true;
-      else sh.any_mlp_bf16 = true;
+      else if (J.precision == 1) sh.any_mlp_bf16 = true;
+      else sh.any_mlp_x3 = true;
       if (J.ablation & kAblGradNormals) sh.any_grad = true;
     }
   }
@@ -539,7 +552,8 @@ static PipelineShape shape_of(odc_context* ctx, int n) {
 
 static bool same_shape(const PipelineShape& a, const PipelineShape& b) {
   return a.any_csg == b.any_csg && a.any_mlp == b.any_mlp && a.any_mlp_fp32 == b.any_mlp_fp32 &&
-         a.any_mlp_bf16 == b.any_mlp_bf16 && a.any_grad == b.any_grad;
+         a.any_mlp_bf16 == b.any_mlp_bf16 && a.any_mlp_x3 == b.any_mlp_x3 &&
+         a.any_grad == b.any_grad;
 }
 static bool same_cfg(const LaunchCfg& a, const LaunchCfg& b) {
   return a.grid_blocks == b.grid_blocks && a.elem_blocks == b.elem_blocks &&
@@ -791,6 +805,8 @@ void odc::fill_counts(const odc_context* ctx, int k, odc_mesh_counts* c) {
   const int64_t per_pair = 1 + (J.lin1 + J.bin1) + 2 * (J.lin2 + J.bin2);
   c->n_search2d_queries =
       (J.ablation & kAblGradNormals) ? 0 : c->n_pairs * per_pair - (int64_t)o[8];
+  c->n_search2d_needed =
+      (J.kind == 1 && !(J.ablation & kAblGradNormals)) ? (int64_t)o[9] : -1;
   c->n_queries = (int64_t)J.g.nc + c->n_guard_corners +
                  c->n_active_edges * ((J.ablation & kAblLinear1D) ? 2 : J.iters_1d) +
                  c->n_search2d_queries;
@@ -935,10 +951,12 @@ extern "C" int32_t odc_field_eval(odc_context* ctx, const odc_field* f, int32_t 
   if (!ctx) return ODC_ERR_INVALID_ARG;
   if (n < 0 || n > (1LL << 30) || (n > 0 && (!xyz || !z)))
     return fail(ctx, ODC_ERR_INVALID_ARG, "bad point count or NULL buffers");
-  if (precision != ODC_PREC_FP32 && precision != ODC_PREC_BF16_GUARDED)
+  if (precision != ODC_PREC_FP32 && precision != ODC_PREC_BF16_GUARDED &&
+      precision != ODC_PREC_BF16_X3)
     return fail(ctx, ODC_ERR_INVALID_ARG, "unknown precision %d", precision);
   odc_params p;
   odc_params_default(&p, 1);
+  p.precision = precision;  // the split-bf16 evaluation needs its weight terms packed
   odc_mesh_buffers o;
   memset(&o, 0, sizeof(o));
   TRY(validate_job(ctx, f, &p, &o));

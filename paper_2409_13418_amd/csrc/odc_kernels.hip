@@ -164,10 +164,22 @@ static void scan(const Job* d, int njobs, const LaunchCfg& cfg, hipStream_t s) {
 
 // ------------------------------------------------------------ MLP weights
 // Packs the binary32 weights into the fragment orders of odc_mlp.h.
+// Term t (0, 1, 2) of the exact three-term bf16 split of a binary32 weight:
+// each term is the remainder of the previous ones rounded to bf16.
+__device__ __forceinline__ __bf16 bf16_term(float w, int t) {
+  const __bf16 w0 = (__bf16)w;
+  if (t == 0) return w0;
+  const float r = w - (float)w0;
+  const __bf16 w1 = (__bf16)r;
+  if (t == 1) return w1;
+  return (__bf16)(r - (float)w1);
+}
+
 __device__ void pack_mlp(const float* __restrict__ w, int in_dim, int depth, long long id,
                          float* __restrict__ w1f, float* __restrict__ whf,
                          v8bf* __restrict__ w1b, v8bf* __restrict__ whb,
-                         float* __restrict__ bias, float* __restrict__ wout) {
+                         float* __restrict__ bias, float* __restrict__ wout,
+                         v8bf* __restrict__ wx1, v8bf* __restrict__ wx2) {
   const int kb1f = kb1_fp32(in_dim), kb1b = kb1_bf16(in_dim);
   const size_t l1 = (size_t)kWidth * in_dim;
   const size_t hid = (size_t)kWidth * kWidth;
@@ -236,7 +248,41 @@ __device__ void pack_mlp(const float* __restrict__ w, int in_dim, int depth, lon
       return;
     }
     r -= (long long)depth * kWidth;
-    wout[r] = w[l1 + kWidth + (size_t)(depth - 1) * (hid + kWidth) + r];
+    if (r < kWidth) {
+      wout[r] = w[l1 + kWidth + (size_t)(depth - 1) * (hid + kWidth) + r];
+      return;
+    }
+    r -= kWidth;
+    // the second and third bf16 terms, in the order of the bf16 fragments
+    // (layer 1, then the hidden layers): term 1 + r / (n_w1b + n_whb)
+    const long long nb = n_w1b + n_whb;
+    if (r >= 2 * nb) return;
+    const int t = 1 + (int)(r / nb);
+    r %= nb;
+    v8bf* dst = t == 1 ? wx1 : wx2;
+    v8bf v;
+    if (r < n_w1b) {
+      const int lane = r % 64, R = (r / 64) % 8, b = (int)(r / 512);
+      const int row = 32 * R + (lane & 31), h = lane >> 5;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = feature_of_pair(8 * b + j, h);
+        v[j] = bf16_term(k >= 0 && k < in_dim ? w[(size_t)row * in_dim + k] : 0.0f, t);
+      }
+    } else {
+      const long long q = r - n_w1b;
+      const int lane = q % 64, R = (q / 64) % 8, b = (int)((q / 512) % kHiddenBlocksBF16);
+      const int l = (int)(q / (512LL * kHiddenBlocksBF16));
+      const int row = 32 * R + (lane & 31), h = lane >> 5;
+      const int T = b >> 1, beta = b & 1;
+      const float* W = w + l1 + kWidth + (size_t)l * (hid + kWidth);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int n = 32 * T + 16 * beta + 8 * (j >> 2) + 4 * h + (j & 3);
+        v[j] = bf16_term(W[(size_t)row * kWidth + n], t);
+      }
+    }
+    dst[r] = v;
   }
 }
 
@@ -244,8 +290,9 @@ __device__ void pack_mlp(const float* __restrict__ w, int in_dim, int depth, lon
 __device__ __forceinline__ long long pack_units(const Job& J) {
   if (J.kind != 1) return 0;
   const int d = J.mlp.depth;
-  return (long long)(J.mlp.kb1f + (d - 1) * kHiddenBlocksF32 + J.mlp.kb1b +
-                     (d - 1) * kHiddenBlocksBF16) * 512 + (long long)(d + 1) * kWidth;
+  const long long nb = (long long)(J.mlp.kb1b + (d - 1) * kHiddenBlocksBF16) * 512;
+  return (long long)(J.mlp.kb1f + (d - 1) * kHiddenBlocksF32) * 512 + nb +
+         (long long)(d + 1) * kWidth + (J.mlp.wx1 ? 2 * nb : 0);
 }
 
 __global__ __launch_bounds__(256) void k_pack(const Job* __restrict__ jobs, int njobs,
@@ -257,7 +304,8 @@ __global__ __launch_bounds__(256) void k_pack(const Job* __restrict__ jobs, int 
       pack_mlp(weights[k], J.mlp.in_dim, J.mlp.depth, id, const_cast<float*>(J.mlp.w1f),
                const_cast<float*>(J.mlp.whf), const_cast<v8bf*>(J.mlp.w1b),
                const_cast<v8bf*>(J.mlp.whb), const_cast<float*>(J.mlp.bias),
-               const_cast<float*>(J.mlp.wout));
+               const_cast<float*>(J.mlp.wout), const_cast<v8bf*>(J.mlp.wx1),
+               const_cast<v8bf*>(J.mlp.wx2));
   }
 }
 
@@ -268,6 +316,7 @@ __global__ void k_clear_status(const Job* __restrict__ jobs, int njobs) {
     jobs[k].status[1] = 0;
     jobs[k].status[2] = 0;
     jobs[k].status[3] = 0;
+    jobs[k].status[4] = 0;
   }
 }
 
@@ -287,6 +336,7 @@ __global__ void k_gather(const Job* __restrict__ jobs, int njobs,
     o[6] = J.status[0];
     o[7] = J.status[1] | (J.status[2] << 32);
     o[8] = J.status[3];
+    o[9] = J.status[4];
   }
 }
 
@@ -354,7 +404,12 @@ __global__ __launch_bounds__(256) void k_labels_mlp(const Job* __restrict__ jobs
       }
     }
   };
-  const auto mine = [](const Job& J) { return J.kind == 1 && J.precision == BF16; };
+  // bf16 corners also for the split-bf16 precision (2); both re-evaluate
+  // their guard band in fp32 (k_relabel_fp32), so their corner signs are
+  // the fp32 path's
+  const auto mine = [](const Job& J) {
+    return J.kind == 1 && (BF16 ? J.precision >= 1 : J.precision == 0);
+  };
   if constexpr (BF16) {
     for_units(jobs, njobs, (int)blockIdx.x, (int)gridDim.x,
               [&](const Job& J) { return mine(J) ? (J.nw_c + 3) >> 2 : 0; },
@@ -371,7 +426,7 @@ __global__ __launch_bounds__(256) void k_relabel_fp32(const Job* __restrict__ jo
   float* act = act_lds[threadIdx.x >> 6];
   for_units(jobs, njobs, gwave(), nwaves(),
             [](const Job& J) {
-              if (J.kind != 1 || J.precision != 1) return 0;
+              if (J.kind != 1 || J.precision == 0) return 0;
               const unsigned long long n = J.status[0];
               const int m = (int)(n < (unsigned long long)J.guard_cap ? n : J.guard_cap);
               return (m + 31) >> 5;
@@ -599,6 +654,26 @@ struct MlpLabel {
   __device__ __forceinline__ bool skippable(int unneeded) const { return __all(unneeded); }
 };
 
+// workgroup-cooperative (split-bf16 evaluation): the four wavefronts of the
+// workgroup call it together, each for its 32 elements
+struct X3Label {
+  const Grid* g;
+  const Mlp* m;
+  char* lds;
+  int wave;
+  mutable int parity;
+  __device__ __forceinline__ int operator()(const float gp[3]) const {
+    float x[3];
+    grid_world(*g, gp, x);
+    return mlp_logit_x3(*m, x, lds, wave) > 0.0f;
+  }
+  // skip only when no lane of the workgroup needs the answer
+  __device__ __forceinline__ bool skippable(int unneeded) const {
+    parity ^= 1;
+    return x3_vote_all(lds, wave, parity, unneeded);
+  }
+};
+
 // ------------------------------------------------------------ (b) 1D points
 // Bisection (Sec. 5.1): k halvings of [0,1] keeping distinct end labels; the
 // point is the middle of the final bracket.
@@ -663,7 +738,9 @@ __global__ __launch_bounds__(256) void k_bisect_mlp(const Job* __restrict__ jobs
   __shared__ __align__(16) float act_lds[kBlock / 64][kActWords];
   float* act = act_lds[threadIdx.x >> 6];
   for_units(jobs, njobs, gwave(), nwaves(),
-            [](const Job& J) { return J.kind == 1 ? (n_edges_of(J) + 31) >> 5 : 0; },
+            [](const Job& J) {
+              return J.kind == 1 && J.precision != 2 ? (n_edges_of(J) + 31) >> 5 : 0;
+            },
             [&](const Job& J, int t) {
               const int ne = n_edges_of(J);
               const int lane = lane_id();
@@ -678,6 +755,32 @@ __global__ __launch_bounds__(256) void k_bisect_mlp(const Job* __restrict__ jobs
                 MlpLabel lab{&J.g, &J.mlp, act};
                 tt = bisect_edge(J, lab, e, bits);
               }
+              if (valid && lane < 32) {
+                J.et[x] = tt;
+                if (J.etrace) J.etrace[x] = bits;
+              }
+            });
+}
+
+// Split-bf16 evaluation (precision 2): a workgroup takes 128 crossing edges,
+// 32 per wavefront, and the four evaluate each bisection query together.
+__global__ __launch_bounds__(256) void k_bisect_x3(const Job* __restrict__ jobs, int njobs) {
+  __shared__ __align__(16) char lds[kX3LdsBytes];
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  for_units(jobs, njobs, (int)blockIdx.x, (int)gridDim.x,
+            [](const Job& J) { return J.kind == 1 && J.precision == 2 ? (n_edges_of(J) + 127) >> 7 : 0; },
+            [&](const Job& J, int t) {
+              lds_block_sync();  // the previous unit's reads of the staged field are done
+              x3_stage(J.mlp, lds);
+              lds_block_sync();
+              const int ne = n_edges_of(J);
+              const int lane = lane_id();
+              const int x = t * 128 + wave * 32 + (lane & 31);
+              const bool valid = x < ne;
+              const int e = J.elist[valid ? x : ne - 1];
+              X3Label lab{&J.g, &J.mlp, lds, wave, 0};
+              uint32_t bits;
+              const float tt = bisect_edge(J, lab, e, bits);
               if (valid && lane < 32) {
                 J.et[x] = tt;
                 if (J.etrace) J.etrace[x] = bits;
@@ -791,10 +894,13 @@ struct LineBinary {
 //
 // Query q of the sequence (0 = m, then step 1's ray, then step 2's two rays)
 // sets bit q of `evald` when it is evaluated and bit q of `bits` to its
-// label: the decision trace that a checker can replay.
+// label: the decision trace that a checker can replay.  `need` counts the
+// queries the method itself needs for this pair: m, each ray's linear
+// samples up to its first label change and its halvings, and no step-2 ray
+// when step 1 ends at m.
 template <class Lab>
 __device__ double2 search_pair(const Job& j, const Lab& lab, int face, int slot, int& skipped,
-                               uint64_t& bits, uint64_t& evald) {
+                               uint64_t& bits, uint64_t& evald, int& need) {
   const Grid& g = j.g;
   FaceFrame fr;
   face_pos(g, face, fr.a, fr.p);
@@ -815,6 +921,7 @@ __device__ double2 search_pair(const Job& j, const Lab& lab, int face, int slot,
   LineBinary lb;
   int sm = 0;
   skipped = 0;
+  need = 0;
   bits = 0ull;
   evald = 0ull;
   float q[2] = {m[0], m[1]}, q1[2] = {0, 0}, s1 = 0.0f;
@@ -834,6 +941,7 @@ __device__ double2 search_pair(const Job& j, const Lab& lab, int face, int slot,
     // a linear sample after the first label change cannot move the bracket
     // (the change already fixed i*), so its query is skipped where the label
     // functor allows; the bracket bookkeeping still runs (and ignores l)
+    need += step == 0 || ((step <= n1 || s1 != 0.0f) && !(k < lb.nl && lb.found));
     int l = 0;
     if (step == 0 || k >= lb.nl || !lab.skippable(lb.found)) {
       float gp[3] = {(float)fr.p[0], (float)fr.p[1], (float)fr.p[2]};
@@ -919,9 +1027,9 @@ __global__ __launch_bounds__(256) void k_search2d_csg(const Job* __restrict__ jo
             [&](const Job& J, int x) {
               CsgLabel lab{&J.g, J.prims, J.n_prims};
               const int rec = J.plist[x];
-              int skipped;
+              int skipped, need;
               uint64_t bits, evald;
-              J.pf[x] = search_pair(J, lab, rec >> 1, rec & 1, skipped, bits, evald);
+              J.pf[x] = search_pair(J, lab, rec >> 1, rec & 1, skipped, bits, evald, need);
               if (J.ptrace) {
                 J.ptrace[2 * x] = bits;
                 J.ptrace[2 * x + 1] = evald;
@@ -934,8 +1042,9 @@ __global__ __launch_bounds__(256) void k_search2d_mlp(const Job* __restrict__ jo
   float* act = act_lds[threadIdx.x >> 6];
   for_units(jobs, njobs, gwave(), nwaves(),
             [](const Job& J) {
-              return (J.kind == 1 && !(J.ablation & kAblGradNormals)) ? (n_pairs_of(J) + 31) >> 5
-                                                                       : 0;
+              return (J.kind == 1 && J.precision != 2 && !(J.ablation & kAblGradNormals))
+                         ? (n_pairs_of(J) + 31) >> 5
+                         : 0;
             },
             [&](const Job& J, int t) {
               const int np = n_pairs_of(J);
@@ -944,9 +1053,9 @@ __global__ __launch_bounds__(256) void k_search2d_mlp(const Job* __restrict__ jo
               const bool valid = x < np;
               MlpLabel lab{&J.g, &J.mlp, act};
               const int rec = J.plist[valid ? x : np - 1];
-              int skipped;  // wave-uniform
+              int skipped, need;  // skipped: wave-uniform
               uint64_t bits, evald;
-              const double2 r = search_pair(J, lab, rec >> 1, rec & 1, skipped, bits, evald);
+              const double2 r = search_pair(J, lab, rec >> 1, rec & 1, skipped, bits, evald, need);
               if (valid && lane < 32) {
                 J.pf[x] = r;
                 if (J.ptrace) {
@@ -957,6 +1066,44 @@ __global__ __launch_bounds__(256) void k_search2d_mlp(const Job* __restrict__ jo
               if (lane == 0 && skipped)
                 atomicAdd(&J.status[3],
                           (unsigned long long)skipped * (unsigned long long)min(32, np - t * 32));
+              const int nsum = wave_sum(valid && lane < 32 ? need : 0);
+              if (lane == 0) atomicAdd(&J.status[4], (unsigned long long)nsum);
+            });
+}
+
+// Split-bf16 evaluation (precision 2): a workgroup takes 128 pairs, 32 per
+// wavefront, and the four evaluate each search query together; a linear
+// sample is skipped when no pair of the workgroup needs it.
+__global__ __launch_bounds__(256) void k_search2d_x3(const Job* __restrict__ jobs, int njobs) {
+  __shared__ __align__(16) char lds[kX3LdsBytes];
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  for_units(jobs, njobs, (int)blockIdx.x, (int)gridDim.x,
+            [](const Job& J) { return J.kind == 1 && J.precision == 2 ? (n_pairs_of(J) + 127) >> 7 : 0; },
+            [&](const Job& J, int t) {
+              lds_block_sync();
+              x3_stage(J.mlp, lds);
+              lds_block_sync();
+              const int np = n_pairs_of(J);
+              const int lane = lane_id();
+              const int x = t * 128 + wave * 32 + (lane & 31);
+              const bool valid = x < np;
+              X3Label lab{&J.g, &J.mlp, lds, wave, 0};
+              const int rec = J.plist[valid ? x : np - 1];
+              int skipped, need;  // skipped: workgroup-uniform
+              uint64_t bits, evald;
+              const double2 r = search_pair(J, lab, rec >> 1, rec & 1, skipped, bits, evald, need);
+              if (valid && lane < 32) {
+                J.pf[x] = r;
+                if (J.ptrace) {
+                  J.ptrace[2 * x] = bits;
+                  J.ptrace[2 * x + 1] = evald;
+                }
+              }
+              if (wave == 0 && lane == 0 && skipped)
+                atomicAdd(&J.status[3],
+                          (unsigned long long)skipped * (unsigned long long)min(128, np - t * 128));
+              const int nsum = wave_sum(valid && lane < 32 ? need : 0);
+              if (lane == 0) atomicAdd(&J.status[4], (unsigned long long)nsum);
             });
 }
 
@@ -1426,10 +1573,9 @@ hipError_t launch_pipeline(const Job* d, int njobs, const PipelineShape& sh,
   mark(0);
   if (sh.any_csg) k_labels_csg<<<cfg.grid_blocks, kBlock, 0, s>>>(d, njobs);
   if (sh.any_mlp_fp32) k_labels_mlp<0><<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
-  if (sh.any_mlp_bf16) {
-    k_labels_mlp<1><<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
+  if (sh.any_mlp_bf16 || sh.any_mlp_x3) k_labels_mlp<1><<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
+  if (sh.any_mlp_bf16 || sh.any_mlp_x3)
     k_relabel_fp32<<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
-  }
   mark(1);
   k_classify_edges<<<cfg.grid_blocks, kBlock, 0, s>>>(d, njobs);
   k_classify_faces<<<cfg.grid_blocks, kBlock, 0, s>>>(d, njobs, table);
@@ -1441,10 +1587,13 @@ hipError_t launch_pipeline(const Job* d, int njobs, const PipelineShape& sh,
   k_compact<<<cfg.grid_blocks, kBlock, 0, s>>>(d, njobs);
   mark(3);
   if (sh.any_csg) k_bisect_csg<<<cfg.elem_blocks, kBlock, 0, s>>>(d, njobs);
-  if (sh.any_mlp) k_bisect_mlp<<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
+  if (sh.any_mlp_fp32 || sh.any_mlp_bf16) k_bisect_mlp<<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
+  if (sh.any_mlp_x3) k_bisect_x3<<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
   mark(4);
   if (sh.any_csg) k_search2d_csg<<<cfg.elem_blocks, kBlock, 0, s>>>(d, njobs);
-  if (sh.any_mlp) k_search2d_mlp<<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
+  if (sh.any_mlp_fp32 || sh.any_mlp_bf16)
+    k_search2d_mlp<<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
+  if (sh.any_mlp_x3) k_search2d_x3<<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
   if (sh.any_grad) k_grad_mlp<<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
   mark(5);
   k_cell_count<<<cfg.elem_blocks, kBlock, 0, s>>>(d, njobs, table);
@@ -1493,6 +1642,24 @@ __global__ __launch_bounds__(256) void k_eval_mlp(const Job* __restrict__ job,
   }
 }
 
+__global__ __launch_bounds__(256) void k_eval_x3(const Job* __restrict__ job,
+                                                 const float* __restrict__ xyz, int n,
+                                                 float* __restrict__ z) {
+  __shared__ __align__(16) char lds[kX3LdsBytes];
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const Mlp& m = job->mlp;
+  const int lane = lane_id();
+  x3_stage(m, lds);
+  lds_block_sync();
+  for (int t = blockIdx.x; t * 128 < n; t += gridDim.x) {
+    const int i = t * 128 + wave * 32 + (lane & 31);
+    const int k = i < n ? i : n - 1;
+    const float x[3] = {xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2]};
+    const float v = mlp_logit_x3(m, x, lds, wave);
+    if (i < n && lane < 32) z[i] = v;
+  }
+}
+
 hipError_t launch_eval(const Job* d_job, const Job& h_job, const float* const* d_weights,
                        int precision, const float* xyz, int n, float* z, const LaunchCfg& cfg,
                        hipStream_t s) {
@@ -1501,7 +1668,8 @@ hipError_t launch_eval(const Job* d_job, const Job& h_job, const float* const* d
   } else {
     k_pack<<<cfg.pack_blocks, kBlock, 0, s>>>(d_job, 1, d_weights);
     if (precision == 0) k_eval_mlp<0><<<cfg.mlp_blocks, kBlock, 0, s>>>(d_job, xyz, n, z);
-    else k_eval_mlp<1><<<cfg.mlp_blocks, kBlock, 0, s>>>(d_job, xyz, n, z);
+    else if (precision == 1) k_eval_mlp<1><<<cfg.mlp_blocks, kBlock, 0, s>>>(d_job, xyz, n, z);
+    else k_eval_x3<<<cfg.mlp_blocks, kBlock, 0, s>>>(d_job, xyz, n, z);
   }
   return hipGetLastError();
 }

@@ -105,6 +105,11 @@ struct Mlp {
   const float* whf;  // [depth-1][128][8][64]    hidden layers, fp32 fragments
   const v8bf* w1b;   // [kb1b][8][64]            layer 1, bf16 fragments
   const v8bf* whb;   // [depth-1][16][8][64]     hidden layers, bf16 fragments
+  // the second and third bf16 terms of every weight (w = w0 + w1 + w2
+  // exactly, w0 = the fragments above), laid out as w1b then whb: the
+  // split-bf16 evaluation only (else NULL)
+  const v8bf* wx1;
+  const v8bf* wx2;
   const float* bias; // [depth][256]
   const float* wout; // [256]
   const float* spheres;
@@ -114,6 +119,13 @@ struct Mlp {
 };
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Sum of an int over the 64 lanes of the wavefront (every lane gets it).
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
 
 // Entry of a per-neuron vector (bias, output weights) for accumulator
 // register i of tile T in lane half h: neuron 32 T + 8 (i/4) + 4 h + i%4.
@@ -716,6 +728,221 @@ __device__ __forceinline__ float mlp_logit_bf16_split(const Mlp& M, const float 
       for (int e = 0; e < 4; ++e) mine[T][4 * g + e] = v[e];
     }
   return mlp_output(M, mine, h, zero, x);
+}
+
+// ---------------------------------------------------------- split bf16
+// Evaluation at binary32 accuracy on the bf16 matrix cores.  Every weight is
+// split exactly into three bf16 terms, w = w0 + w1 + w2 (each the rounded
+// remainder of the previous: 8 + 8 + 8 significant bits), and so is every
+// activation, a = a0 + a1 + a2.  A layer accumulates in binary32 the six
+// products w_i a_j with i + j <= 2, smallest first.  Each product of two
+// bf16 numbers is exact in binary32, and the three terms left out are each
+// below 2^-24 |w a|: the result carries the error of binary32 arithmetic,
+// not bf16's.  Six bf16 matrix instructions cost about 0.4 of one fp32 one
+// for the same K rows.
+//
+// The four wavefronts of a 256-thread workgroup evaluate 128 queries
+// together (set s = the 32 queries of wavefront s), split by output tiles
+// as in the bf16 corner pass: wavefront w computes tiles 2w, 2w + 1 of every
+// layer for all four sets, streaming only those tiles' three weight terms.
+// Layer inputs are exchanged through LDS as binary32 activations,
+// relu(pre + bias), in the bf16 B-operand order: [set][K block][half][lane]
+// vectors of four (128 KB); each wavefront splits them into three bf16
+// operands as it reads them.  Biases and output weights are staged in LDS by the caller
+// (x3_stage) before the first call for a field.  The output layer sums, per
+// wavefront, its 64 neurons for the four sets; the four partial sums then
+// add in wavefront order, y = ((y_0 + y_1) + y_2) + y_3, followed by the
+// output bias, out_scale and the sdf term as in mlp_finish.
+constexpr int kX3OpBytes = 4 * kHiddenBlocksBF16 * 64 * 32;    // 128 KB
+constexpr int kX3PartOff = kX3OpBytes;                          // [set][wave][32] floats
+constexpr int kX3BiasOff = kX3PartOff + 4 * 4 * 32 * 4;          // (depth + 1) x 256 floats
+constexpr int kX3VoteOff = kX3BiasOff + (kMaxDepth + 1) * kWidth * 4;
+constexpr int kX3LdsBytes = kX3VoteOff + 2 * 4 * 4;              // two vote slots of 4 ints
+constexpr int kX3Ring = 2;  // weight ring depth in K blocks (each ~1500 matrix cycles)
+
+// Stages the field's biases and output weights in the workgroup's LDS; all
+// 256 threads call it, then a barrier, before x3 evaluations of the field.
+__device__ __forceinline__ void x3_stage(const Mlp& M, char* lds) {
+  v4f* dst = reinterpret_cast<v4f*>(lds + kX3BiasOff);
+  const ODC_GLOBAL v4f* Bsrc = (const ODC_GLOBAL v4f*)gmem(M.bias);
+  const ODC_GLOBAL v4f* Wsrc = (const ODC_GLOBAL v4f*)gmem(M.wout);
+  const int nb = M.depth * 64;
+  for (int i = (int)threadIdx.x; i < nb + 64; i += 256) dst[i] = i < nb ? Bsrc[i] : Wsrc[i - nb];
+}
+
+// Eight binary32 values to the three bf16 terms of each (exact split).
+__device__ __forceinline__ void split3(v4f lo, v4f hi, v8bf& a0, v8bf& a1, v8bf& a2) {
+  typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+  auto pk = [](v4f a, v4f b) -> v4u {
+    return (v4u){pack_bf16(a[0], a[1]), pack_bf16(a[2], a[3]), pack_bf16(b[0], b[1]),
+                 pack_bf16(b[2], b[3])};
+  };
+  // a packed pair back to binary32: the low half shifted up, the high half masked
+  auto un = [](v4u p, v4f& a, v4f& b) {
+    a = (v4f){__builtin_bit_cast(float, p[0] << 16), __builtin_bit_cast(float, p[0] & 0xffff0000u),
+              __builtin_bit_cast(float, p[1] << 16), __builtin_bit_cast(float, p[1] & 0xffff0000u)};
+    b = (v4f){__builtin_bit_cast(float, p[2] << 16), __builtin_bit_cast(float, p[2] & 0xffff0000u),
+              __builtin_bit_cast(float, p[3] << 16), __builtin_bit_cast(float, p[3] & 0xffff0000u)};
+  };
+  const v4u p0 = pk(lo, hi);
+  v4f f0, f1;
+  un(p0, f0, f1);
+  const v4f r0 = lo - f0, r1 = hi - f1;
+  const v4u p1 = pk(r0, r1);
+  v4f g0, g1;
+  un(p1, g0, g1);
+  const v4u p2 = pk(r0 - g0, r1 - g1);
+  a0 = __builtin_bit_cast(v8bf, p0);
+  a1 = __builtin_bit_cast(v8bf, p1);
+  a2 = __builtin_bit_cast(v8bf, p2);
+}
+
+// The logit of this lane's query (lanes l and l + 32 hold query l % 32);
+// all four wavefronts call together.  2 depth + 1 barriers.
+__device__ __forceinline__ float mlp_logit_x3(const Mlp& M, const float x[3], char* __restrict__ lds,
+                                              int wave) {
+  const int lane = lane_id();
+  const int h = lane >> 5;
+  int zero = 0;  // keeps the stream prologue here (see mlp_logit_fp32)
+  asm volatile("" : "+v"(zero));
+  v4f* const opnd = reinterpret_cast<v4f*>(lds);  // [set][block][half][lane]
+  float* const part = reinterpret_cast<float*>(lds + kX3PartOff);
+  const v4f* const bias4 = reinterpret_cast<const v4f*>(lds + kX3BiasOff);
+  // half k (rows 4k..4k+3 of the lane's eight) of set `set`, K block b
+  auto op = [&](int set, int b, int k) -> v4f* {
+    return opnd + ((set * kHiddenBlocksBF16 + b) * 2 + k) * 64 + lane;
+  };
+  const size_t stream = ((size_t)kPrefetchBF16 + (size_t)(M.depth - 1) * kHiddenBlocksBF16 +
+                         kPrefetchBF16) * 8192;
+  const __amdgpu_buffer_rsrc_t w0s = weight_stream(M.w1b, stream);
+  const __amdgpu_buffer_rsrc_t w1s = weight_stream(M.wx1, stream);
+  const __amdgpu_buffer_rsrc_t w2s = weight_stream(M.wx2, stream);
+  const int voff = (lane + zero) * 16;
+  auto S = [&](__amdgpu_buffer_rsrc_t r, int b, int j) -> v8bf {
+    return __builtin_bit_cast(
+        v8bf, __builtin_amdgcn_raw_buffer_load_b128(r, voff, (b * 8 + 2 * wave + j) * 1024, 0));
+  };
+  // ring of kX3Ring K blocks: [slot][tile j][term]
+  v8bf wr[kX3Ring][2][3];
+  auto refill = [&](int d, int b) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      wr[d][j][0] = S(w0s, b, j);
+      wr[d][j][1] = S(w1s, b, j);
+      wr[d][j][2] = S(w2s, b, j);
+    }
+  };
+#pragma unroll
+  for (int d = 0; d < kX3Ring; ++d) refill(d, d);
+  // layer-1 inputs of this wavefront's queries: K block b, lane half h, row
+  // j = member h of input pair 8b + j (binary32 features)
+#pragma unroll
+  for (int b = 0; b < kPrefetchBF16; ++b) {
+    v4f f[2];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) f[j >> 2][j & 3] = pair_feature(8 * b + j, h, x);
+    *op(wave, b, 0) = f[0];
+    *op(wave, b, 1) = f[1];
+  }
+  lds_block_sync();
+  const v16f zacc = {};
+  v16f acc[4][2];
+  // one layer: stream blocks base..base+nblk-1 (the ring continues into the
+  // next layer's first blocks; the streams carry padding after the last)
+  auto layer = [&](int base, auto nblk_c) {
+    constexpr int nblk = decltype(nblk_c)::value;
+#pragma unroll
+    for (int i = 0; i < nblk; ++i) {
+      const int d = i % kX3Ring;
+#pragma unroll
+      for (int set = 0; set < 4; ++set) {
+        v8bf a0, a1, a2;
+        split3(*op(set, i, 0), *op(set, i, 1), a0, a1, a2);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          v16f c = i == 0 ? zacc : acc[set][j];
+          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[d][j][2], a0, c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[d][j][1], a1, c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[d][j][0], a2, c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[d][j][1], a0, c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[d][j][0], a1, c, 0, 0, 0);
+          acc[set][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[d][j][0], a0, c, 0, 0, 0);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      refill(d, base + i + kX3Ring);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+  using L1 = std::integral_constant<int, kPrefetchBF16>;
+  using LH = std::integral_constant<int, kHiddenBlocksBF16>;
+  layer(0, L1{});
+  const v4f* Bg = bias4 + h;
+  for (int l = 1; l < M.depth; ++l) {
+    lds_block_sync();  // every wavefront's reads of this layer's inputs are done
+    // this wavefront's share of layer l's inputs: operand block b = 2 T + beta
+    const v4f* Bl = Bg + (size_t)(l - 1) * 64;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int beta = 0; beta < 2; ++beta) {
+        const int b = 2 * (2 * wave + j) + beta;
+        const v4f t0 = Bl[4 * b], t1 = Bl[4 * b + 2];
+#pragma unroll
+        for (int set = 0; set < 4; ++set) {
+          const v16f& a = acc[set][j];
+          const v4f a0 = {a[8 * beta], a[8 * beta + 1], a[8 * beta + 2], a[8 * beta + 3]};
+          const v4f a1 = {a[8 * beta + 4], a[8 * beta + 5], a[8 * beta + 6], a[8 * beta + 7]};
+          const v4f s0 = a0 + t0, s1 = a1 + t1;
+          *op(set, b, 0) =
+              (v4f){fmaxf(s0[0], 0.0f), fmaxf(s0[1], 0.0f), fmaxf(s0[2], 0.0f), fmaxf(s0[3], 0.0f)};
+          *op(set, b, 1) =
+              (v4f){fmaxf(s1[0], 0.0f), fmaxf(s1[1], 0.0f), fmaxf(s1[2], 0.0f), fmaxf(s1[3], 0.0f)};
+        }
+      }
+    lds_block_sync();  // layer l's inputs are complete
+    layer(kPrefetchBF16 + (l - 1) * kHiddenBlocksBF16, LH{});
+  }
+  // output sums over this wavefront's 64 neurons (tile 2 wave + j, register
+  // group G' = 4 h-interleaved neurons 32 T + 8 G' + 4 h + d), lane halves combined
+  {
+    const v4f* Bl = Bg + (size_t)(M.depth - 1) * 64;
+    const v4f* Wo = bias4 + (size_t)M.depth * 64 + h;
+    float ps[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int gq = 0; gq < 4; ++gq) {
+        const int G = 4 * (2 * wave + j) + gq;
+        const v4f bb = Bl[2 * G], wo = Wo[2 * G];
+#pragma unroll
+        for (int set = 0; set < 4; ++set)
+#pragma unroll
+          for (int d = 0; d < 4; ++d)
+            ps[set] = __builtin_fmaf(wo[d], fmaxf(acc[set][j][4 * gq + d] + bb[d], 0.0f), ps[set]);
+      }
+#pragma unroll
+    for (int set = 0; set < 4; ++set) {
+      const float t = ps[set] + __shfl_xor(ps[set], 32);
+      if (h == 0) part[(set * 4 + wave) * 32 + lane] = t;
+    }
+  }
+  lds_block_sync();
+  const float* pp = part + wave * 4 * 32 + (lane & 31);
+  const float y = ((pp[0] + pp[32]) + pp[64]) + pp[96];
+  return mlp_finish(M, h ? 0.0f : y, x);
+}
+
+// Workgroup-wide "may skip": 1 when every lane of the four wavefronts
+// passes unneeded != 0.  Alternating vote slots (`parity`, flipped by the
+// caller each vote) let a fast wavefront write the next vote while a slow
+// one still reads this one; one barrier.
+__device__ __forceinline__ int x3_vote_all(char* lds, int wave, int parity, int unneeded) {
+  int* slot = reinterpret_cast<int*>(lds + kX3VoteOff) + 4 * parity;
+  const int mine = __all(unneeded);
+  if (lane_id() == 0) slot[wave] = mine;
+  lds_block_sync();
+  return slot[0] & slot[1] & slot[2] & slot[3];
 }
 
 }  // namespace odc

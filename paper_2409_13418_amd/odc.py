@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libodc.so")
 
 OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_CAPACITY, ERR_HIP, ERR_UNSUPPORTED, ERR_BUSY = range(7)
 FIELD_CSG, FIELD_MLP = 0, 1
-PREC_FP32, PREC_BF16_GUARDED = 0, 1
+PREC_FP32, PREC_BF16_GUARDED, PREC_BF16_X3 = 0, 1, 2
 INTERMEDIATES = {"labels": (0, np.uint32), "edge_ids": (1, np.int32), "edge_t": (2, np.float32),
                  "pairs": (3, np.int32), "pair_pf": (4, np.float64), "cell_ids": (5, np.int32),
                  "cell_partmap": (6, np.uint32), "cell_nf": (7, np.uint32),
@@ -60,7 +60,7 @@ class MeshCounts(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "n_vertices", "n_triangles", "n_active_edges", "n_pairs", "n_active_cells", "n_case3",
         "n_flipped_faces", "n_fp64_cells", "n_guard_corners", "n_queries",
-        "n_search2d_queries")]
+        "n_search2d_queries", "n_search2d_needed")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}

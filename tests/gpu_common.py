@@ -160,6 +160,33 @@ def trace_of(O, r, staged=False, labels_given=False):
                    edge_grad=grad if grad is not None and len(grad) else None)
 
 
+def needed_search_queries(m, g):
+    """Sec. 5.2 / App. A.1.3 with early exits, from an oracle mesh's query
+    labels: per pair m, each ray's linear samples up to the first label that
+    differs from m's (all of them when none does) and its halvings; no
+    step-2 rays when step 1 ends at m (pair_info bit 13)."""
+    lab = m["pair_bits"][:, 0].astype(np.uint64)
+    qm = (m["pair_info"] >> 13) & 1
+    total = 0
+    for x in range(len(lab)):
+        b = int(lab[x])
+        sm = b & 1
+        n = 1
+
+        def ray(first, n_lin, n_bin):
+            for i in range(n_lin):
+                if ((b >> (first + i)) & 1) != sm:
+                    return i + 1 + n_bin
+            return n_lin + n_bin
+
+        n += ray(1, g.lin1, g.bin1)
+        if not qm[x]:
+            s2 = 1 + g.lin1 + g.bin1
+            n += ray(s2, g.lin2, g.bin2) + ray(s2 + g.lin2 + g.bin2, g.lin2, g.bin2)
+        total += n
+    return total
+
+
 def check_replayed(r, m, tr, res, label, vert_tol=VERT_TOL):
     """The bar once the oracle has followed the GPU's branches at its own
     near-ties: no other decision differs; integer structure, 1D points and 2D

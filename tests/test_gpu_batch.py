@@ -26,7 +26,7 @@ def _jobs():
     for k, res in enumerate((24, 40, 16, 20, 33, 28)):
         seed = 4000 + k
         f = I.csg_random_field(seed) if k % 2 == 0 else I.mlp_field(seed)
-        prec = 1 if k == 3 else 0
+        prec = {3: 1, 5: 2}.get(k, 0)   # MLP jobs: fp32, bf16-guarded, split-bf16
         out.append((f, I.unit_grid(res, 15), prec))
     f, g = I.sphere_case(32, 10)
     out.append((f, g, 0))
@@ -75,8 +75,8 @@ def _check_job_against_oracle(O, f, g, r, label, sample_rng=None):
 
 
 def test_batch_jobs_against_oracle(odc, oracle_mod):
-    """Every job of a mixed batch (CSG, MLP fp32 and bf16-guarded, the sphere)
-    against the oracle, whole grids."""
+    """Every job of a mixed batch (CSG, MLP fp32, bf16-guarded and split-bf16,
+    the sphere) against the oracle, whole grids."""
     jobs = _jobs()
     ctx = odc.Context(0)
     ctx.set_trace(True)

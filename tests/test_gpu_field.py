@@ -42,6 +42,28 @@ def test_mlp_fp32_logits_match_binary64(env, oracle_mod):
     assert np.median(np.abs(ref)) > 0.1
 
 
+@pytest.mark.parametrize("shape", [(3, 6, 4), (5, 0, 1), (7, 7, 8)])
+def test_mlp_x3_logits_match_binary64(env, oracle_mod, shape):
+    """The split-bf16 evaluation (three bf16 terms per weight and activation,
+    six products, binary32 accumulation) carries binary32's error: within the
+    same bound as the fp32 matrix-core path, on the benchmark's network and
+    on others (depth 1 and 8; no and 7 Fourier bands)."""
+    odc, ctx = env
+    seed, bands, depth = shape
+    f = I.mlp_field(seed, n_bands=bands, depth=depth) if shape != (3, 6, 4) else I.mlp_field(3)
+    pts = _points(oracle_mod, f, seed=seed)
+    df = odc.DeviceField(f)
+    z = ctx.field_eval(df, pts, odc.PREC_BF16_X3).astype(np.float64)
+    z32 = ctx.field_eval(df, pts, odc.PREC_FP32).astype(np.float64)
+    o = oracle_mod.Oracle(f, I.unit_grid(16))
+    ref = np.array([o.label_world(p)[2] for p in pts])
+    err, err32 = np.abs(z - ref), np.abs(z32 - ref)
+    print(f"x3 logit error {err.max():.2e} (fp32 path {err32.max():.2e}), depth {depth}, "
+          f"{bands} bands")
+    assert err.max() < FP32_LOGIT_TOL, float(err.max())
+    assert np.median(np.abs(ref)) > 0.1
+
+
 def test_mlp_bf16_error_inside_guard_band(env, oracle_mod):
     """The bf16 logit stays well inside the guard band of the fp32 one, so a
     bf16 sign outside the band equals the fp32 sign."""

@@ -9,7 +9,9 @@
   crossing edges, face pairs and active cells are recomputed one by one by
   the oracle replaying the GPU's decision traces, at the small tests' bar;
   the properties that hold at any size are checked on the whole mesh.  The
-  fp32 path on the same grid must give the same mesh bit for bit.
+  fp32 path on the same grid must give the same mesh bit for bit, and the
+  split-bf16 searches the same topology, their vertices sampled against the
+  replaying oracle.
 """
 import os
 
@@ -137,6 +139,29 @@ def test_mlp256_bf16_equals_fp32(ctx, mlp256):
     assert np.array_equal(ra["triangles"], rb["triangles"])
     assert np.array_equal(ra["vertices"], rb["vertices"])
     assert rb["n_guard_corners"] > 0
+
+
+def test_mlp256_x3_same_topology_and_sampled_replayed(ctx, mlp256, oracle_mod):
+    """Split-bf16 searches at 256^3: every corner sign, crossing edge, pair,
+    cell, partition map and the vertex numbering equal the guarded path's
+    (whose mesh is the fp32 path's); the searches' samples against the
+    oracle replaying the split-bf16 decisions, at the small tests' bar; the
+    mesh is a closed oriented manifold."""
+    f, g, rb = mlp256
+    rx, _ = gpu_run(f, g, precision=2, ctx=ctx)
+    for k in ("corner_label", "edge_ids", "pairs", "cell_ids", "cell_partmap", "cell_nf"):
+        assert np.array_equal(rx[k], rb[k]), k
+    npart = int(np.sum(rb["cell_nf"] & 15))
+    assert np.array_equal(rx["vertex_ref"][:npart], rb["vertex_ref"][:npart])
+    rng = np.random.default_rng(17)
+    adopted = check_sampled_replayed(rx, g, oracle_mod, f, rng, 0, 150, 60, 40, "mlp256 x3")
+    ok, why = M.is_closed_oriented_manifold(rx["triangles"], rx["n_vertices"])
+    assert ok, why
+    d = np.max(np.abs(rx["vertices_local"][:npart].astype(np.float64) -
+                      rb["vertices_local"][:npart]), axis=1)
+    print(f"mlp256 x3: topology equal to the guarded path's; {adopted} near-tie decisions "
+          f"followed; vertex difference to the guarded path's: median {np.median(d):.1e}, "
+          f"max {d.max():.1e} cells ({int(np.sum(d > 1e-5))} of {npart} above 1e-5)")
 
 
 def test_sdf256_bf16_equals_fp32_and_sampled_labels(ctx, oracle_mod):

@@ -18,7 +18,8 @@ import pytest
 
 import odc_inputs as I
 import meshcheck as M
-from gpu_common import MLP_TIE, check_replayed, gpu_run, trace_of, vertex_grid_coords
+from gpu_common import (MLP_TIE, check_replayed, gpu_run, needed_search_queries, trace_of,
+                        vertex_grid_coords)
 
 pytestmark = pytest.mark.gpu
 
@@ -101,10 +102,12 @@ def test_single_cell_grid(ctx, oracle_mod):
 
 
 @pytest.mark.parametrize("res,k,prec", [(16, 10, 0), (24, 15, 0), (40, 15, 0), (24, 15, 1),
-                                        (31, 15, 1)])
+                                        (31, 15, 1), (16, 10, 2), (24, 15, 2), (40, 15, 2),
+                                        (61, 15, 2)])
 def test_mlp_parity_replayed(ctx, oracle_mod, res, k, prec):
-    """MLP field (fp32 matrix-core path, or bf16-guarded corners) against the
-    binary64 oracle replaying the GPU's branches at its near-ties.  At k = 15
+    """MLP field (fp32 matrix-core path, bf16-guarded corners, or those with
+    split-bf16 searches) against the binary64 oracle replaying the GPU's
+    branches at its near-ties.  At k = 15
     nearly every vertex depends on some near-tie (the final bracket is below
     the binary32 evaluation noise), so only the replay can hold every element
     to the stated bar."""
@@ -117,6 +120,9 @@ def test_mlp_parity_replayed(ctx, oracle_mod, res, k, prec):
     tr = trace_of(oracle_mod, r)
     m = oracle_mod.Oracle(f, g, mlp_tie_eps=MLP_TIE, trace=tr).mesh()
     dv = check_replayed(r, m, tr, res, f"mlp{res} k={k} prec={prec}")
+    # the method's own query count: what the replayed oracle's decisions need
+    assert r["n_search2d_needed"] == needed_search_queries(m, g)
+    assert r["n_search2d_needed"] <= r["n_search2d_queries"]
     nvt = int(plain["vert_tie"].sum())
     print(f"mlp{res} k={k} prec={prec}: {tr.adopted} near-tie decisions followed, "
           f"{nvt}/{len(plain['vert'])} vertices with a near-tie in their cone; "
@@ -138,6 +144,29 @@ def test_bf16_guarded_matches_fp32(ctx, res):
     assert np.array_equal(a["vertices"], b["vertices"])
 
 
+@pytest.mark.parametrize("res", [20, 32])
+def test_x3_topology_matches_fp32(ctx, res):
+    """Split-bf16 searches keep the guarded corners: labels, crossing edges,
+    pairs, cells, partitions and vertex numbering are the fp32 path's bit for
+    bit.  Vertices are not compared: at k = 15 nearly every vertex depends on
+    a search decision within binary32 noise of the threshold, where the two
+    evaluations may branch differently (each branch is checked against the
+    oracle replaying it in test_mlp_parity_replayed)."""
+    f = I.mlp_field(3)
+    g = I.unit_grid(res, 15)
+    a, _ = gpu_run(f, g, precision=0, ctx=ctx, trace=False)
+    b, _ = gpu_run(f, g, precision=2, ctx=ctx, trace=False)
+    assert b["n_guard_corners"] > 0
+    for k in ("corner_label", "edge_ids", "pairs", "cell_ids", "cell_partmap", "cell_nf"):
+        assert np.array_equal(a[k], b[k]), k
+    npart = int(np.sum(a["cell_nf"] & 15))
+    assert np.array_equal(a["vertex_ref"][:npart], b["vertex_ref"][:npart])
+    d = np.max(np.abs(a["vertices_local"][:npart].astype(np.float64) -
+                      b["vertices_local"][:npart]), axis=1)
+    print(f"x3 vs fp32 at {res}^3: vertex difference median {np.median(d):.1e}, max "
+          f"{d.max():.1e} cells")
+
+
 def test_search2d_query_counts(ctx):
     """The 2D searches skip a linear sample only when every pair of the
     wavefront has seen its label change (the sample cannot move any bracket);
@@ -148,8 +177,11 @@ def test_search2d_query_counts(ctx):
     most = (g.lin1 - 1) + 2 * (g.lin2 - 1)
     r, _ = gpu_run(I.csg_random_field(2), g, ctx=ctx, want_local=False)
     assert r["n_search2d_queries"] == r["n_pairs"] * per_pair
-    r, _ = gpu_run(I.mlp_field(3), g, ctx=ctx, want_local=False)
-    n, q = r["n_pairs"], r["n_search2d_queries"]
-    print(f"mlp40: {q} 2D-search queries for {n} pairs ({q / n:.2f} per pair of {per_pair})")
-    assert n * (per_pair - most) <= q < n * per_pair
-    assert r["n_queries"] == (41 ** 3 + r["n_guard_corners"] + r["n_active_edges"] * 15 + q)
+    assert r["n_search2d_needed"] == -1
+    for prec in (0, 2):
+        r, _ = gpu_run(I.mlp_field(3), g, precision=prec, ctx=ctx, want_local=False)
+        n, q, need = r["n_pairs"], r["n_search2d_queries"], r["n_search2d_needed"]
+        print(f"mlp40 prec={prec}: {q} 2D-search queries for {n} pairs ({q / n:.2f} per pair "
+              f"of {per_pair}), {need} needed by the method")
+        assert n * (per_pair - most) <= q < n * per_pair and 0 < need <= q
+        assert r["n_queries"] == (41 ** 3 + r["n_guard_corners"] + r["n_active_edges"] * 15 + q)

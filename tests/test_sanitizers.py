@@ -98,7 +98,7 @@ b, fits = C.c_int64(), C.c_int32()
 sizes = {}
 for res in list(range(1, 70)) + [96, 128, 129, 192, 255, 256, 257, 384, 511, 512]:
     for kind in (0, 1):
-        for prec in (0, 1):
+        for prec in (0, 1, 2):
             rc = L.odc_plan_scratch(C.byref(field(kind)), C.byref(params(res, precision=prec)),
                                     C.byref(b), C.byref(fits))
             assert rc == 0 and b.value > 0, (res, kind, rc)
@@ -107,7 +107,7 @@ assert sizes[(256, 1, 1)][1] == 1 and sizes[(512, 0, 0)][1] == 0
 assert sizes[(256, 1, 1)][0] < sizes[(512, 1, 1)][0]
 bad_params = [dict(res=0), dict(res=513), dict(iters_1d=0), dict(iters_1d=24), dict(lin1=0),
               dict(bin1=-1), dict(lin2=65), dict(bin2=31), dict(range1=0.0), dict(range2=-1.0),
-              dict(qef_tau=1.0), dict(qef_tau=-0.1), dict(precision=2), dict(guard_logit=0.0),
+              dict(qef_tau=1.0), dict(qef_tau=-0.1), dict(precision=3), dict(guard_logit=0.0),
               dict(guard_logit=float("nan")), dict(fp64_cond=0.0), dict(fp64_cond=float("nan")),
               dict(ablation=16), dict(ablation=8), dict(clamp_vertices=2), dict(size=0.0),
               dict(size=float("inf"))]

@@ -50,7 +50,7 @@ def _same(a, b, label):
         assert np.array_equal(a[k], b[k]), (label, k)
 
 
-@pytest.mark.parametrize("kind", ["mlp", "csg"])
+@pytest.mark.parametrize("kind", ["mlp", "mlp_x3", "csg"])
 def test_noalloc_equals_extract_twice(kind):
     from paper_2409_13418_amd import odc
     ctx = odc.Context(0)
@@ -58,6 +58,8 @@ def test_noalloc_equals_extract_twice(kind):
     try:
         if kind == "mlp":
             field, prec, sizes = I.mlp_field(3), odc.PREC_BF16_GUARDED, (96, 40)
+        elif kind == "mlp_x3":  # the split weight terms live in the array too
+            field, prec, sizes = I.mlp_field(5), odc.PREC_BF16_X3, (64, 33)
         else:
             field, prec, sizes = I.csg_random_field(2), odc.PREC_FP32, (128, 61)
         for res in sizes:  # the second call is smaller and reuses the array
