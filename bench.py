@@ -496,8 +496,6 @@ def _roofline(odc, field, grid, counts, stages, prec):
     if x3 and dom != "labels":
         rl["bf16_products_per_flop"] = 6
         rl["executed_frac"] = 6 * achieved / peak
-    if dom == "search2d":
-        rl["lockstep_queries_frac"] = counts["n_search2d_queries"] / counts["n_search2d_needed"]
     return rl, stages_out
 
 

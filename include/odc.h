@@ -164,17 +164,15 @@ typedef struct {
   int64_t n_fp64_cells;    /* QEF solves redone in binary64 */
   int64_t n_guard_corners; /* bf16 corner queries re-evaluated in fp32 */
   int64_t n_queries;       /* occupancy queries issued */
-  int64_t n_search2d_queries; /* of which in the 2D searches: n_pairs x (1 + lin1 + bin1 +
-                                 2 (lin2 + bin2)), less the linear samples past the first
-                                 label change of every pair that one evaluation step holds
-                                 (MLP: 32 pairs of a wavefront; 128 of a workgroup for
-                                 ODC_PREC_BF16_X3) */
+  int64_t n_search2d_queries; /* of which in the 2D searches: analytic fields every query of
+                                 each pair's sequence, n_pairs x (1 + lin1 + bin1 +
+                                 2 (lin2 + bin2)); MLP fields only the queries each pair
+                                 needs (= n_search2d_needed) */
   int64_t n_search2d_needed;  /* MLP fields: the 2D-search queries the method itself needs,
                                  summed over pairs (m; per ray the linear samples up to
                                  the first label change and the halvings; no step-2 rays
-                                 when step 1 ends at m); the rest of n_search2d_queries
-                                 is lockstep work.  -1 for CSG fields and gradient
-                                 normals (not counted). */
+                                 when step 1 ends at m).  -1 for analytic fields and
+                                 gradient normals (not counted). */
 } odc_mesh_counts;
 
 /* Status text (static storage). */

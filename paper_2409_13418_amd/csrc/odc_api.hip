@@ -393,7 +393,7 @@ Layout job_layout(const Job& J, const odc_field* f, bool guard_full, bool trace)
   L.active[17] = trace ? align_up(ne * 4) : 0;
   L.active[18] = trace ? align_up(np * 16) : 0;
   L.active_total += L.active[16] + L.active[17] + L.active[18];
-  L.status = align_up(5 * sizeof(unsigned long long));
+  L.status = align_up(4 * sizeof(unsigned long long));
   if (f->kind == ODC_FIELD_MLP) {
     const int kb1f = kb1_fp32(f->in_dim), kb1b = kb1_bf16(f->in_dim), d = f->depth;
     L.n_w1f = (size_t)kb1f * 512;
@@ -799,14 +799,14 @@ void odc::fill_counts(const odc_context* ctx, int k, odc_mesh_counts* c) {
   c->n_guard_corners = (int64_t)o[6];
   c->n_fp64_cells = (int64_t)(o[7] & 0xFFFFFFFFull);
   // occupancy queries: every corner, the bf16 guard's fp32 repeats, the 1D
-  // points (two corner queries each for linear points), the 2D searches less
-  // the linear samples no lane of a wavefront needed (none with gradient
+  // points (two corner queries each for linear points), the 2D searches: for
+  // analytic fields every query of each pair's sequence, for MLP fields the
+  // queries the pairs needed, counted on the device (none with gradient
   // normals, whose passes are not occupancy queries)
   const int64_t per_pair = 1 + (J.lin1 + J.bin1) + 2 * (J.lin2 + J.bin2);
-  c->n_search2d_queries =
-      (J.ablation & kAblGradNormals) ? 0 : c->n_pairs * per_pair - (int64_t)o[8];
-  c->n_search2d_needed =
-      (J.kind == 1 && !(J.ablation & kAblGradNormals)) ? (int64_t)o[9] : -1;
+  const bool grad = (J.ablation & kAblGradNormals) != 0;
+  c->n_search2d_needed = (J.kind == 1 && !grad) ? (int64_t)o[8] : -1;
+  c->n_search2d_queries = grad ? 0 : (J.kind == 1 ? (int64_t)o[8] : c->n_pairs * per_pair);
   c->n_queries = (int64_t)J.g.nc + c->n_guard_corners +
                  c->n_active_edges * ((J.ablation & kAblLinear1D) ? 2 : J.iters_1d) +
                  c->n_search2d_queries;

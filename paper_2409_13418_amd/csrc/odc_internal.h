@@ -34,8 +34,8 @@ hipError_t launch_pipeline(const Job* d, int njobs, const PipelineShape& sh,
                            const LaunchCfg& cfg, hipEvent_t* ev, hipStream_t s);
 // kGatherWords x uint64 per job: edges, pairs, cells, partition vertices,
 // triangles, case-3 vertices, guard corners, fp64 cells | overflow << 32,
-// 2D-search queries skipped, 2D-search queries the method needs (MLP)
-constexpr int kGatherWords = 10;
+// 2D-search queries made (MLP)
+constexpr int kGatherWords = 9;
 hipError_t launch_gather(const Job* d, int njobs, unsigned long long* out, hipStream_t s);
 hipError_t launch_eval(const Job* d_job, const Job& h_job, const float* const* d_weights,
                        int precision, const float* xyz, int n, float* z, const LaunchCfg& cfg,

@@ -316,7 +316,6 @@ __global__ void k_clear_status(const Job* __restrict__ jobs, int njobs) {
     jobs[k].status[1] = 0;
     jobs[k].status[2] = 0;
     jobs[k].status[3] = 0;
-    jobs[k].status[4] = 0;
   }
 }
 
@@ -336,7 +335,6 @@ __global__ void k_gather(const Job* __restrict__ jobs, int njobs,
     o[6] = J.status[0];
     o[7] = J.status[1] | (J.status[2] << 32);
     o[8] = J.status[3];
-    o[9] = J.status[4];
   }
 }
 
@@ -634,9 +632,6 @@ struct CsgLabel {
     grid_world(*g, gp, x);
     return csg_inside(prims, n, x);
   }
-  // CSG queries are per thread and cheap: none is skipped, so the query
-  // count stays exact without a per-thread counter
-  __device__ __forceinline__ bool skippable(int) const { return false; }
 };
 
 // wave-cooperative: every lane of the wave must call it together
@@ -649,9 +644,8 @@ struct MlpLabel {
     grid_world(*g, gp, x);
     return mlp_logit_fp32(*m, x, act) > 0.0f;
   }
-  // the wavefront evaluates together, so it skips only when no lane needs
-  // the answer
-  __device__ __forceinline__ bool skippable(int unneeded) const { return __all(unneeded); }
+  // whether any lane of the wavefront (which evaluates together) has a query
+  __device__ __forceinline__ bool any(bool q) const { return __any(q); }
 };
 
 // workgroup-cooperative (split-bf16 evaluation): the four wavefronts of the
@@ -667,10 +661,10 @@ struct X3Label {
     grid_world(*g, gp, x);
     return mlp_logit_x3(*m, x, lds, wave) > 0.0f;
   }
-  // skip only when no lane of the workgroup needs the answer
-  __device__ __forceinline__ bool skippable(int unneeded) const {
+  // whether any lane of the workgroup (which evaluates together) has a query
+  __device__ __forceinline__ bool any(bool q) const {
     parity ^= 1;
-    return x3_vote_all(lds, wave, parity, unneeded);
+    return !x3_vote_all(lds, wave, parity, !q);
   }
 };
 
@@ -879,114 +873,75 @@ struct LineBinary {
         nr = (istar == 1) ? 0.0f : (R * (float)(istar - 1)) / (float)nl;
         fa = (R * (float)istar) / (float)nl;
       }
-    } else if (lab == s0) {
-      nr = s;
     } else {
-      fa = s;
+      // both ends written through selects: a store whose address depends on
+      // the label would keep the state out of registers
+      const bool keep = lab == s0;
+      nr = keep ? s : nr;
+      fa = keep ? fa : s;
     }
   }
 };
 
-// The three steps of Sec. 5.2 for pair `slot` of face `face`, as a fixed
-// sequence of 1 + (lin1 + bin1) + 2 (lin2 + bin2) occupancy queries so that a
-// wavefront can batch each query across its lanes.  `lab` is called from
-// exactly one place.
+// The three steps of Sec. 5.2 for pair `slot` of face `face`, as a resumable
+// sequence of 1 + (lin1 + bin1) + 2 (lin2 + bin2) occupancy queries: next()
+// gives the grid point of the next query the pair needs, take() consumes its
+// label, result() is the 2D point once next() reports the end.  A driver
+// can thus interleave the queries of many pairs (one lane per pair, each at
+// its own place in its sequence) into one batched evaluation.
+//
+// With `skip`, queries the method does not need are passed over: a linear
+// sample after its ray's first label change (the change already fixed i*),
+// and step 2 when step 1 ends at m (the point is m).  Without it every query
+// of the sequence is made (the results are the same).
 //
 // Query q of the sequence (0 = m, then step 1's ray, then step 2's two rays)
 // sets bit q of `evald` when it is evaluated and bit q of `bits` to its
 // label: the decision trace that a checker can replay.  `need` counts the
-// queries the method itself needs for this pair: m, each ray's linear
-// samples up to its first label change and its halvings, and no step-2 ray
-// when step 1 ends at m.
-template <class Lab>
-__device__ double2 search_pair(const Job& j, const Lab& lab, int face, int slot, int& skipped,
-                               uint64_t& bits, uint64_t& evald, int& need) {
-  const Grid& g = j.g;
+// queries made.
+struct PairSearch {
   FaceFrame fr;
-  face_pos(g, face, fr.a, fr.p);
-  other_axes(fr.a, fr.u, fr.v);
-  int L[4], pa[2], pb[2];
-  face_labels(g, j.labels, fr.a, fr.p, L);
-  face_pairs(L, bit_of(j.fflip, face), pa, pb);
-  const int fa = slot ? pa[1] : pa[0], fb = slot ? pb[1] : pb[0];
-  const float t1 = j.et[edge_slot(j, face_edge_global(g, fr, fa))];
-  const float t2 = j.et[edge_slot(j, face_edge_global(g, fr, fb))];
-  float P1[2], P2[2];
-  face_edge_point(fa, t1, P1);
-  face_edge_point(fb, t2, P2);
-  const float m[2] = {(P1[0] + P2[0]) * 0.5f, (P1[1] + P2[1]) * 0.5f};
-  const float du = P2[0] - P1[0], dv = P2[1] - P1[1];
-  const int n1 = j.lin1 + j.bin1, n2 = j.lin2 + j.bin2;
-  const int total = 1 + n1 + 2 * n2;
+  float P1[2], P2[2], m[2], q[2], q1[2], H[4];
+  float s1, cs;
   LineBinary lb;
-  int sm = 0;
-  skipped = 0;
-  need = 0;
-  bits = 0ull;
-  evald = 0ull;
-  float q[2] = {m[0], m[1]}, q1[2] = {0, 0}, s1 = 0.0f;
-  for (int step = 0; step < total; ++step) {
-    // the query of this step
-    float P[2], s = 0.0f;
-    int k = 0;
-    if (step == 0) {
-      P[0] = m[0];
-      P[1] = m[1];
-    } else {
-      // index of the query within its own ray
-      k = step <= n1 ? step - 1 : (step <= n1 + n2 ? step - 1 - n1 : step - 1 - n1 - n2);
-      s = lb.param(k);
-      lb.point(s, P);
-    }
-    // a linear sample after the first label change cannot move the bracket
-    // (the change already fixed i*), so its query is skipped where the label
-    // functor allows; the bracket bookkeeping still runs (and ignores l)
-    need += step == 0 || ((step <= n1 || s1 != 0.0f) && !(k < lb.nl && lb.found));
-    int l = 0;
-    if (step == 0 || k >= lb.nl || !lab.skippable(lb.found)) {
-      float gp[3] = {(float)fr.p[0], (float)fr.p[1], (float)fr.p[2]};
-      add_at3(gp, fr.u, P[0]);
-      add_at3(gp, fr.v, P[1]);
-      l = lab(gp);
-      if (step < 64) {  // sequences longer than 64 queries are not traced
-        evald |= 1ull << step;
-        bits |= (uint64_t)l << step;
-      }
-    } else {
-      ++skipped;
-    }
-    if (step == 0) {
-      // step 1: the ray from m orthogonal to l, towards a corner whose label
-      // differs from m's; when both sides qualify, the side of the corner the
-      // pair cuts off.  Which side a corner is on does not depend on t in
-      // (0,1), so it is evaluated at t = 1/2 where the products are exact.
-      sm = l;
-      const float dd = du * du, ee = dv * dv;
-      const float len = sqrtf(dd + ee);
-      const float perp[2] = {-dv / len, du / len};  // left of P1 -> P2
-      float H1[2], H2[2];
-      face_edge_point(fa, 0.5f, H1);
-      face_edge_point(fb, 0.5f, H2);
-      int nleft = 0, nright = 0, dleft = 0, dright = 0;
-#pragma unroll
-      for (int lc = 0; lc < 4; ++lc) {
-        const float cu = (float)(lc & 1), cv = (float)(lc >> 1);
-        const float cr = (H2[0] - H1[0]) * (cv - H1[1]) - (H2[1] - H1[1]) * (cu - H1[0]);
-        if (cr > 0.0f) {
-          ++nleft;
-          dleft |= L[lc] != sm;
-        } else {
-          ++nright;
-          dright |= L[lc] != sm;
-        }
-      }
-      const int go_left =
-          (dleft && !dright) ? 1 : ((dright && !dleft) ? 0 : (nleft <= nright ? 1 : 0));
-      const float d[2] = {go_left ? perp[0] : -perp[0], go_left ? perp[1] : -perp[1]};
-      lb.start(m, d, sm, j.range1, j.lin1);
-      continue;
-    }
-    lb.consume(k, s, l);
+  int lmask, sm, n1, n2, total, step, ck, need;
+  uint64_t bits, evald;
+
+  __device__ __forceinline__ void init(const Job& j, int face, int slot) {
+    const Grid& g = j.g;
+    face_pos(g, face, fr.a, fr.p);
+    other_axes(fr.a, fr.u, fr.v);
+    int L[4], pa[2], pb[2];
+    face_labels(g, j.labels, fr.a, fr.p, L);
+    face_pairs(L, bit_of(j.fflip, face), pa, pb);
+    lmask = L[0] | (L[1] << 1) | (L[2] << 2) | (L[3] << 3);
+    const int fa = slot ? pa[1] : pa[0], fb = slot ? pb[1] : pb[0];
+    const float t1 = j.et[edge_slot(j, face_edge_global(g, fr, fa))];
+    const float t2 = j.et[edge_slot(j, face_edge_global(g, fr, fb))];
+    face_edge_point(fa, t1, P1);
+    face_edge_point(fb, t2, P2);
+    // which side of the chord a corner lies on does not depend on t in
+    // (0,1); it is evaluated at t = 1/2, where the products are exact
+    face_edge_point(fa, 0.5f, H);
+    face_edge_point(fb, 0.5f, H + 2);
+    m[0] = (P1[0] + P2[0]) * 0.5f;
+    m[1] = (P1[1] + P2[1]) * 0.5f;
+    q[0] = m[0];
+    q[1] = m[1];
+    q1[0] = q1[1] = 0.0f;
+    s1 = 0.0f;
+    sm = 0;
+    n1 = j.lin1 + j.bin1;
+    n2 = j.lin2 + j.bin2;
+    total = 1 + n1 + 2 * n2;
+    step = 0;
+    need = 0;
+    bits = 0ull;
+    evald = 0ull;
+  }
+
+  // the ray transitions after the query at `step` (Sec. 5.2 steps 1 and 2)
+  __device__ __forceinline__ void after(const Job& j) {
     if (step == n1) {
       // end of step 1: q; step 2 starts towards P1
       s1 = lb.nr;
@@ -1002,109 +957,236 @@ __device__ double2 search_pair(const Job& j, const Lab& lab, int face, int slot,
       lb.start(q, un, sm, j.range2, j.lin2);
     }
   }
-  float q2[2];
-  lb.point(lb.nr, q2);
-  if (s1 == 0.0f) return make_double2(m[0], m[1]);
-  // step 3: intersection of line(P1,q1) and line(P2,q2).  On smooth surfaces
-  // l1 and l2 are nearly parallel (sin ~ 1e-4), where binary32 differences of
-  // the inputs alone move the apex by 1e-7/sin; the solve is binary64 (the
-  // differences of binary32 inputs are then exact) and the point is kept in
-  // binary64: where a cell cuts a tiny corner, its 2D points sit within 1e-5
-  // of their 1D points near face coordinate 1, below binary32 resolution
-  // there relative to the distance that sets the normal.
-  const double Au = (double)q1[0] - (double)P1[0], Av = (double)q1[1] - (double)P1[1];
-  const double Bu = (double)q2[0] - (double)P2[0], Bv = (double)q2[1] - (double)P2[1];
-  const double det = Au * Bv - Av * Bu;
-  if (det == 0.0) return make_double2(q[0], q[1]);
-  const double Du = (double)P2[0] - (double)P1[0], Dv = (double)P2[1] - (double)P1[1];
-  const double alpha = (Du * Bv - Dv * Bu) / det;
-  return make_double2((double)P1[0] + alpha * Au, (double)P1[1] + alpha * Av);
-}
 
+  __device__ __forceinline__ bool next(const Job& j, bool skip, float gp[3]) {
+    while (step < total) {
+      float P[2];
+      if (step == 0) {
+        P[0] = m[0];
+        P[1] = m[1];
+      } else {
+        if (skip && step > n1 && s1 == 0.0f) {  // step 1 ended at m
+          step = total;
+          break;
+        }
+        // index of the query within its own ray
+        const int k =
+            step <= n1 ? step - 1 : (step <= n1 + n2 ? step - 1 - n1 : step - 1 - n1 - n2);
+        const float s = lb.param(k);
+        if (skip && k < lb.nl && lb.found) {  // the bookkeeping still runs (label unused)
+          lb.consume(k, s, 0);
+          after(j);
+          ++step;
+          continue;
+        }
+        ck = k;
+        cs = s;
+        lb.point(s, P);
+      }
+      gp[0] = (float)fr.p[0];
+      gp[1] = (float)fr.p[1];
+      gp[2] = (float)fr.p[2];
+      add_at3(gp, fr.u, P[0]);
+      add_at3(gp, fr.v, P[1]);
+      return true;
+    }
+    return false;
+  }
+
+  __device__ __forceinline__ void take(const Job& j, int l) {
+    if (step < 64) {  // sequences longer than 64 queries are not traced
+      evald |= 1ull << step;
+      bits |= (uint64_t)l << step;
+    }
+    ++need;
+    if (step == 0) {
+      // step 1: the ray from m orthogonal to l, towards a corner whose label
+      // differs from m's; when both sides qualify, the side of the corner the
+      // pair cuts off
+      sm = l;
+      const float du = P2[0] - P1[0], dv = P2[1] - P1[1];
+      const float dd = du * du, ee = dv * dv;
+      const float len = sqrtf(dd + ee);
+      const float perp[2] = {-dv / len, du / len};  // left of P1 -> P2
+      int nleft = 0, nright = 0, dleft = 0, dright = 0;
+#pragma unroll
+      for (int lc = 0; lc < 4; ++lc) {
+        const float cu = (float)(lc & 1), cv = (float)(lc >> 1);
+        const float cr = (H[2] - H[0]) * (cv - H[1]) - (H[3] - H[1]) * (cu - H[0]);
+        const int differs = ((lmask >> lc) & 1) != sm;
+        if (cr > 0.0f) {
+          ++nleft;
+          dleft |= differs;
+        } else {
+          ++nright;
+          dright |= differs;
+        }
+      }
+      const int go_left =
+          (dleft && !dright) ? 1 : ((dright && !dleft) ? 0 : (nleft <= nright ? 1 : 0));
+      const float d[2] = {go_left ? perp[0] : -perp[0], go_left ? perp[1] : -perp[1]};
+      lb.start(m, d, sm, j.range1, j.lin1);
+    } else {
+      lb.consume(ck, cs, l);
+      after(j);
+    }
+    ++step;
+  }
+
+  __device__ __forceinline__ double2 result() const {
+    if (s1 == 0.0f) return make_double2(m[0], m[1]);
+    float q2[2];
+    lb.point(lb.nr, q2);
+    // step 3: intersection of line(P1,q1) and line(P2,q2).  On smooth
+    // surfaces l1 and l2 are nearly parallel (sin ~ 1e-4), where binary32
+    // differences of the inputs alone move the apex by 1e-7/sin; the solve
+    // is binary64 (the differences of binary32 inputs are then exact) and
+    // the point is kept in binary64: where a cell cuts a tiny corner, its 2D
+    // points sit within 1e-5 of their 1D points near face coordinate 1, below
+    // binary32 resolution there relative to the distance that sets the normal.
+    const double Au = (double)q1[0] - (double)P1[0], Av = (double)q1[1] - (double)P1[1];
+    const double Bu = (double)q2[0] - (double)P2[0], Bv = (double)q2[1] - (double)P2[1];
+    const double det = Au * Bv - Av * Bu;
+    if (det == 0.0) return make_double2(q[0], q[1]);
+    const double Du = (double)P2[0] - (double)P1[0], Dv = (double)P2[1] - (double)P1[1];
+    const double alpha = (Du * Bv - Dv * Bu) / det;
+    return make_double2((double)P1[0] + alpha * Au, (double)P1[1] + alpha * Av);
+  }
+};
+
+// Analytic fields: one thread per pair, every query of the sequence made
+// (queries are cheap; the count stays n_pairs x the sequence length).
 __global__ __launch_bounds__(256) void k_search2d_csg(const Job* __restrict__ jobs, int njobs) {
   for_units(jobs, njobs, gthread(), nthreads(),
             [](const Job& J) { return J.kind == 0 ? n_pairs_of(J) : 0; },
             [&](const Job& J, int x) {
               CsgLabel lab{&J.g, J.prims, J.n_prims};
               const int rec = J.plist[x];
-              int skipped, need;
-              uint64_t bits, evald;
-              J.pf[x] = search_pair(J, lab, rec >> 1, rec & 1, skipped, bits, evald, need);
+              PairSearch ps;
+              ps.init(J, rec >> 1, rec & 1);
+              float gp[3];
+              while (ps.next(J, false, gp)) ps.take(J, lab(gp));
+              J.pf[x] = ps.result();
               if (J.ptrace) {
-                J.ptrace[2 * x] = bits;
-                J.ptrace[2 * x + 1] = evald;
+                J.ptrace[2 * x] = ps.bits;
+                J.ptrace[2 * x + 1] = ps.evald;
               }
             });
+}
+
+// MLP fields: a wavefront keeps 32 pairs in flight, one per lane (lanes
+// l and l + 32 mirror each other: they hold the two K halves of one query
+// column), and evaluates the next query of all of them at once.  A lane whose
+// pair ends takes the next pair of the wavefront's stream at once, so lanes
+// do not wait for the slowest pair of a group, and each pair makes only the
+// queries it needs.  The stream is the pairs of the units this worker owns
+// (units of `per_unit` pairs; this wavefront's 32 of each start at `off`).
+// `lab.any` ends the loop when no lane of the evaluating group has a query.
+template <class Lab>
+__device__ __forceinline__ void search_stream(const Job& J, const Lab& lab, int u0, int W,
+                                              int n_units, int per_unit, int off) {
+  const int np = n_pairs_of(J);
+  const int lane = lane_id(), ln = lane & 31;
+  const int slen = n_units * 32;
+  int next = 0, have = 0, x = 0, need = 0;
+  PairSearch ps;
+  while (true) {
+    float gp[3] = {0.0f, 0.0f, 0.0f};
+    bool q = false;
+    if (have) {
+      q = ps.next(J, true, gp);
+      if (!q) {
+        if (lane < 32) {
+          J.pf[x] = ps.result();
+          if (J.ptrace) {
+            J.ptrace[2 * x] = ps.bits;
+            J.ptrace[2 * x + 1] = ps.evald;
+          }
+        }
+        need += ps.need;
+        have = 0;
+      }
+    }
+    // refill: the free lanes (the same in both halves) take the next pairs
+    const uint32_t free_lanes = (uint32_t)__ballot(!have);
+    if (free_lanes != 0u && next < slen) {
+      const int pos = next + __popc(free_lanes & ((1u << ln) - 1u));
+      next += __popc(free_lanes);
+      if (!have && pos < slen) {
+        const int xi = (u0 + (pos >> 5) * W) * per_unit + off + (pos & 31);
+        if (xi < np) {
+          x = xi;
+          const int rec = J.plist[x];
+          ps.init(J, rec >> 1, rec & 1);
+          have = 1;
+          q = ps.next(J, true, gp);  // m: always made
+        }
+      }
+    }
+    if (!lab.any(q)) break;
+    const int l = lab(gp);
+    if (q) ps.take(J, l);
+  }
+  const int nsum = wave_sum(lane < 32 ? need : 0);
+  if (lane == 0 && nsum) atomicAdd(&J.status[3], (unsigned long long)nsum);
+}
+
+// Job-major distribution of whole unit streams: body(J, u0, W, count) gets
+// the units u0, u0 + W, ... (count of them) of every job that belong to
+// `worker`, the same units for_units would give it.
+template <class NFn, class Body>
+__device__ __forceinline__ void for_unit_streams(const Job* __restrict__ jobs, int njobs,
+                                                 int worker, int W, const NFn& nunits,
+                                                 const Body& body) {
+  const __attribute__((address_space(4))) Job* cj =
+      (const __attribute__((address_space(4))) Job*)jobs;
+  long long rot = 0;
+  for (int k = 0; k < njobs; ++k) {
+    const Job& J = *(const Job*)&cj[k];
+    const int n = nunits(J);
+    if (n <= 0) continue;
+    int u0 = (int)(((long long)worker - rot) % W);
+    if (u0 < 0) u0 += W;
+    if (u0 < n) body(J, u0, (n - u0 + W - 1) / W);
+    rot += n;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_search2d_mlp(const Job* __restrict__ jobs, int njobs) {
   __shared__ __align__(16) float act_lds[kBlock / 64][kActWords];
   float* act = act_lds[threadIdx.x >> 6];
-  for_units(jobs, njobs, gwave(), nwaves(),
-            [](const Job& J) {
-              return (J.kind == 1 && J.precision != 2 && !(J.ablation & kAblGradNormals))
-                         ? (n_pairs_of(J) + 31) >> 5
-                         : 0;
-            },
-            [&](const Job& J, int t) {
-              const int np = n_pairs_of(J);
-              const int lane = lane_id();
-              const int x = t * 32 + (lane & 31);
-              const bool valid = x < np;
-              MlpLabel lab{&J.g, &J.mlp, act};
-              const int rec = J.plist[valid ? x : np - 1];
-              int skipped, need;  // skipped: wave-uniform
-              uint64_t bits, evald;
-              const double2 r = search_pair(J, lab, rec >> 1, rec & 1, skipped, bits, evald, need);
-              if (valid && lane < 32) {
-                J.pf[x] = r;
-                if (J.ptrace) {
-                  J.ptrace[2 * x] = bits;
-                  J.ptrace[2 * x + 1] = evald;
-                }
-              }
-              if (lane == 0 && skipped)
-                atomicAdd(&J.status[3],
-                          (unsigned long long)skipped * (unsigned long long)min(32, np - t * 32));
-              const int nsum = wave_sum(valid && lane < 32 ? need : 0);
-              if (lane == 0) atomicAdd(&J.status[4], (unsigned long long)nsum);
-            });
+  const int W = nwaves();
+  for_unit_streams(jobs, njobs, gwave(), W,
+                   [](const Job& J) {
+                     return (J.kind == 1 && J.precision != 2 &&
+                             !(J.ablation & kAblGradNormals))
+                                ? (n_pairs_of(J) + 31) >> 5
+                                : 0;
+                   },
+                   [&](const Job& J, int u0, int count) {
+                     MlpLabel lab{&J.g, &J.mlp, act};
+                     search_stream(J, lab, u0, W, count, 32, 0);
+                   });
 }
 
-// Split-bf16 evaluation (precision 2): a workgroup takes 128 pairs, 32 per
-// wavefront, and the four evaluate each search query together; a linear
-// sample is skipped when no pair of the workgroup needs it.
+// Split-bf16 evaluation (precision 2): a workgroup keeps 128 pairs in
+// flight, 32 per wavefront, and the four evaluate each round of queries
+// together; it stops when none of the four has a query left.
 __global__ __launch_bounds__(256) void k_search2d_x3(const Job* __restrict__ jobs, int njobs) {
   __shared__ __align__(16) char lds[kX3LdsBytes];
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  for_units(jobs, njobs, (int)blockIdx.x, (int)gridDim.x,
-            [](const Job& J) { return J.kind == 1 && J.precision == 2 ? (n_pairs_of(J) + 127) >> 7 : 0; },
-            [&](const Job& J, int t) {
-              lds_block_sync();
-              x3_stage(J.mlp, lds);
-              lds_block_sync();
-              const int np = n_pairs_of(J);
-              const int lane = lane_id();
-              const int x = t * 128 + wave * 32 + (lane & 31);
-              const bool valid = x < np;
-              X3Label lab{&J.g, &J.mlp, lds, wave, 0};
-              const int rec = J.plist[valid ? x : np - 1];
-              int skipped, need;  // skipped: workgroup-uniform
-              uint64_t bits, evald;
-              const double2 r = search_pair(J, lab, rec >> 1, rec & 1, skipped, bits, evald, need);
-              if (valid && lane < 32) {
-                J.pf[x] = r;
-                if (J.ptrace) {
-                  J.ptrace[2 * x] = bits;
-                  J.ptrace[2 * x + 1] = evald;
-                }
-              }
-              if (wave == 0 && lane == 0 && skipped)
-                atomicAdd(&J.status[3],
-                          (unsigned long long)skipped * (unsigned long long)min(128, np - t * 128));
-              const int nsum = wave_sum(valid && lane < 32 ? need : 0);
-              if (lane == 0) atomicAdd(&J.status[4], (unsigned long long)nsum);
-            });
+  const int W = (int)gridDim.x;
+  for_unit_streams(jobs, njobs, (int)blockIdx.x, W,
+                   [](const Job& J) {
+                     return J.kind == 1 && J.precision == 2 ? (n_pairs_of(J) + 127) >> 7 : 0;
+                   },
+                   [&](const Job& J, int u0, int count) {
+                     lds_block_sync();  // the previous job's reads of the staged field are done
+                     x3_stage(J.mlp, lds);
+                     lds_block_sync();
+                     X3Label lab{&J.g, &J.mlp, lds, wave, 0};
+                     search_stream(J, lab, u0, W, count, 128, wave * 32);
+                   });
 }
 
 // ----------------------------------------------------- (d) partitions, QEF
