@@ -145,4 +145,25 @@ __device__ __forceinline__ void for_units(const Job* __restrict__ jobs, int njob
   }
 }
 
+// Job-major distribution of whole unit streams: body(J, u0, W, count) gets
+// the units u0, u0 + W, ... (count of them) of every job that belong to
+// `worker`, the same units for_units would give it.
+template <class NFn, class Body>
+__device__ __forceinline__ void for_unit_streams(const Job* __restrict__ jobs, int njobs,
+                                                 int worker, int W, const NFn& nunits,
+                                                 const Body& body) {
+  const __attribute__((address_space(4))) Job* cj =
+      (const __attribute__((address_space(4))) Job*)jobs;
+  long long rot = 0;
+  for (int k = 0; k < njobs; ++k) {
+    const Job& J = *(const Job*)&cj[k];
+    const int n = nunits(J);
+    if (n <= 0) continue;
+    int u0 = (int)(((long long)worker - rot) % W);
+    if (u0 < 0) u0 += W;
+    if (u0 < n) body(J, u0, (n - u0 + W - 1) / W);
+    rot += n;
+  }
+}
+
 }  // namespace odc

@@ -360,31 +360,27 @@ __global__ __launch_bounds__(256) void k_labels_csg(const Job* __restrict__ jobs
 
 // MLP corners, 32 per wavefront.  fp32: each wavefront takes label words on
 // its own.  bf16 (guard-band corners queued for fp32 re-evaluation): the four
-// wavefronts of a workgroup evaluate their 128 corners together, split by
-// output tiles (mlp_logit_bf16_split), so they take four consecutive words
-// together (workgroup-uniform units, a wavefront past the end evaluating a
-// clamped dummy) and every call is made by all four.
+// wavefronts of a workgroup evaluate their 128 corners together
+// (mlp_logit_bf16_pp), so they take four consecutive words together
+// (workgroup-uniform units, a wavefront past the end evaluating a clamped
+// dummy) and every call is made by all four; two such workgroups share a
+// compute unit (one wavefront of each per SIMD), so one's matrix work fills
+// the other's waits.
 template <int BF16>
-__global__ __launch_bounds__(256) void k_labels_mlp(const Job* __restrict__ jobs, int njobs) {
-  static_assert(kBlock == 256, "the split bf16 evaluation takes four wavefronts");
+__global__ __launch_bounds__(256, BF16 ? 2 : 1) void k_labels_mlp(const Job* __restrict__ jobs,
+                                                                 int njobs) {
+  static_assert(kBlock == 256, "the bf16 evaluation takes four wavefronts");
   __shared__ __align__(16) float act_lds[BF16 ? 1 : kBlock / 64][BF16 ? 4 : kActWords];
-  __shared__ __align__(16) char split_lds[BF16 ? kSplitLdsBytes : 16];
+  __shared__ __align__(16) char pp_lds[BF16 ? kPPLdsBytes : 16];
   // wave-uniform (the loads' scalar offsets depend on it)
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   float* act = act_lds[BF16 ? 0 : wave];
-  auto body = [&](const Job& J, int t) {
+  auto body = [&](const Job& J, int t, float z) {
     const Grid& g = J.g;
     const int lane = lane_id();
     const bool unit = t < J.nw_c;
     const int c = t * 32 + (lane & 31);
     const bool valid = unit && c < g.nc;
-    const int cc = valid ? c : g.nc - 1;
-    const int n1 = g.N + 1;
-    const float gp[3] = {(float)(cc % n1), (float)((cc / n1) % n1), (float)(cc / (n1 * n1))};
-    float x[3];
-    grid_world(g, gp, x);
-    const float z = BF16 ? mlp_logit_bf16_split(J.mlp, x, split_lds, wave)
-                         : mlp_logit_fp32(J.mlp, x, act);
     const uint64_t b = __ballot(valid && z > 0.0f);
     if (unit && lane == 0) J.labels[t] = (uint32_t)b;
     if (BF16) {
@@ -402,6 +398,15 @@ __global__ __launch_bounds__(256) void k_labels_mlp(const Job* __restrict__ jobs
       }
     }
   };
+  // world position of corner word t's lane
+  auto position = [&](const Job& J, int t, float x[3]) {
+    const Grid& g = J.g;
+    const int c = t * 32 + (lane_id() & 31);
+    const int cc = t < J.nw_c && c < g.nc ? c : g.nc - 1;
+    const int n1 = g.N + 1;
+    const float gp[3] = {(float)(cc % n1), (float)((cc / n1) % n1), (float)(cc / (n1 * n1))};
+    grid_world(g, gp, x);
+  };
   // bf16 corners also for the split-bf16 precision (2); both re-evaluate
   // their guard band in fp32 (k_relabel_fp32), so their corner signs are
   // the fp32 path's
@@ -409,12 +414,32 @@ __global__ __launch_bounds__(256) void k_labels_mlp(const Job* __restrict__ jobs
     return J.kind == 1 && (BF16 ? J.precision >= 1 : J.precision == 0);
   };
   if constexpr (BF16) {
-    for_units(jobs, njobs, (int)blockIdx.x, (int)gridDim.x,
-              [&](const Job& J) { return mine(J) ? (J.nw_c + 3) >> 2 : 0; },
-              [&](const Job& J, int grp) { body(J, 4 * grp + wave); });
+    // the field's biases and output weights are staged, and the weight ring
+    // primed, once per job
+    for_unit_streams(jobs, njobs, (int)blockIdx.x, (int)gridDim.x,
+                     [&](const Job& J) { return mine(J) ? (J.nw_c + 3) >> 2 : 0; },
+                     [&](const Job& J, int u0, int count) {
+                       lds_block_sync();  // the previous job's reads are done
+                       stage_bias_wout(J.mlp, pp_lds + kPPBiasOff);
+                       const PPStream S(J.mlp, wave);
+                       v8bf W[kPPRing][2];
+                       pp_prime(S, W);
+                       lds_block_sync();
+                       for (int i = 0; i < count; ++i) {
+                         const int t = 4 * (u0 + i * (int)gridDim.x) + wave;
+                         float x[3];
+                         position(J, t, x);
+                         body(J, t, mlp_logit_bf16_pp(J.mlp, x, pp_lds, wave, S, W));
+                       }
+                     });
   } else {
     for_units(jobs, njobs, gwave(), nwaves(),
-              [&](const Job& J) { return mine(J) ? J.nw_c : 0; }, body);
+              [&](const Job& J) { return mine(J) ? J.nw_c : 0; },
+              [&](const Job& J, int t) {
+                float x[3];
+                position(J, t, x);
+                body(J, t, mlp_logit_fp32(J.mlp, x, act));
+              });
   }
 }
 
@@ -1131,27 +1156,6 @@ __device__ __forceinline__ void search_stream(const Job& J, const Lab& lab, int 
   if (lane == 0 && nsum) atomicAdd(&J.status[3], (unsigned long long)nsum);
 }
 
-// Job-major distribution of whole unit streams: body(J, u0, W, count) gets
-// the units u0, u0 + W, ... (count of them) of every job that belong to
-// `worker`, the same units for_units would give it.
-template <class NFn, class Body>
-__device__ __forceinline__ void for_unit_streams(const Job* __restrict__ jobs, int njobs,
-                                                 int worker, int W, const NFn& nunits,
-                                                 const Body& body) {
-  const __attribute__((address_space(4))) Job* cj =
-      (const __attribute__((address_space(4))) Job*)jobs;
-  long long rot = 0;
-  for (int k = 0; k < njobs; ++k) {
-    const Job& J = *(const Job*)&cj[k];
-    const int n = nunits(J);
-    if (n <= 0) continue;
-    int u0 = (int)(((long long)worker - rot) % W);
-    if (u0 < 0) u0 += W;
-    if (u0 < n) body(J, u0, (n - u0 + W - 1) / W);
-    rot += n;
-  }
-}
-
 __global__ __launch_bounds__(256) void k_search2d_mlp(const Job* __restrict__ jobs, int njobs) {
   __shared__ __align__(16) float act_lds[kBlock / 64][kActWords];
   float* act = act_lds[threadIdx.x >> 6];
@@ -1655,7 +1659,8 @@ hipError_t launch_pipeline(const Job* d, int njobs, const PipelineShape& sh,
   mark(0);
   if (sh.any_csg) k_labels_csg<<<cfg.grid_blocks, kBlock, 0, s>>>(d, njobs);
   if (sh.any_mlp_fp32) k_labels_mlp<0><<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
-  if (sh.any_mlp_bf16 || sh.any_mlp_x3) k_labels_mlp<1><<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
+  if (sh.any_mlp_bf16 || sh.any_mlp_x3)
+    k_labels_mlp<1><<<2 * cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
   if (sh.any_mlp_bf16 || sh.any_mlp_x3)
     k_relabel_fp32<<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
   mark(1);
@@ -1706,11 +1711,10 @@ __global__ __launch_bounds__(256) void k_eval_csg(const float* __restrict__ prim
   }
 }
 
-template <int BF16>
-__global__ __launch_bounds__(256) void k_eval_mlp(const Job* __restrict__ job,
-                                                  const float* __restrict__ xyz, int n,
-                                                  float* __restrict__ z) {
-  __shared__ __align__(16) float act_lds[kBlock / 64][BF16 ? kActWordsBF16 : kActWords];
+__global__ __launch_bounds__(256) void k_eval_fp32(const Job* __restrict__ job,
+                                                   const float* __restrict__ xyz, int n,
+                                                   float* __restrict__ z) {
+  __shared__ __align__(16) float act_lds[kBlock / 64][kActWords];
   float* act = act_lds[threadIdx.x >> 6];
   const Mlp& m = job->mlp;
   const int lane = lane_id();
@@ -1718,8 +1722,30 @@ __global__ __launch_bounds__(256) void k_eval_mlp(const Job* __restrict__ job,
     const int i = t * 32 + (lane & 31);
     const int k = i < n ? i : n - 1;
     const float x[3] = {xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2]};
-    const float v = BF16 ? mlp_logit_bf16(m, x, act)
-                         : mlp_logit_fp32(m, x, act);
+    const float v = mlp_logit_fp32(m, x, act);
+    if (i < n && lane < 32) z[i] = v;
+  }
+}
+
+// the bf16 evaluation of the corner pass (mlp_logit_bf16_pp), 128 points per
+// workgroup
+__global__ __launch_bounds__(256, 2) void k_eval_bf16(const Job* __restrict__ job,
+                                                   const float* __restrict__ xyz, int n,
+                                                   float* __restrict__ z) {
+  __shared__ __align__(16) char lds[kPPLdsBytes];
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const Mlp& m = job->mlp;
+  const int lane = lane_id();
+  stage_bias_wout(m, lds + kPPBiasOff);
+  const PPStream S(m, wave);
+  v8bf W[kPPRing][2];
+  pp_prime(S, W);
+  lds_block_sync();
+  for (int t = blockIdx.x; t * 128 < n; t += gridDim.x) {
+    const int i = t * 128 + wave * 32 + (lane & 31);
+    const int k = i < n ? i : n - 1;
+    const float x[3] = {xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2]};
+    const float v = mlp_logit_bf16_pp(m, x, lds, wave, S, W);
     if (i < n && lane < 32) z[i] = v;
   }
 }
@@ -1749,8 +1775,8 @@ hipError_t launch_eval(const Job* d_job, const Job& h_job, const float* const* d
     k_eval_csg<<<cfg.elem_blocks, kBlock, 0, s>>>(h_job.prims, h_job.n_prims, xyz, n, z);
   } else {
     k_pack<<<cfg.pack_blocks, kBlock, 0, s>>>(d_job, 1, d_weights);
-    if (precision == 0) k_eval_mlp<0><<<cfg.mlp_blocks, kBlock, 0, s>>>(d_job, xyz, n, z);
-    else if (precision == 1) k_eval_mlp<1><<<cfg.mlp_blocks, kBlock, 0, s>>>(d_job, xyz, n, z);
+    if (precision == 0) k_eval_fp32<<<cfg.mlp_blocks, kBlock, 0, s>>>(d_job, xyz, n, z);
+    else if (precision == 1) k_eval_bf16<<<2 * cfg.mlp_blocks, kBlock, 0, s>>>(d_job, xyz, n, z);
     else k_eval_x3<<<cfg.mlp_blocks, kBlock, 0, s>>>(d_job, xyz, n, z);
   }
   return hipGetLastError();

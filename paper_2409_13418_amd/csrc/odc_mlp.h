@@ -430,16 +430,9 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
   return mlp_output<kTan>(M, acc, h, zero, x);
 }
 
-// bf16 operands, fp32 accumulation (all 64 lanes must be active).  `act`
-// is this wavefront's LDS region of kActWordsBF16 floats: the parked
-// pre-activations of the last layer, laid out as in the fp32 path, then the
-// 256 biases of that layer.  A K block b of a hidden layer takes, in lane
-// half h, neurons 16b + 4h + (0..3) and 16b + 8 + 4h + (0..3): parked
-// vectors 2b and 2b + 1 of the lane and bias vectors 4b + h and 4b + 2 + h.
-// Its B operand bf16(relu(pre + bias)) is formed while the previous block's
-// matrix instructions run (bf16 matrix instructions co-issue with a few VALU
-// instructions each; a serial transition between layers would not).
-constexpr int kActWordsBF16 = kActWords + kWidth;
+// bf16 evaluation (corner pass): a K block b of a hidden layer takes, in
+// lane half h, neurons 16b + 4h + (0..3) and 16b + 8 + 4h + (0..3); its B
+// operand is bf16(relu(pre + bias)) (bf16_operand).
 // Ring depth of the bf16 weight stream (K blocks of 16 rows; 32 registers
 // per block), as in the fp32 path.
 constexpr int kPrefetchBF16 = 4;
@@ -469,98 +462,6 @@ __device__ __forceinline__ v8bf bf16_operand(v4f a0, v4f a1, v4f t0, v4f t1) {
   return relu_bf16(__builtin_bit_cast(v8bf, p));
 }
 
-__device__ __forceinline__ float mlp_logit_bf16(const Mlp& M, const float x[3],
-                                                float* __restrict__ act) {
-  const int lane = lane_id();
-  const int h = lane >> 5;
-  int zero = 0;  // keeps the ring prologue here (see mlp_logit_fp32)
-  asm volatile("" : "+v"(zero));
-  v4f* act4 = reinterpret_cast<v4f*>(act);
-  v4f* tab4 = act4 + kGroupsF32 * 64;
-  // this lane's four biases of each layer, fetched one layer ahead
-  const ODC_GLOBAL v4f* Bg = (const ODC_GLOBAL v4f*)gmem(M.bias) + lane + zero;
-  v4f tb = Bg[0];
-  // layer 1, then the hidden layers, through a buffer resource as in the
-  // fp32 path: vector (8b + R) of the stream holds tile R of K block b
-  const __amdgpu_buffer_rsrc_t ws = weight_stream(
-      M.w1b, ((size_t)M.kb1b + (size_t)(M.depth - 1) * kHiddenBlocksBF16 + kPrefetchBF16) * 8192);
-  const int voff = (lane + zero) * 16;
-  auto S = [&](int vec) -> v8bf {
-    return __builtin_bit_cast(v8bf, __builtin_amdgcn_raw_buffer_load_b128(ws, voff, vec * 1024, 0));
-  };
-  v8bf wr[kPrefetchBF16][8];
-#pragma unroll
-  for (int d = 0; d < kPrefetchBF16; ++d)
-#pragma unroll
-    for (int R = 0; R < 8; ++R) wr[d][R] = S(d * 8 + R);
-  const v16f zacc = {};
-  v16f acc[8];
-  const float quarter_h = h ? 0.25f : 0.0f;
-  auto features = [&](int b) {
-    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
-    v4u p;
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      p[j] = pack_bf16(pair_feature_fast(8 * b + 2 * j, quarter_h, h, x),
-                       pair_feature_fast(8 * b + 2 * j + 1, quarter_h, h, x));
-    return __builtin_bit_cast(v8bf, p);
-  };
-  const int ng = M.kb1b / kPrefetchBF16;
-  v8bf bv = features(0);
-#pragma unroll
-  for (int gi = 0; gi < kMaxGroups1BF16; ++gi) {
-    if (gi == 0 || gi < ng) {
-#pragma unroll
-      for (int d = 0; d < kPrefetchBF16; ++d) {
-        const int b = gi * kPrefetchBF16 + d;
-#pragma unroll
-        for (int R = 0; R < 8; ++R)
-          acc[R] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[d][R], bv, b == 0 ? zacc : acc[R],
-                                                           0, 0, 0);
-        bv = features(b + 1);
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int R = 0; R < 8; ++R) wr[d][R] = S((b + kPrefetchBF16) * 8 + R);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
-  }
-  for (int l = 1; l < M.depth; ++l) {
-    // park layer l's pre-activations and biases; fetch layer l+1's biases
-#pragma unroll
-    for (int T = 0; T < 8; ++T)
-#pragma unroll
-      for (int g = 0; g < 4; ++g)
-        act4[(4 * T + g) * 64 + lane] =
-            (v4f){acc[T][4 * g], acc[T][4 * g + 1], acc[T][4 * g + 2], acc[T][4 * g + 3]};
-    tab4[lane] = tb;
-    tb = Bg[(size_t)l * 64];
-    const int wn = (M.kb1b + (l - 1) * kHiddenBlocksBF16 + kPrefetchBF16) * 8;
-    bv = bf16_operand(act4[lane], act4[64 + lane], tab4[h], tab4[2 + h]);
-#pragma unroll
-    for (int b0 = 0; b0 < kHiddenBlocksBF16; b0 += kPrefetchBF16) {
-#pragma unroll
-      for (int d = 0; d < kPrefetchBF16; ++d) {
-        const int b = b0 + d;
-        const int bn = (b + 1) & (kHiddenBlocksBF16 - 1);
-        const v4f a0 = act4[(2 * bn) * 64 + lane], a1 = act4[(2 * bn + 1) * 64 + lane];
-        const v4f t0 = tab4[4 * bn + h], t1 = tab4[4 * bn + 2 + h];
-#pragma unroll
-        for (int R = 0; R < 8; ++R)
-          acc[R] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[d][R], bv, b == 0 ? zacc : acc[R],
-                                                           0, 0, 0);
-        // the next block's operand (after the last block: unused)
-        bv = bf16_operand(a0, a1, t0, t1);
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int R = 0; R < 8; ++R) wr[d][R] = S(wn + b * 8 + R);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
-  }
-  return mlp_output(M, acc, h, zero, x);
-}
-
 // LDS wait and workgroup barrier: this wavefront's LDS operations are
 // complete, and the other wavefronts' are once it returns.
 __device__ __forceinline__ void lds_block_sync() {
@@ -569,165 +470,244 @@ __device__ __forceinline__ void lds_block_sync() {
   __builtin_amdgcn_sched_barrier(0);
 }
 
-// The bf16 evaluation of 128 queries by the four wavefronts of a
-// 256-thread workgroup, split by output tiles: wavefront w computes tiles
-// 2w and 2w + 1 (neurons 64w..64w + 63) of every layer for all four query
-// sets (set s = the 32 queries of wavefront s), streaming only those tiles'
-// weight fragments (two 16-byte loads per lane per K block).  The layers'
-// inputs are exchanged as bf16 operands through two LDS buffers of
-// [set][K block][lane] 16-byte vectors (64 KB each, alternating between
-// layers): a layer's end converts the wavefront's accumulators into its
-// share of the next layer's operands, bf16(relu(pre + bias)), then one
-// barrier.  After the last layer every wavefront parks its fp32
-// accumulators in the same 128 KB as [set][tile][group][lane] vectors and
-// reads back its own set's 8 tiles, so the output layer runs on exactly the
-// accumulators mlp_logit_bf16 would hold: operands, matrix instructions
-// (per tile and set, in K order) and the output are those of
-// mlp_logit_bf16, and the logit is the same bit for bit.
+// ---------------------------------------------------------- bf16 ping-pong
+// The bf16 evaluation of 128 queries by the four wavefronts of a 256-thread
+// workgroup, split by output tiles (wavefront w computes tiles 2w and 2w + 1,
+// neurons 64w..64w + 63, of every layer, streaming only those tiles' weight
+// fragments: two 16-byte loads per lane per K block), with the queries in two
+// groups of 64: group g = sets 2g and 2g + 1 (set s = the 32 queries of
+// wavefront s).  The groups take turns on the matrix cores.  While group 0
+// runs layer k, the wavefront converts group 1's layer k - 1 accumulators
+// into group 1's layer-k operands, bf16(relu(pre + bias)), and while group
+// 1 runs layer k it converts group 0's layer-k accumulators.  Each phase's
+// conversions thus run in the shadow of the other group's matrix
+// instructions instead of between layers.  A barrier separates the phases
+// (2 per layer): a group's LDS operands are rewritten only after every
+// wavefront has read them.
+//
+// The weight fragments stream through a ring of kPPRing K blocks in
+// registers, each slot reloaded with the block kPPRing ahead as soon as its
+// matrix instructions are issued; the ring runs on into the next phase and,
+// after the last, into the next call's layer 1, so a call starts with its
+// weights loaded.  Biases and output weights are staged in LDS
+// (stage_bias_wout), so the matrix loop issues no vector memory load but the
+// weight refills.  At most 128 accumulator and 128 other registers per lane
+// let two workgroups share a compute unit: one's matrix instructions run
+// while the other converts, waits at a barrier or computes the output.
+//
+// The output layer sums, per wavefront, its 64 neurons for each set (group
+// 0's in the shadow of group 1's last layer); the four partial sums then add
+// in wavefront order, y = ((y_0 + y_1) + y_2) + y_3, followed by the output
+// bias, out_scale and the sdf term as in mlp_finish.
 //
 // All four wavefronts of the workgroup must call it together, for the same
-// field (depth + 2 barriers per call); `lds` is the workgroup's
-// kSplitLdsBytes and `wave` the wavefront's index in the workgroup.
-constexpr int kSplitBufBytes = 4 * kHiddenBlocksBF16 * 64 * 16;  // 64 KB
-constexpr int kSplitLdsBytes = 2 * kSplitBufBytes;
-static_assert(4 * 8 * 4 * 64 * 16 == kSplitLdsBytes, "the output park fills both buffers");
+// field (2 depth + 2 barriers per call); `lds` is the workgroup's
+// kPPLdsBytes with the field staged at kPPBiasOff, `wave` the wavefront's
+// index in the workgroup.
+constexpr int kPPOpBytes = 2 * kHiddenBlocksBF16 * 64 * 16;  // one group's operands: 32 KB
+constexpr int kPPPartOff = 2 * kPPOpBytes;                   // [set][wave][32] floats
+constexpr int kPPBiasOff = kPPPartOff + 4 * 4 * 32 * 4;      // depth x 256 biases, then w_out
+constexpr int kPPLdsBytes = kPPBiasOff + (kMaxDepth + 1) * kWidth * 4;
+constexpr int kB1 = kMaxGroups1BF16 * kPrefetchBF16;  // layer-1 K blocks
+static_assert(kb1_bf16(3) == kB1 && kb1_bf16(kMaxInDim) == kB1, "one layer-1 block count");
 
-__device__ __forceinline__ float mlp_logit_bf16_split(const Mlp& M, const float x[3],
-                                                      char* __restrict__ lds, int wave) {
-  const int lane = lane_id();
-  const int h = lane >> 5;
-  int zero = 0;  // keeps the stream prologue here (see mlp_logit_fp32)
-  asm volatile("" : "+v"(zero));
-  v8bf* bufA = reinterpret_cast<v8bf*>(lds);
-  v8bf* bufB = reinterpret_cast<v8bf*>(lds + kSplitBufBytes);
-  auto op = [&](v8bf* buf, int set, int b) -> v8bf* {
-    return buf + (set * kHiddenBlocksBF16 + b) * 64 + lane;
-  };
-  const __amdgpu_buffer_rsrc_t ws = weight_stream(
-      M.w1b, ((size_t)M.kb1b + (size_t)(M.depth - 1) * kHiddenBlocksBF16 + kPrefetchBF16) * 8192);
-  const int voff = (lane + zero) * 16;
-  // tile 2 wave + j of K block b of the stream
-  auto S = [&](int b, int j) -> v8bf {
+// Copies the field's biases (depth x 256) and output weights (256) to dst
+// (LDS); all 256 threads call it, then a barrier before they are read.
+__device__ __forceinline__ void stage_bias_wout(const Mlp& M, char* dst_bytes) {
+  v4f* dst = reinterpret_cast<v4f*>(dst_bytes);
+  const ODC_GLOBAL v4f* Bsrc = (const ODC_GLOBAL v4f*)gmem(M.bias);
+  const ODC_GLOBAL v4f* Wsrc = (const ODC_GLOBAL v4f*)gmem(M.wout);
+  const int nb = M.depth * 64;
+  for (int i = (int)threadIdx.x; i < nb + 64; i += 256) dst[i] = i < nb ? Bsrc[i] : Wsrc[i - nb];
+}
+
+// The weight stream of the ping-pong evaluation: tile 2 wave + j of stream
+// block b (layer 1's kB1 blocks, then each hidden layer's NB; blocks past the
+// end read as zero).
+struct PPStream {
+  __amdgpu_buffer_rsrc_t ws;
+  int voff, wave;
+  __device__ __forceinline__ PPStream(const Mlp& M, int wave_) : wave(wave_) {
+    ws = weight_stream(M.w1b, ((size_t)kB1 + (size_t)(M.depth - 1) * kHiddenBlocksBF16 +
+                               kPrefetchBF16) * 8192);
+    voff = lane_id() * 16;
+  }
+  __device__ __forceinline__ v8bf operator()(int b, int j) const {
     return __builtin_bit_cast(
         v8bf, __builtin_amdgcn_raw_buffer_load_b128(ws, voff, (b * 8 + 2 * wave + j) * 1024, 0));
+  }
+};
+constexpr int kPPRing = 4;  // weight ring slots (K blocks)
+
+// Loads the ring for a call's first phase: layer 1's blocks.
+__device__ __forceinline__ void pp_prime(const PPStream& S, v8bf (&W)[kPPRing][2]) {
+#pragma unroll
+  for (int b = 0; b < kPPRing; ++b)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) W[b][j] = S(b, j);
+}
+
+// W: the weight ring, loaded by pp_prime before the first call for a field;
+// each call leaves it loaded for the next.
+__device__ __forceinline__ float mlp_logit_bf16_pp(const Mlp& M, const float x[3],
+                                                   char* __restrict__ lds, int wave,
+                                                   const PPStream& S, v8bf (&W)[kPPRing][2]) {
+  const int lane = lane_id();
+  const int h = lane >> 5;
+  constexpr int NB = kHiddenBlocksBF16;
+  static_assert(kB1 == kPPRing, "layer 1 fills the ring exactly");
+  // operand vector of set s (0, 1) of group g, K block b
+  auto op = [&](int g, int s, int b) -> v8bf* {
+    return reinterpret_cast<v8bf*>(lds + g * kPPOpBytes) + (s * NB + b) * 64 + lane;
   };
-  v8bf wr[kPrefetchBF16][2];
-#pragma unroll
-  for (int d = 0; d < kPrefetchBF16; ++d)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) wr[d][j] = S(d, j);
+  float* const part = reinterpret_cast<float*>(lds + kPPPartOff);
+  const v4f* const bias4 = reinterpret_cast<const v4f*>(lds + kPPBiasOff) + h;
   // layer-1 operands of this wavefront's queries (set = wave)
-  const float quarter_h = h ? 0.25f : 0.0f;
+  {
+    const float quarter_h = h ? 0.25f : 0.0f;
 #pragma unroll
-  for (int b = 0; b < kMaxGroups1BF16 * kPrefetchBF16; ++b) {
-    if (b < M.kb1b) {
+    for (int b = 0; b < kB1; ++b) {
       typedef uint32_t v4u __attribute__((ext_vector_type(4)));
       v4u p;
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         p[j] = pack_bf16(pair_feature_fast(8 * b + 2 * j, quarter_h, h, x),
                          pair_feature_fast(8 * b + 2 * j + 1, quarter_h, h, x));
-      *op(bufA, wave, b) = __builtin_bit_cast(v8bf, p);
+      *op(wave >> 1, wave & 1, b) = __builtin_bit_cast(v8bf, p);
     }
   }
   lds_block_sync();
   const v16f zacc = {};
-  v16f acc[4][2];
-  // one K block of the stream: eight matrix instructions (4 sets x 2 tiles)
-  // with the weight slot d, the next block's operands read ahead
-  v8bf bo[4], bn[4];
-  auto kblock = [&](v8bf* in, int b, int nb, int d, bool first) {
-#pragma unroll
-    for (int set = 0; set < 4; ++set) bn[set] = *op(in, set, nb);
-#pragma unroll
-    for (int set = 0; set < 4; ++set)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-        acc[set][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[d][j], bo[set],
-                                                              first ? zacc : acc[set][j], 0, 0, 0);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int j = 0; j < 2; ++j) wr[d][j] = S(b + kPrefetchBF16, j);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int set = 0; set < 4; ++set) bo[set] = bn[set];
+  v16f acc[4][2];  // [set][tile]
+  float ps[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  // Side work k (0..7) done in the shadow of the other group's phase: operand
+  // vector k of group g for the next layer (side 1, layer bias lb), or a
+  // slice of group g's output sums (side 2).  Its two bias (or bias and
+  // output weight) vectors are read from LDS before the block's matrix
+  // instructions and used after them.
+  struct SideIn {
+    v4f t0, t1;
   };
-  // layer 1
-  const int ng = M.kb1b / kPrefetchBF16;
-#pragma unroll
-  for (int set = 0; set < 4; ++set) bo[set] = *op(bufA, set, 0);
-#pragma unroll
-  for (int gi = 0; gi < kMaxGroups1BF16; ++gi) {
-    if (gi == 0 || gi < ng) {
-#pragma unroll
-      for (int d = 0; d < kPrefetchBF16; ++d) {
-        const int b = gi * kPrefetchBF16 + d;
-        kblock(bufA, b, b + 1 < M.kb1b ? b + 1 : b, d, b == 0);
-      }
+  auto side_load = [&](auto side_c, int k, int lb) __attribute__((always_inline)) -> SideIn {
+    constexpr int side = decltype(side_c)::value;
+    SideIn r{};
+    if constexpr (side == 1) {
+      const int j = (k >> 1) & 1, beta = k & 1;
+      const int b = 2 * (2 * wave + j) + beta;
+      const v4f* Bl = bias4 + lb * 64;
+      r.t0 = Bl[4 * b];
+      r.t1 = Bl[4 * b + 2];
+    } else if constexpr (side == 2) {
+      const int G = 4 * (2 * wave + (k >> 2)) + (k & 3);
+      r.t0 = bias4[(M.depth - 1) * 64 + 2 * G];
+      r.t1 = bias4[M.depth * 64 + 2 * G];
     }
-  }
-  // hidden layers: this wavefront's share of layer l's operands from its
-  // accumulators and layer l - 1's bias, one barrier, layer l
-  const ODC_GLOBAL v4f* Bg = (const ODC_GLOBAL v4f*)gmem(M.bias) + h + zero;
-  v8bf* in = bufA;
-  v8bf* out = bufB;
-  for (int l = 1; l < M.depth; ++l) {
-    const ODC_GLOBAL v4f* Bl = Bg + (size_t)(l - 1) * 64;
+    return r;
+  };
+  auto side_run = [&](auto side_c, auto g_c, int k, const SideIn& in)
+      __attribute__((always_inline)) {
+    constexpr int side = decltype(side_c)::value;
+    constexpr int g = decltype(g_c)::value;
+    if constexpr (side == 1) {
+      const int s = k >> 2, j = (k >> 1) & 1, beta = k & 1;
+      const int b = 2 * (2 * wave + j) + beta;
+      const v16f& a = acc[2 * g + s][j];
+      const v4f a0 = {a[8 * beta], a[8 * beta + 1], a[8 * beta + 2], a[8 * beta + 3]};
+      const v4f a1 = {a[8 * beta + 4], a[8 * beta + 5], a[8 * beta + 6], a[8 * beta + 7]};
+      *op(g, s, b) = bf16_operand(a0, a1, in.t0, in.t1);
+    } else if constexpr (side == 2) {
+      const int j = k >> 2, gq = k & 3;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int T = 2 * wave + j;
+      for (int s = 0; s < 2; ++s)
 #pragma unroll
-      for (int beta = 0; beta < 2; ++beta) {
-        const int b = 2 * T + beta;
-        const v4f t0 = Bl[4 * b], t1 = Bl[4 * b + 2];
-#pragma unroll
-        for (int set = 0; set < 4; ++set) {
-          const v16f& a = acc[set][j];
-          const v4f a0 = {a[8 * beta], a[8 * beta + 1], a[8 * beta + 2], a[8 * beta + 3]};
-          const v4f a1 = {a[8 * beta + 4], a[8 * beta + 5], a[8 * beta + 6], a[8 * beta + 7]};
-          *op(out, set, b) = bf16_operand(a0, a1, t0, t1);
-        }
-      }
+        for (int d = 0; d < 4; ++d)
+          ps[2 * g + s] = __builtin_fmaf(
+              in.t1[d], fmaxf(acc[2 * g + s][j][4 * gq + d] + in.t0[d], 0.0f), ps[2 * g + s]);
     }
+  };
+  using G0 = std::integral_constant<int, 0>;
+  using G1 = std::integral_constant<int, 1>;
+  using Side0 = std::integral_constant<int, 0>;
+  using Side1 = std::integral_constant<int, 1>;
+  using Side2 = std::integral_constant<int, 2>;
+  // one phase: group g's matrix work over the nblk blocks of stream blocks
+  // rb.., each block's operands read one block ahead, and side work for the
+  // other group.  After block b's matrix instructions its slot is reloaded
+  // with the block kPPRing ahead: of this phase while there is one, then of
+  // the next phase (stream blocks rn..).
+  auto phase = [&](auto g_c, auto nblk_c, auto side_c, int rb, int rn, int lb)
+      __attribute__((always_inline)) {
+    constexpr int g = decltype(g_c)::value;
+    constexpr int nblk = decltype(nblk_c)::value;
+    constexpr int side = decltype(side_c)::value;
+    constexpr int per = nblk >= 8 ? 1 : 8 / nblk;  // side slices per block (every other, if 1)
+    using OG = std::integral_constant<int, 1 - g>;
+    v8bf bo[2], bn[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) bo[s] = *op(g, s, 0);
+#pragma unroll
+    for (int b = 0; b < nblk; ++b) {
+      const int nb = b + 1 < nblk ? b + 1 : b;
+      const int d = b % kPPRing;
+      constexpr int nsl = side == 0 ? 0 : per;
+      const bool has = side != 0 && (nblk < 8 || (b & 1) == 0);
+      SideIn in[per];
+      if (has) {
+#pragma unroll
+        for (int i = 0; i < nsl; ++i) in[i] = side_load(side_c, nblk >= 8 ? b >> 1 : b * per + i, lb);
+      }
+#pragma unroll
+      for (int s = 0; s < 2; ++s) bn[s] = *op(g, s, nb);
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[2 * g + s][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              W[d][j], bo[s], b == 0 ? zacc : acc[2 * g + s][j], 0, 0, 0);
+      if (has) {
+#pragma unroll
+        for (int i = 0; i < nsl; ++i)
+          side_run(side_c, OG{}, nblk >= 8 ? b >> 1 : b * per + i, in[i]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      const int sb = b + kPPRing < nblk ? rb + b + kPPRing : rn + b + kPPRing - nblk;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) W[d][j] = S(sb, j);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int s = 0; s < 2; ++s) bo[s] = bn[s];
+    }
+  };
+  using L1 = std::integral_constant<int, kB1>;
+  using LH = std::integral_constant<int, NB>;
+  const int D = M.depth;
+  // stream block of hidden layer k's first block (k >= 1)
+  auto hb = [&](int k) { return kB1 + (k - 1) * NB; };
+  // layer 1 (k = 0); the last phase reloads the ring with layer 1 for the
+  // next call
+  phase(G0{}, L1{}, Side0{}, 0, 0, 0);
+  lds_block_sync();
+  if (D > 1) phase(G1{}, L1{}, Side1{}, 0, hb(1), 0);
+  else phase(G1{}, L1{}, Side2{}, 0, 0, 0);
+  lds_block_sync();
+  for (int k = 1; k < D; ++k) {
+    phase(G0{}, LH{}, Side1{}, hb(k), hb(k), k - 1);
     lds_block_sync();
-    const int base = M.kb1b + (l - 1) * kHiddenBlocksBF16;
-#pragma unroll
-    for (int set = 0; set < 4; ++set) bo[set] = *op(out, set, 0);
-#pragma unroll
-    for (int b0 = 0; b0 < kHiddenBlocksBF16; b0 += kPrefetchBF16) {
-#pragma unroll
-      for (int d = 0; d < kPrefetchBF16; ++d) {
-        const int b = b0 + d;
-        kblock(out, base + b, (b + 1) & (kHiddenBlocksBF16 - 1), d, b == 0);
-      }
-    }
-    v8bf* t = in;
-    in = out;
-    out = t;
+    if (k + 1 < D) phase(G1{}, LH{}, Side1{}, hb(k), hb(k + 1), k);
+    else phase(G1{}, LH{}, Side2{}, hb(k), 0, k);
+    lds_block_sync();
   }
-  // every wavefront's reads of the last operands are done before the park
+#pragma unroll
+  for (int k = 0; k < 8; ++k) side_run(Side2{}, G1{}, k, side_load(Side2{}, k, 0));
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const float t = ps[s] + __shfl_xor(ps[s], 32);
+    if (h == 0) part[(s * 4 + wave) * 32 + lane] = t;
+  }
   lds_block_sync();
-  v4f* park = reinterpret_cast<v4f*>(lds);  // [set][tile][group][lane]
-#pragma unroll
-  for (int set = 0; set < 4; ++set)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int g = 0; g < 4; ++g)
-        park[((set * 8 + 2 * wave + j) * 4 + g) * 64 + lane] =
-            (v4f){acc[set][j][4 * g], acc[set][j][4 * g + 1], acc[set][j][4 * g + 2],
-                  acc[set][j][4 * g + 3]};
-  lds_block_sync();
-  v16f mine[8];
-#pragma unroll
-  for (int T = 0; T < 8; ++T)
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const v4f v = park[((wave * 8 + T) * 4 + g) * 64 + lane];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) mine[T][4 * g + e] = v[e];
-    }
-  return mlp_output(M, mine, h, zero, x);
+  const float* pp = part + wave * 4 * 32 + (lane & 31);
+  const float y = ((pp[0] + pp[32]) + pp[64]) + pp[96];
+  return mlp_finish(M, h ? 0.0f : y, x);
 }
 
 // ---------------------------------------------------------- split bf16
@@ -763,11 +743,7 @@ constexpr int kX3Ring = 2;  // weight ring depth in K blocks (each ~1500 matrix 
 // Stages the field's biases and output weights in the workgroup's LDS; all
 // 256 threads call it, then a barrier, before x3 evaluations of the field.
 __device__ __forceinline__ void x3_stage(const Mlp& M, char* lds) {
-  v4f* dst = reinterpret_cast<v4f*>(lds + kX3BiasOff);
-  const ODC_GLOBAL v4f* Bsrc = (const ODC_GLOBAL v4f*)gmem(M.bias);
-  const ODC_GLOBAL v4f* Wsrc = (const ODC_GLOBAL v4f*)gmem(M.wout);
-  const int nb = M.depth * 64;
-  for (int i = (int)threadIdx.x; i < nb + 64; i += 256) dst[i] = i < nb ? Bsrc[i] : Wsrc[i - nb];
+  stage_bias_wout(M, lds + kX3BiasOff);
 }
 
 // Eight binary32 values to the three bf16 terms of each (exact split).
