@@ -7,7 +7,8 @@ bf16-guarded precision.  One step = one full extraction (stages a-e, all
 occupancy queries included) of that field with its inputs resident in HBM.
 Metric: active cells meshed per second.
 
-Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+Prints one JSON line (--jsonl PATH also appends it, after per-step records,
+to a JSONL file).  --gpus above 1 is refused: this build runs on one GPU.
 Besides the timed steps, the line carries (all outside the timed region):
 the dominant kernel's roofline; the plain fp32 path's throughput on the same
 grid and whether its mesh equals the guarded path's (fp32_path); the same
@@ -23,7 +24,9 @@ Other modes (not run by default):
   --mode batch  64 seeded shapes (32 CSG, 32 MLP fields; res uniform over
                 {64, 96, 128, 192, 256}) meshed as one batch per step,
                 graph-replayed with the autotuned launch shape; reported with
-                the same shapes meshed one at a time on the plain fp32 path.
+                the same batch under the default launch shape (the
+                autotuner's gain) and the same shapes meshed one at a time
+                on the plain fp32 path.
   --mode copy   a plain device-to-device copy of --copy-mib MiB, repeated
                 --steps times: the reference kernel that scales the HBM byte
                 counters (FETCH_SIZE, WRITE_SIZE) of a profile.
@@ -176,6 +179,18 @@ def mesh_quality(ctx, df, grid, samples: int = 1000000, params=None) -> dict:
             "closed_manifold": bool(ok), "samples": samples}
 
 
+def emit(out: dict, args, records=()) -> None:
+    """Prints the result line; with --jsonl, also appends it (after any
+    per-step records) to that file, one JSON object per line."""
+    line = json.dumps(out)
+    print(line, flush=True)
+    if getattr(args, "jsonl", None):
+        with open(args.jsonl, "a") as fh:
+            for r in records:
+                fh.write(json.dumps(r) + "\n")
+            fh.write(line + "\n")
+
+
 def _batch_mode(args):
     """64 shapes per step in one batched, graph-replayed launch."""
     import torch
@@ -187,20 +202,25 @@ def _batch_mode(args):
     ps = [odc.default_params(g, prec if f.kind == odc.FIELD_MLP else odc.PREC_FP32)
           for f, g in cfgs]
     ctx = odc.Context(0)
-    # autotune on the largest MLP shape of the batch
+    ctx.set_graph(True)
+    caps = [(max(4096, 10 * g.res * g.res), max(8192, 20 * g.res * g.res)) for _, g in cfgs]
+
+    def timed_batch():
+        for _ in range(args.warmup):
+            ctx.extract_batch(dfs, ps, caps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            res = ctx.extract_batch(dfs, ps, caps)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / args.steps, res
+
+    # the default launch shape, then autotuned on the largest MLP shape
+    ms_default, _ = timed_batch()
     big = max((k for k in range(len(cfgs)) if cfgs[k][0].kind == odc.FIELD_MLP),
               key=lambda k: cfgs[k][1].res)
     chosen = ctx.autotune(dfs[big], ps[big])
-    ctx.set_graph(True)
-    caps = [(max(4096, 10 * g.res * g.res), max(8192, 20 * g.res * g.res)) for _, g in cfgs]
-    for _ in range(args.warmup):
-        out = ctx.extract_batch(dfs, ps, caps)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        out = ctx.extract_batch(dfs, ps, caps)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms, out = timed_batch()
     cells = sum(o["n_active_cells"] for o in out)
     # the same shapes one at a time, plain fp32 path, default launch shape
     ref = odc.Context(0)
@@ -225,14 +245,16 @@ def _batch_mode(args):
                    "res": [g.res for _, g in cfgs], "precision_mlp": args.precision,
                    "launch_blocks": list(chosen), "graph": True},
         "active_cells": cells,
+        "default_launch_shape": {"value": cells / (ms_default / 1e3), "unit": "cells/s",
+                                 "ms_per_step": ms_default},
         "sequential_fp32": {"value": cells / (ms32 / 1e3), "unit": "cells/s", "ms": ms32},
     }
-    print(json.dumps(out), flush=True)
+    emit(out, args)
 
 
 def _serve_mode(args):
     """Poisson request trace through the serving loop."""
-    print(json.dumps(serve_run(args, args.serve_requests, args.serve_warmup_s)), flush=True)
+    emit(serve_run(args, args.serve_requests, args.serve_warmup_s), args)
 
 
 def serve_run(args, n_requests: int, warm_s: float) -> dict:
@@ -401,7 +423,7 @@ def _ablation_mode(args):
         print(f"# {name}: {ms:.1f} ms, {'|psi|' if sdf else '|phi-1/2|'} {fit:.3e}, SI pairs {si}, "
               f"V {counts['n_vertices']}, "
               f"T {counts['n_triangles']}, manifold {ok}", file=sys.stderr, flush=True)
-    print(json.dumps({
+    emit({
         "metric": f"Table 3 ablation rows on the {args.res}^3 MLP "
                   f"{'signed-distance' if sdf else 'occupancy'} field", "n_gpus": 1,
         "dtype": DTYPE[args.precision], "data": "synthetic",
@@ -411,7 +433,7 @@ def _ablation_mode(args):
                    "fit": ("mean |psi| = mean |z| at area-uniform mesh samples" if sdf else
                            "mean |phi - 1/2| = mean |tanh(z/2)|/2 at area-uniform mesh samples"),
                    "self_intersections": "pairs of vertex-disjoint triangles that intersect"},
-        "rows": rows}), flush=True)
+        "rows": rows}, args)
 
 
 def _copy_mode(args):
@@ -425,8 +447,8 @@ def _copy_mode(args):
         y.copy_(x)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
-    print(json.dumps({"mode": "copy", "bytes_read": n, "bytes_written": n, "copies": args.steps,
-                      "GB_per_s": 2 * n / dt / 1e9}), flush=True)
+    emit({"mode": "copy", "bytes_read": n, "bytes_written": n, "copies": args.steps,
+          "GB_per_s": 2 * n / dt / 1e9}, args)
 
 
 COUNT_KEYS = ("n_active_cells", "n_active_edges", "n_pairs", "n_vertices", "n_triangles",
@@ -529,6 +551,8 @@ def main():
                     help="requests of the Poisson trace served after the timed steps (0: none)")
     ap.add_argument("--serve-warmup-default-s", type=float, default=3.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--jsonl", default=None,
+                    help="also append the result (and per-step records) to this JSONL file")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build meshes on one GPU only; run with --gpus 1"}))
@@ -616,7 +640,8 @@ def main():
         out["cpu_baseline"] = cb
         if cham is not None:
             out["chamfer_vs_oracle"] = cham
-    print(json.dumps(out), flush=True)
+    emit(out, args, [{"step": i, "ms": t, "workload": out["config"]["workload"]}
+                     for i, t in enumerate(step_ms)])
 
 
 if __name__ == "__main__":

@@ -258,13 +258,22 @@ int32_t odc_mesh_sync_batch(odc_context* ctx, int32_t n, odc_mesh_counts* counts
 int32_t odc_context_set_graph(odc_context* ctx, int32_t enable);
 
 /* Autotuner: times the extraction of `field` under candidate persistent grid
- * sizes (grid-wide passes, per-element passes, matrix-core passes), keeps the
- * fastest of each for this context and writes them to chosen[3] (may be
- * NULL).  Synchronous. */
+ * sizes (grid-wide passes, per-element passes, matrix-core passes) and
+ * writes the fastest of each to chosen[3] (may be NULL).  The result is
+ * cached per (field kind, resolution bucket: res <= 64, <= 128, <= 256,
+ * above) and becomes the context's default: an extraction or batch uses the
+ * cached entry of its dominant job (the largest MLP job, else the largest
+ * job), else the default.  Synchronous. */
 int32_t odc_autotune(odc_context* ctx, const odc_field* field, const odc_params* params,
                      int32_t* chosen);
-/* Sets the three grid sizes (blocks of 256 threads) directly. */
+/* Sets the three grid sizes (blocks of 256 threads) directly as the default
+ * and clears the autotuner's cache. */
 int32_t odc_set_launch_config(odc_context* ctx, const int32_t* grid_elem_mlp_blocks);
+/* The grid sizes an extraction whose dominant job has field kind `kind` and
+ * `res` cells per axis would use (cfg3[3]), and whether they come from the
+ * autotuner's cache (*tuned = 1; may be NULL).  Errors: INVALID_ARG. */
+int32_t odc_get_launch_config(const odc_context* ctx, int32_t kind, int32_t res, int32_t* cfg3,
+                              int32_t* tuned);
 
 /* Copies an intermediate array of the last extract (after odc_mesh_sync) into
  * dst (device memory of cap_bytes).  *n receives the element count.

@@ -561,6 +561,23 @@ static bool same_cfg(const LaunchCfg& a, const LaunchCfg& b) {
          a.pack_blocks == b.pack_blocks;
 }
 
+// The launch shape for the n jobs in ctx->hjobs: the autotuned entry of the
+// dominant job's (field kind, resolution bucket) when there is one, else the
+// context's.  The dominant job is the largest MLP job if any (its matrix
+// stages dominate), else the largest job.
+static const LaunchCfg& cfg_for(const odc_context* ctx, int n) {
+  if (ctx->tuning || n <= 0) return ctx->cfg;
+  int best = 0;
+  for (int k = 1; k < n; ++k) {
+    const Job& a = ctx->hjobs[k];
+    const Job& b = ctx->hjobs[best];
+    if (a.kind > b.kind || (a.kind == b.kind && a.g.N > b.g.N)) best = k;
+  }
+  const Job& J = ctx->hjobs[best];
+  const int kind = J.kind == 1 ? 1 : 0, rb = res_bucket(J.g.N);
+  return ctx->tuned_ok[kind][rb] ? ctx->tuned[kind][rb] : ctx->cfg;
+}
+
 // Uploads the job array and launches the whole path for n jobs: directly, or
 // by replaying a captured graph (the kernels read everything from the job
 // array, so one graph serves every batch of the same size and kinds).
@@ -573,16 +590,17 @@ static int32_t run_batch(odc_context* ctx, int n) {
   HIP_TRY(ctx, hipMemcpyAsync(P<const float*>(ctx->dweights), ctx->hweights,
                               n * sizeof(float*), hipMemcpyHostToDevice, s));
   const PipelineShape sh = shape_of(ctx, n);
+  const LaunchCfg& cfg = cfg_for(ctx, n);
   if (ctx->use_graph && !ctx->timing) {
     const void* ptrs[3] = {ctx->djobs.p, ctx->dweights.p, ctx->table.p};
     const bool reuse = ctx->graph && ctx->graph_njobs == n && same_shape(ctx->graph_shape, sh) &&
-                       same_cfg(ctx->graph_cfg, ctx->cfg) && ptrs[0] == ctx->graph_ptrs[0] &&
+                       same_cfg(ctx->graph_cfg, cfg) && ptrs[0] == ctx->graph_ptrs[0] &&
                        ptrs[1] == ctx->graph_ptrs[1] && ptrs[2] == ctx->graph_ptrs[2];
     if (!reuse) {
       drop_graph(ctx);
       hipGraph_t g = nullptr;
       HIP_TRY(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
-      hipError_t le = launch_pipeline(d, n, sh, dw, P<uint32_t>(ctx->table), ctx->cfg, nullptr,
+      hipError_t le = launch_pipeline(d, n, sh, dw, P<uint32_t>(ctx->table), cfg, nullptr,
                                       ctx->capture_stream);
       hipError_t ce = hipStreamEndCapture(ctx->capture_stream, &g);
       if (le != hipSuccess || ce != hipSuccess)
@@ -596,12 +614,12 @@ static int32_t run_batch(odc_context* ctx, int n) {
       }
       ctx->graph_njobs = n;
       ctx->graph_shape = sh;
-      ctx->graph_cfg = ctx->cfg;
+      ctx->graph_cfg = cfg;
       for (int i = 0; i < 3; ++i) ctx->graph_ptrs[i] = ptrs[i];
     }
     HIP_TRY(ctx, hipGraphLaunch(ctx->graph, s));
   } else {
-    HIP_TRY(ctx, launch_pipeline(d, n, sh, dw, P<uint32_t>(ctx->table), ctx->cfg,
+    HIP_TRY(ctx, launch_pipeline(d, n, sh, dw, P<uint32_t>(ctx->table), cfg,
                                  ctx->timing ? ctx->ev : nullptr, s));
   }
   HIP_TRY(ctx, launch_gather(d, n, P<unsigned long long>(ctx->dgather), s));
@@ -724,7 +742,7 @@ extern "C" int32_t odc_mesh_extract_noalloc(odc_context* ctx, const odc_field* f
                               hipMemcpyHostToDevice, s));
   const PipelineShape sh = shape_of(ctx, 1);
   HIP_TRY(ctx, launch_pipeline(P<Job>(ctx->djobs), 1, sh, P<const float*>(ctx->dweights),
-                               P<uint32_t>(ctx->table), ctx->cfg,
+                               P<uint32_t>(ctx->table), cfg_for(ctx, 1),
                                ctx->timing ? ctx->ev : nullptr, s));
   HIP_TRY(ctx, launch_gather(P<Job>(ctx->djobs), 1, P<unsigned long long>(ctx->dgather), s));
   HIP_TRY(ctx, hipMemcpyAsync(ctx->hgather, P<unsigned long long>(ctx->dgather),
@@ -979,7 +997,9 @@ extern "C" int32_t odc_field_eval(odc_context* ctx, const odc_field* f, int32_t 
 
 // ------------------------------------------------------------- autotuner
 // Picks the persistent grid sizes for one field by timing the stages they
-// drive: grid-wide passes, thread-per-element passes and MLP passes.
+// drive: grid-wide passes, thread-per-element passes and MLP passes.  The
+// result is cached for the field's (kind, resolution bucket) and becomes the
+// context's default.
 extern "C" int32_t odc_autotune(odc_context* ctx, const odc_field* f, const odc_params* p,
                                 int32_t* chosen) {
   if (!ctx || !f || !p) return ODC_ERR_INVALID_ARG;
@@ -988,6 +1008,13 @@ extern "C" int32_t odc_autotune(odc_context* ctx, const odc_field* f, const odc_
   TRY(validate_job(ctx, f, p, &o));
   const bool was_timing = ctx->timing;
   TRY(odc_context_set_timing(ctx, 1));
+  struct Tuning {  // timing candidates in ctx->cfg, bypassing the cache
+    odc_context* c;
+    ~Tuning() { c->tuning = false; }
+  } tuning{ctx};
+  ctx->tuning = true;
+  const int kind = f->kind == ODC_FIELD_MLP ? 1 : 0, rb = res_bucket(p->res);
+  if (ctx->tuned_ok[kind][rb]) ctx->cfg = ctx->tuned[kind][rb];
   auto time_stages = [&](float st[8]) -> int32_t {
     TRY(enqueue_batch(ctx, 1, f, p, &o));
     TRY(finish(ctx));
@@ -1027,6 +1054,8 @@ extern "C" int32_t odc_autotune(odc_context* ctx, const odc_field* f, const odc_
     }
   }
   ctx->cfg = best;
+  ctx->tuned[kind][rb] = best;
+  ctx->tuned_ok[kind][rb] = true;
   if (!was_timing) ctx->timing = false;
   if (chosen) {
     chosen[0] = best.grid_blocks;
@@ -1044,5 +1073,20 @@ extern "C" int32_t odc_set_launch_config(odc_context* ctx, const int32_t* cfg3) 
   ctx->cfg.grid_blocks = cfg3[0];
   ctx->cfg.elem_blocks = cfg3[1];
   ctx->cfg.mlp_blocks = cfg3[2];
+  memset(ctx->tuned_ok, 0, sizeof(ctx->tuned_ok));  // an explicit shape overrides the cache
+  return ODC_OK;
+}
+
+extern "C" int32_t odc_get_launch_config(const odc_context* ctx, int32_t kind, int32_t res,
+                                         int32_t* cfg3, int32_t* tuned) {
+  if (!ctx || !cfg3 || (kind != ODC_FIELD_CSG && kind != ODC_FIELD_MLP) || res < 1)
+    return ODC_ERR_INVALID_ARG;
+  const int rb = res_bucket(res);
+  const bool ok = ctx->tuned_ok[kind][rb];
+  const LaunchCfg& c = ok ? ctx->tuned[kind][rb] : ctx->cfg;
+  cfg3[0] = c.grid_blocks;
+  cfg3[1] = c.elem_blocks;
+  cfg3[2] = c.mlp_blocks;
+  if (tuned) *tuned = ok ? 1 : 0;
   return ODC_OK;
 }

@@ -51,6 +51,11 @@ struct odc_context {
   const float** hweights = nullptr;        // pinned
   unsigned long long* hgather = nullptr;   // pinned, kGatherWords per job
   odc::LaunchCfg cfg;
+  // autotuned launch shapes per (field kind, resolution bucket), filled by
+  // odc_autotune; an extraction uses the entry of its dominant job, else cfg
+  odc::LaunchCfg tuned[2][odc::kResBuckets];
+  bool tuned_ok[2][odc::kResBuckets] = {};
+  bool tuning = false;  // odc_autotune is timing candidates in cfg
   double cap_scale = 1.0;
   bool trace = false;  // record decision traces of the searches
   // the device's fixed scratch array (odc_mesh_extract_noalloc), and whether

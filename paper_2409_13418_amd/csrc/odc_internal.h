@@ -20,6 +20,11 @@ struct LaunchCfg {
   int pack_blocks = 512;
 };
 
+// Resolution buckets of the autotuner's cache: res <= 64, <= 128, <= 256,
+// above.
+constexpr int kResBuckets = 4;
+inline int res_bucket(int res) { return res <= 64 ? 0 : (res <= 128 ? 1 : (res <= 256 ? 2 : 3)); }
+
 // Which kernels a launch needs.
 struct PipelineShape {
   bool any_csg = false, any_mlp = false, any_mlp_fp32 = false, any_mlp_bf16 = false;

@@ -101,7 +101,7 @@ EXPORTS = ("odc_status_string", "odc_last_error", "odc_context_create", "odc_con
            "odc_server_poll", "odc_server_wait", "odc_server_get_stats",
            "odc_server_reset_stats", "odc_count_self_intersections",
            "odc_get_job_intermediate", "odc_context_set_trace", "odc_mesh_extract_noalloc",
-           "odc_plan_scratch", "odc_inject_alloc_failures")
+           "odc_plan_scratch", "odc_inject_alloc_failures", "odc_get_launch_config")
 STAGES = ("labels", "classify", "compact", "bisect", "search2d", "cell_count", "cell_qef", "emit")
 
 _lib = None
@@ -169,6 +169,9 @@ def load(path: str = LIB_PATH):
     L.odc_autotune.restype = C.c_int32
     L.odc_set_launch_config.argtypes = [C.c_void_p, C.POINTER(C.c_int32)]
     L.odc_set_launch_config.restype = C.c_int32
+    L.odc_get_launch_config.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                        C.POINTER(C.c_int32)]
+    L.odc_get_launch_config.restype = C.c_int32
     L.odc_server_create.argtypes = [C.c_void_p, C.POINTER(ServerConfig), C.POINTER(C.c_void_p)]
     L.odc_server_create.restype = C.c_int32
     L.odc_server_destroy.argtypes = [C.c_void_p]
@@ -375,7 +378,8 @@ class Context:
 
     def autotune(self, dfield: DeviceField, params: Params):
         """Times candidate launch shapes on this field; returns the chosen
-        (grid, element, matrix-core) block counts, kept for this context."""
+        (grid, element, matrix-core) block counts, cached for the field's
+        kind and resolution bucket and kept as this context's default."""
         ch = (C.c_int32 * 3)()
         self._check(load().odc_autotune(self.h, C.byref(dfield.c), C.byref(params), ch),
                     "autotune")
@@ -384,6 +388,15 @@ class Context:
     def set_launch_config(self, grid_blocks: int, elem_blocks: int, mlp_blocks: int):
         v = (C.c_int32 * 3)(grid_blocks, elem_blocks, mlp_blocks)
         self._check(load().odc_set_launch_config(self.h, v), "set_launch_config")
+
+    def launch_config(self, kind: int, res: int):
+        """((grid, element, matrix-core) blocks, from_cache) an extraction
+        whose dominant job has this field kind and resolution would use."""
+        v = (C.c_int32 * 3)()
+        t = C.c_int32()
+        self._check(load().odc_get_launch_config(self.h, int(kind), int(res), v, C.byref(t)),
+                    "launch_config")
+        return tuple(v), bool(t.value)
 
     def extract_batch(self, dfields, params_list, caps=None, want_local=False):
         """Meshes several fields in one launch per stage.  Returns a list of

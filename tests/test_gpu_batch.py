@@ -169,6 +169,34 @@ def test_scratch_overflow_reruns(odc):
     ctx.close()
 
 
+def test_autotune_cache_per_kind_and_resolution(odc):
+    """The autotuner's result is cached for the tuned field's kind and
+    resolution bucket; other keys fall back to the context default, and an
+    explicit launch shape clears the cache.  A batch whose dominant job hits
+    the cache meshes exactly as with the default shape."""
+    ctx = odc.Context(0)
+    f = I.mlp_field(3)
+    g = I.unit_grid(48, 15)
+    df = odc.DeviceField(f)
+    p = odc.default_params(g, odc.PREC_BF16_GUARDED)
+    ref = ctx.extract(df, p)["triangles"].cpu().numpy().copy()
+    default, hit = ctx.launch_config(odc.FIELD_MLP, 48)
+    assert not hit
+    ctx.set_launch_config(*default)
+    chosen = ctx.autotune(df, p)
+    assert ctx.launch_config(odc.FIELD_MLP, 48) == (chosen, True)
+    assert ctx.launch_config(odc.FIELD_MLP, 64) == (chosen, True)     # same bucket
+    assert ctx.launch_config(odc.FIELD_MLP, 200)[1] is False
+    assert ctx.launch_config(odc.FIELD_CSG, 48)[1] is False
+    fc, gc = I.csg_random_field(2), I.unit_grid(40, 15)
+    out = ctx.extract_batch([df, odc.DeviceField(fc)],
+                            [p, odc.default_params(gc)])
+    assert np.array_equal(out[0]["triangles"].cpu().numpy(), ref)
+    ctx.set_launch_config(*default)
+    assert ctx.launch_config(odc.FIELD_MLP, 48) == (default, False)
+    ctx.close()
+
+
 def test_autotune_keeps_results(odc):
     f = I.csg_random_field(2)
     g = I.unit_grid(48)
