@@ -13,7 +13,8 @@ Besides the timed steps, the line carries (all outside the timed region):
 the dominant kernel's roofline; the plain fp32 path's throughput on the same
 grid and whether its mesh equals the guarded path's (fp32_path); the same
 with split-bf16 searches (x3_path: corner signs and cells equal to the
-guarded path's, vertices to binary32 rounding of the searches); the paper's
+guarded path's, vertices to binary32 rounding of the searches) and with
+coarse-to-fine corner evaluation (adaptive_path: 4-cell coarse grid); the paper's
 quality measures of the mesh; a short Poisson serving trace through the
 continuous-batching server (serve: p50/p99 latency, cells/s; --serve-requests-
 default requests after --serve-warmup-default-s seconds of arrivals); the
@@ -48,6 +49,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -62,6 +64,7 @@ import odc_inputs as I  # noqa: E402
 MLP_FLOP_PER_QUERY = lambda f: 2 * (f.in_dim * f.width + (f.depth - 1) * f.width * f.width  # noqa: E731
                                     + f.width)
 PEAK_FP32_MFMA = 157.3e12
+ADAPTIVE_STEP = 4
 PEAK_BF16_MFMA = 2.5e15
 
 
@@ -452,8 +455,8 @@ def _copy_mode(args):
 
 
 COUNT_KEYS = ("n_active_cells", "n_active_edges", "n_pairs", "n_vertices", "n_triangles",
-              "n_queries", "n_search2d_queries", "n_search2d_needed", "n_guard_corners",
-              "n_fp64_cells")
+              "n_queries", "n_search2d_queries", "n_search2d_needed", "n_corner_queries",
+              "n_guard_corners", "n_fp64_cells")
 
 
 def _timed(ctx, df, params, steps: int, warmup: int):
@@ -485,17 +488,16 @@ def _timed(ctx, df, params, steps: int, warmup: int):
 def _roofline(odc, field, grid, counts, stages, prec):
     """The dominant stage's kernel against its matrix-core peak, and every
     query stage: algorithmic FLOP = queries the method needs x the network's
-    FLOP per query (corners: all of them, plus the fp32 re-evaluation of the
-    guard band; 1D: k per crossing edge; 2D: the per-pair count with early
-    exits).  bf16-guarded and fp32 searches run on the fp32 matrix peak;
+    FLOP per query (corners: every corner query made, all of them unless the
+    evaluation is coarse to fine, plus the fp32 re-evaluation of the guard
+    band; 1D: k per crossing edge; 2D: the per-pair count with early exits).  bf16-guarded and fp32 searches run on the fp32 matrix peak;
     split-bf16 searches on the bf16 peak, executing six bf16 products per
     binary32-accurate one (reported as the executed fraction)."""
     per_query = MLP_FLOP_PER_QUERY(field)
-    nc = (grid.res + 1) ** 3
     x3 = prec == odc.PREC_BF16_X3
     search_peak = PEAK_BF16_MFMA if x3 else PEAK_FP32_MFMA
     corner_peak = PEAK_FP32_MFMA if prec == odc.PREC_FP32 else PEAK_BF16_MFMA
-    flop = {"labels": nc * per_query,
+    flop = {"labels": counts["n_corner_queries"] * per_query,
             "bisect": counts["n_active_edges"] * grid.iters_1d * per_query,
             "search2d": counts["n_search2d_needed"] * per_query}
     guard = counts["n_guard_corners"] * per_query
@@ -547,6 +549,8 @@ def main():
                     help="timed steps of the plain fp32 path after the guarded path's")
     ap.add_argument("--x3-steps", type=int, default=6,
                     help="timed steps with split-bf16 searches after the guarded path's")
+    ap.add_argument("--adaptive-steps", type=int, default=4,
+                    help="timed steps with coarse-to-fine corner evaluation after the guarded path's")
     ap.add_argument("--serve-requests-default", type=int, default=300,
                     help="requests of the Poisson trace served after the timed steps (0: none)")
     ap.add_argument("--serve-warmup-default-s", type=float, default=3.0)
@@ -605,16 +609,22 @@ def main():
         ref_tris = ref["triangles"].cpu().numpy().copy()
         ref_labels = ctx.intermediate("labels").copy()
         ref_cells = ctx.intermediate("cell_ids").copy()
-        for name, steps in (("fp32", args.fp32_steps), ("x3", args.x3_steps)):
+        for name, steps in (("fp32", args.fp32_steps), ("x3", args.x3_steps),
+                            ("adaptive", args.adaptive_steps)):
             if steps <= 0:
                 continue
-            p2 = odc.default_params(grid, _prec(odc, name))
+            p2 = odc.default_params(grid, _prec(odc, "bf16" if name == "adaptive" else name))
+            if name == "adaptive":
+                # coarse-to-fine corners: 4-cell coarse grid, logit band 1.5 x the
+                # exactness condition for a logit slope of 20 (the sdf gain)
+                p2.coarse_step = ADAPTIVE_STEP
+                p2.coarse_band = 1.5 * 20.0 * math.sqrt(3.0) * ADAPTIVE_STEP / grid.res
             ms2, _, st2, c2 = _timed(ctx, df, p2, steps, 1)
             r2 = ctx.extract(df, p2, want_local=True)
             same_topo = bool(np.array_equal(ctx.intermediate("labels"), ref_labels) and
                              np.array_equal(ctx.intermediate("cell_ids"), ref_cells))
             same = bool(np.array_equal(r2["triangles"].cpu().numpy(), ref_tris))
-            rl, rs = _roofline(odc, field, grid, c2, st2, _prec(odc, name))
+            rl, rs = _roofline(odc, field, grid, c2, st2, p2.precision)
             out[f"{name}_path"] = {
                 "value": c2["n_active_cells"] / (ms2 / 1e3), "unit": "cells/s",
                 "ms_per_step": ms2, "steps": steps, "stages_ms": st2,

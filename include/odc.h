@@ -118,6 +118,26 @@ typedef struct {
                           * and the method leaves them where the QEF puts them (0);
                           * clamping keeps the intersection-free split's envelope
                           * argument valid (fewer self-intersections) */
+  int32_t coarse_step;   /* adaptive corner evaluation (the paper leaves adaptive
+                          * resolution to future work; this is one reading of it, for
+                          * the evaluation only: the mesh stays on the uniform grid).
+                          * 0 or 1: every corner is evaluated.  S in 2..64 (res a
+                          * multiple of S): the field is first evaluated (binary32) on
+                          * the corners of the coarse grid of S x S x S cells; a coarse
+                          * cell is marked when its 8 corners' labels differ or (MLP)
+                          * one of them has |z| < coarse_band; only fine corners in
+                          * marked coarse cells are evaluated (in blocks of 32 to 128
+                          * consecutive corners), every other corner takes the common
+                          * label of its unmarked coarse cell.  Exact, i.e. the same
+                          * labels as S = 0, when no unmarked coarse cell holds a
+                          * label change: for MLP fields whenever coarse_band >=
+                          * L sqrt(3) S h for a bound L on |grad z| (not checked);
+                          * for CSG fields always: a coarse corner is in the band when
+                          * a signed-distance bound of the solid (the primitives'
+                          * exact distances folded with min/max, 1-Lipschitz) is
+                          * below sqrt(3) S h there. */
+  float coarse_band;     /* logit band of the coarse marking (MLP; >= 0, finite; CSG
+                          * fields ignore it) */
 } odc_params;
 
 /* Ablation baselines (Sec. 4 and Table 3): each bit replaces one step of the
@@ -163,7 +183,7 @@ typedef struct {
   int64_t n_flipped_faces; /* ambiguous faces given the manifold-fix pairing */
   int64_t n_fp64_cells;    /* QEF solves redone in binary64 */
   int64_t n_guard_corners; /* bf16 corner queries re-evaluated in fp32 */
-  int64_t n_queries;       /* occupancy queries issued */
+  int64_t n_queries;       /* occupancy queries issued (corners, guard repeats, searches) */
   int64_t n_search2d_queries; /* of which in the 2D searches: analytic fields every query of
                                  each pair's sequence, n_pairs x (1 + lin1 + bin1 +
                                  2 (lin2 + bin2)); MLP fields only the queries each pair
@@ -173,6 +193,9 @@ typedef struct {
                                  the first label change and the halvings; no step-2 rays
                                  when step 1 ends at m).  -1 for analytic fields and
                                  gradient normals (not counted). */
+  int64_t n_corner_queries;   /* corner queries of stage (a): (res + 1)^3, or with
+                                 coarse_step > 1 the coarse corners plus the fine corners
+                                 evaluated (the bf16 guard's repeats not included) */
 } odc_mesh_counts;
 
 /* Status text (static storage). */

@@ -281,6 +281,13 @@ int32_t odc::validate_job(odc_context* ctx, const odc_field* f, const odc_params
     return fail(ctx, ODC_ERR_INVALID_ARG, "SDF input applies to linear 1D points only");
   if (p->clamp_vertices != 0 && p->clamp_vertices != 1)
     return fail(ctx, ODC_ERR_INVALID_ARG, "clamp_vertices must be 0 or 1");
+  if (p->coarse_step < 0 || p->coarse_step > 64 ||
+      (p->coarse_step > 1 && p->res % p->coarse_step != 0))
+    return fail(ctx, ODC_ERR_INVALID_ARG,
+                "coarse_step must be 0, 1, or 2..64 dividing res (%d, res %d)", p->coarse_step,
+                p->res);
+  if (!(p->coarse_band >= 0.0f) || !isfinite(p->coarse_band))
+    return fail(ctx, ODC_ERR_INVALID_ARG, "coarse_band must be finite and >= 0");
   if ((p->ablation & ODC_ABL_GRAD_NORMALS) && f->kind != ODC_FIELD_MLP)
     return fail(ctx, ODC_ERR_UNSUPPORTED, "gradient normals need an MLP field");
   if ((o->cap_vertices > 0 && !o->vertices) || (o->cap_triangles > 0 && !o->triangles) ||
@@ -342,6 +349,13 @@ void job_scalars(Job& J, const odc_field* f, const odc_params* p, int ce) {
   J.fp64_cond = p->fp64_cond;
   J.ablation = p->ablation;
   J.clamp = p->clamp_vertices;
+  J.coarse_step = p->coarse_step > 1 ? p->coarse_step : 0;
+  J.cn = J.coarse_step ? N / J.coarse_step : 0;
+  // CSG: the band is a distance, the coarse cell's diagonal (the condition
+  // under which marking by the distance bound is exact), with a margin
+  J.coarse_band = f->kind == ODC_FIELD_CSG
+                      ? (float)(sqrt(3.0) * J.coarse_step * (p->size / N) * 1.001 + 1e-6)
+                      : p->coarse_band;
   J.nw_c = (J.g.nc + 31) / 32;
   J.nw_e = (3 * J.g.ea + 31) / 32;
   J.nw_f = (3 * J.g.fa + 31) / 32;
@@ -353,7 +367,7 @@ void job_scalars(Job& J, const odc_field* f, const odc_params* p, int ce) {
 
 // Byte sizes of a job's scratch regions (each a multiple of 256).
 struct Layout {
-  size_t grid[13];
+  size_t grid[16];
   size_t active[19];
   size_t grid_total = 0, active_total = 0;
   size_t mlpw = 0, guard = 0, status = 0;
@@ -375,6 +389,10 @@ Layout job_layout(const Job& J, const odc_field* f, bool guard_full, bool trace)
   L.grid[9] = L.grid[10] = align_up((size_t)J.nw_cell * 4);
   L.grid[11] = align_up((size_t)(J.nw_cell + 1) * 4);
   L.grid[12] = align_up((size_t)((nscan + 1023) / 1024 + 2) * 4);
+  // adaptive corner evaluation: coarse corner labels and band bits, marked coarse cells
+  const size_t c1 = J.coarse_step ? (size_t)J.cn + 1 : 0;
+  L.grid[13] = L.grid[14] = align_up((c1 * c1 * c1 + 31) / 32 * 4);
+  L.grid[15] = J.coarse_step ? align_up(((size_t)J.cn * J.cn * J.cn + 63) / 64 * 8) : 0;
   for (size_t x : L.grid) L.grid_total += x;
   const size_t ne = (size_t)J.cap_edges, np = (size_t)J.cap_pairs, nc = (size_t)J.cap_cells;
   const size_t asz[16] = {align_up(ne * 4),          align_up(ne * 4),
@@ -393,7 +411,7 @@ Layout job_layout(const Job& J, const odc_field* f, bool guard_full, bool trace)
   L.active[17] = trace ? align_up(ne * 4) : 0;
   L.active[18] = trace ? align_up(np * 16) : 0;
   L.active_total += L.active[16] + L.active[17] + L.active[18];
-  L.status = align_up(4 * sizeof(unsigned long long));
+  L.status = align_up(5 * sizeof(unsigned long long));
   if (f->kind == ODC_FIELD_MLP) {
     const int kb1f = kb1_fp32(f->in_dim), kb1b = kb1_bf16(f->in_dim), d = f->depth;
     L.n_w1f = (size_t)kb1f * 512;
@@ -417,14 +435,15 @@ Layout job_layout(const Job& J, const odc_field* f, bool guard_full, bool trace)
 // Points the job's arrays into its scratch regions.
 void job_bind(Job& J, const Layout& L, const odc_field* f, char* grid, char* active, char* mlpw,
               char* guard, char* status) {
-  uint32_t** gp[13] = {&J.labels, &J.emask, &J.ecount, &J.eprefix, &J.fact, &J.famb,
-                       &J.fflip, &J.pcount, &J.pprefix, &J.cmask, &J.ccount, &J.cprefix,
-                       &J.scan_tmp};
+  uint32_t** gp[16] = {&J.labels, &J.emask,  &J.ecount,   &J.eprefix, &J.fact,  &J.famb,
+                       &J.fflip,  &J.pcount, &J.pprefix,  &J.cmask,   &J.ccount, &J.cprefix,
+                       &J.scan_tmp, &J.cbits, &J.cnear,   &J.cmark};
   size_t off = 0;
-  for (int i = 0; i < 13; ++i) {
+  for (int i = 0; i < 16; ++i) {
     *gp[i] = (uint32_t*)(grid + off);
     off += L.grid[i];
   }
+  if (!J.coarse_step) J.cbits = J.cnear = J.cmark = nullptr;
   void** ap[19] = {(void**)&J.elist,    (void**)&J.et,    (void**)&J.ecase, (void**)&J.ntri,
                    (void**)&J.n3,       (void**)&J.tprefix, (void**)&J.c3prefix,
                    (void**)&J.quad,     (void**)&J.plist, (void**)&J.pf,    (void**)&J.clist,
@@ -539,6 +558,7 @@ static PipelineShape shape_of(odc_context* ctx, int n) {
   for (int k = 0; k < n; ++k) {
     const Job& J = ctx->hjobs[k];
     if (J.kind == 0) sh.any_csg = true;
+    if (J.coarse_step) sh.any_coarse = true;
     if (J.kind == 1) {
       sh.any_mlp = true;
       if (J.precision == 0) sh.any_mlp_fp32 = true;
@@ -553,7 +573,7 @@ static PipelineShape shape_of(odc_context* ctx, int n) {
 static bool same_shape(const PipelineShape& a, const PipelineShape& b) {
   return a.any_csg == b.any_csg && a.any_mlp == b.any_mlp && a.any_mlp_fp32 == b.any_mlp_fp32 &&
          a.any_mlp_bf16 == b.any_mlp_bf16 && a.any_mlp_x3 == b.any_mlp_x3 &&
-         a.any_grad == b.any_grad;
+         a.any_grad == b.any_grad && a.any_coarse == b.any_coarse;
 }
 static bool same_cfg(const LaunchCfg& a, const LaunchCfg& b) {
   return a.grid_blocks == b.grid_blocks && a.elem_blocks == b.elem_blocks &&
@@ -825,7 +845,8 @@ void odc::fill_counts(const odc_context* ctx, int k, odc_mesh_counts* c) {
   const bool grad = (J.ablation & kAblGradNormals) != 0;
   c->n_search2d_needed = (J.kind == 1 && !grad) ? (int64_t)o[8] : -1;
   c->n_search2d_queries = grad ? 0 : (J.kind == 1 ? (int64_t)o[8] : c->n_pairs * per_pair);
-  c->n_queries = (int64_t)J.g.nc + c->n_guard_corners +
+  c->n_corner_queries = J.coarse_step ? (int64_t)o[9] : (int64_t)J.g.nc;
+  c->n_queries = c->n_corner_queries + c->n_guard_corners +
                  c->n_active_edges * ((J.ablation & kAblLinear1D) ? 2 : J.iters_1d) +
                  c->n_search2d_queries;
   c->n_flipped_faces = -1;

@@ -150,6 +150,45 @@ __device__ __forceinline__ int csg_inside(const float* __restrict__ prims, int n
   return acc;
 }
 
+// A signed-distance bound of the CSG solid (negative inside): exact distances
+// of the primitives (rotation rows orthonormal; a half-space's normal
+// normalised), folded with min (union), max(a, -b) (subtract) and max
+// (intersect).  The fold is 1-Lipschitz and its sign is the solid's label
+// away from rounding, so where the labels of two points differ, each lies
+// within their distance of a zero of it: |d| at a point bounds how close a
+// label change can be.  Used only to mark coarse cells (adaptive corner
+// evaluation); labels always come from csg_inside.
+__device__ __forceinline__ float prim_distance(const float* __restrict__ p, const float x[3]) {
+  const int type = (int)p[1];
+  const float dx = x[0] - p[2], dy = x[1] - p[3], dz = x[2] - p[4];
+  if (type == 0) return sqrtf(dx * dx + dy * dy + dz * dz) - p[5];
+  if (type == 1) {
+    float out2 = 0.0f, inmax = -INFINITY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float l = p[8 + 3 * a] * dx + p[9 + 3 * a] * dy + p[10 + 3 * a] * dz;
+      const float e = fabsf(l) - p[5 + a];
+      out2 += e > 0.0f ? e * e : 0.0f;
+      inmax = fmaxf(inmax, e);
+    }
+    return sqrtf(out2) + fminf(inmax, 0.0f);
+  }
+  const float nn = sqrtf(p[5] * p[5] + p[6] * p[6] + p[7] * p[7]);
+  return (p[5] * dx + p[6] * dy + p[7] * dz) / nn;
+}
+
+__device__ __forceinline__ float csg_distance(const float* __restrict__ prims, int n,
+                                              const float x[3]) {
+  float acc = prim_distance(prims, x);
+  for (int i = 1; i < n; ++i) {
+    const float* p = prims + kPrimFloats * i;
+    const int op = (int)p[0];
+    const float b = prim_distance(p, x);
+    acc = op == 0 ? fminf(acc, b) : (op == 1 ? fmaxf(acc, -b) : fmaxf(acc, b));
+  }
+  return acc;
+}
+
 // --------------------------------------------------------- faces / cubes
 // face-local corner lc = bu + 2 bv; face-local edges
 // 0: lc0-lc1 (v=0), 1: lc2-lc3 (v=1), 2: lc0-lc2 (u=0), 3: lc1-lc3 (u=1)

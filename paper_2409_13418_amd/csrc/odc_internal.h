@@ -30,6 +30,7 @@ struct PipelineShape {
   bool any_csg = false, any_mlp = false, any_mlp_fp32 = false, any_mlp_bf16 = false;
   bool any_mlp_x3 = false;  // split-bf16 precision
   bool any_grad = false;  // some job takes gradient normals
+  bool any_coarse = false;  // some job evaluates its corners coarse to fine
 };
 
 // The whole path for njobs jobs in device memory; ev (9 events, or NULL)
@@ -39,8 +40,8 @@ hipError_t launch_pipeline(const Job* d, int njobs, const PipelineShape& sh,
                            const LaunchCfg& cfg, hipEvent_t* ev, hipStream_t s);
 // kGatherWords x uint64 per job: edges, pairs, cells, partition vertices,
 // triangles, case-3 vertices, guard corners, fp64 cells | overflow << 32,
-// 2D-search queries made (MLP)
-constexpr int kGatherWords = 9;
+// 2D-search queries made (MLP), corner queries (adaptive evaluation)
+constexpr int kGatherWords = 10;
 hipError_t launch_gather(const Job* d, int njobs, unsigned long long* out, hipStream_t s);
 hipError_t launch_eval(const Job* d_job, const Job& h_job, const float* const* d_weights,
                        int precision, const float* xyz, int n, float* z, const LaunchCfg& cfg,

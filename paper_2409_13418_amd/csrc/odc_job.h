@@ -35,6 +35,14 @@ struct Job {
   double fp64_cond;
   int ablation;   // ODC_ABL_* bits (0 = the method)
   int clamp;      // clamp 3D points into their cells
+  // adaptive corner evaluation (coarse_step > 1): coarse grid of cn cells per
+  // axis (cn + 1 corners); bit sets of the coarse corners' labels, of those
+  // within the logit band, and of the marked coarse cells
+  int coarse_step, cn;
+  float coarse_band;
+  uint32_t* cbits;
+  uint32_t* cnear;
+  uint32_t* cmark;
 
   int nw_c, nw_e, nw_f, nw_cell;       // words of the corner / edge / face / cell bit sets
   int cap_edges, cap_pairs, cap_cells;  // active-set scratch capacities
@@ -86,7 +94,8 @@ struct Job {
   float* out_vloc;
   int* out_vref;
 
-  // [0] guard corners, [1] fp64 cells, [2] overflow
+  // [0] guard corners, [1] fp64 cells, [2] overflow, [3] 2D-search queries,
+  // [4] corner queries (adaptive evaluation)
   unsigned long long* status;
   uint32_t* guard_list;
   int guard_cap;

@@ -316,6 +316,7 @@ __global__ void k_clear_status(const Job* __restrict__ jobs, int njobs) {
     jobs[k].status[1] = 0;
     jobs[k].status[2] = 0;
     jobs[k].status[3] = 0;
+    jobs[k].status[4] = 0;
   }
 }
 
@@ -335,7 +336,102 @@ __global__ void k_gather(const Job* __restrict__ jobs, int njobs,
     o[6] = J.status[0];
     o[7] = J.status[1] | (J.status[2] << 32);
     o[8] = J.status[3];
+    o[9] = J.status[4];
   }
+}
+
+// ------------------------------------------- (a) adaptive corner evaluation
+// With coarse_step S > 1 the field is first evaluated on the corners of the
+// coarse grid (every S-th fine corner per axis), a coarse cell is marked when
+// its corners' labels differ or one lies within the logit band, and the fine
+// corner passes evaluate only corners of marked cells (whole units of 32 to
+// 128 corners); every other corner takes its unmarked coarse cell's common
+// label.
+
+__device__ __forceinline__ int coarse_corners(const Job& J) {
+  return (J.cn + 1) * (J.cn + 1) * (J.cn + 1);
+}
+
+// Binary32 labels of the coarse corners, 32 per wavefront, and whether each
+// lies within the band: |z| < coarse_band for MLP fields, a CSG distance
+// bound below the coarse cell's diagonal for CSG fields.
+__global__ __launch_bounds__(256) void k_coarse_labels(const Job* __restrict__ jobs, int njobs) {
+  __shared__ __align__(16) float act_lds[kBlock / 64][kActWords];
+  float* act = act_lds[threadIdx.x >> 6];
+  for_units(jobs, njobs, gwave(), nwaves(),
+            [](const Job& J) { return J.coarse_step ? (coarse_corners(J) + 31) >> 5 : 0; },
+            [&](const Job& J, int t) {
+              const int ncc = coarse_corners(J), c1 = J.cn + 1, S = J.coarse_step;
+              const int lane = lane_id();
+              const int q = t * 32 + (lane & 31);
+              const bool valid = q < ncc;
+              const int qq = valid ? q : ncc - 1;
+              const float gp[3] = {(float)(S * (qq % c1)), (float)(S * ((qq / c1) % c1)),
+                                   (float)(S * (qq / (c1 * c1)))};
+              float x[3];
+              grid_world(J.g, gp, x);
+              int lab, near = 0;
+              if (J.kind == 0) {
+                lab = csg_inside(J.prims, J.n_prims, x);
+                near = fabsf(csg_distance(J.prims, J.n_prims, x)) < J.coarse_band;
+              } else {
+                const float z = mlp_logit_fp32(J.mlp, x, act);
+                lab = z > 0.0f;
+                near = fabsf(z) < J.coarse_band;
+              }
+              const uint64_t bl = __ballot(valid && lane < 32 && lab);
+              const uint64_t bn = __ballot(valid && lane < 32 && near);
+              if (lane == 0) {
+                J.cbits[t] = (uint32_t)bl;
+                J.cnear[t] = (uint32_t)bn;
+                atomicAdd(&J.status[4], (unsigned long long)min(32, ncc - t * 32));
+              }
+            });
+}
+
+// Marked coarse cells: corners' labels differ, or one is within the band.
+__global__ __launch_bounds__(256) void k_coarse_mark(const Job* __restrict__ jobs, int njobs) {
+  for_units(jobs, njobs, gwave(), nwaves(),
+            [](const Job& J) { return J.coarse_step ? (J.cn * J.cn * J.cn + 63) >> 6 : 0; },
+            [&](const Job& J, int u) {
+              const int cn = J.cn, c1 = cn + 1;
+              const int cell = u * 64 + lane_id();
+              int m = 0;
+              if (cell < cn * cn * cn) {
+                const int i = cell % cn, j = (cell / cn) % cn, k = cell / (cn * cn);
+                int ones = 0, near = 0;
+#pragma unroll
+                for (int d = 0; d < 8; ++d) {
+                  const int q = (i + (d & 1)) + c1 * ((j + ((d >> 1) & 1)) + c1 * (k + (d >> 2)));
+                  ones += bit_of(J.cbits, q);
+                  near |= bit_of(J.cnear, q);
+                }
+                m = (ones != 0 && ones != 8) || near;
+              }
+              const uint64_t b = __ballot(m);
+              const int lane = lane_id();
+              if (lane == 0) J.cmark[2 * u] = (uint32_t)b;
+              if (lane == 32) J.cmark[2 * u + 1] = (uint32_t)(b >> 32);
+            });
+}
+
+// Whether fine corner c lies in a marked coarse cell; else *fill receives
+// the common label of the unmarked coarse cells holding it.
+__device__ __forceinline__ bool corner_needed(const Job& J, int c, int* fill) {
+  const int n1 = J.g.N + 1, S = J.coarse_step, cn = J.cn, c1 = cn + 1;
+  const int p[3] = {c % n1, (c / n1) % n1, c / (n1 * n1)};
+  int lo[3], hi[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = p[a] > 0 ? (p[a] - 1) / S : 0;
+    hi[a] = p[a] / S < cn - 1 ? p[a] / S : cn - 1;
+  }
+  bool need = false;
+  for (int k = lo[2]; k <= hi[2]; ++k)
+    for (int j = lo[1]; j <= hi[1]; ++j)
+      for (int i = lo[0]; i <= hi[0]; ++i) need |= bit_of(J.cmark, i + cn * (j + cn * k)) != 0;
+  *fill = bit_of(J.cbits, lo[0] + c1 * (lo[1] + c1 * lo[2]));
+  return need;
 }
 
 // ------------------------------------------------------------- (a) labels
@@ -347,12 +443,23 @@ __global__ __launch_bounds__(256) void k_labels_csg(const Job* __restrict__ jobs
               const int c = u * 64 + lane_id();
               int lab = 0;
               if (c < g.nc) {
-                const int n1 = g.N + 1;
-                const float gp[3] = {(float)(c % n1), (float)((c / n1) % n1),
-                                     (float)(c / (n1 * n1))};
-                float x[3];
-                grid_world(g, gp, x);
-                lab = csg_inside(J.prims, J.n_prims, x);
+                int fill = 0;
+                const bool need = !J.coarse_step || corner_needed(J, c, &fill);
+                if (need) {
+                  const int n1 = g.N + 1;
+                  const float gp[3] = {(float)(c % n1), (float)((c / n1) % n1),
+                                       (float)(c / (n1 * n1))};
+                  float x[3];
+                  grid_world(g, gp, x);
+                  lab = csg_inside(J.prims, J.n_prims, x);
+                } else {
+                  lab = fill;
+                }
+                if (J.coarse_step) {
+                  const uint64_t ev = __ballot(need);
+                  if (lane_id() == __ffsll((long long)__ballot(1)) - 1)
+                    atomicAdd(&J.status[4], (unsigned long long)__popcll(ev));
+                }
               }
               store_ballot(__ballot(lab), u * 64, J.nw_c, J.labels);
             });
@@ -398,6 +505,24 @@ __global__ __launch_bounds__(256, BF16 ? 2 : 1) void k_labels_mlp(const Job* __r
       }
     }
   };
+  // Adaptive evaluation (coarse_step > 1): whether any corner of word t
+  // needs the field; if none does, the word takes its corners' coarse labels
+  // and true is returned.  Else the evaluated corners are counted.
+  auto filled = [&](const Job& J, int t, bool any_needed_elsewhere) -> bool {
+    const int lane = lane_id();
+    const int c = t * 32 + (lane & 31);
+    const bool valid = t < J.nw_c && c < J.g.nc;
+    int fill = 0;
+    const bool need = valid && corner_needed(J, c, &fill);
+    if (!__any(need) && !any_needed_elsewhere) {
+      const uint64_t b = __ballot(valid && lane < 32 && fill);
+      if (t < J.nw_c && lane == 0) J.labels[t] = (uint32_t)b;
+      return true;
+    }
+    const uint64_t ev = __ballot(valid && lane < 32);
+    if (lane == 0 && ev) atomicAdd(&J.status[4], (unsigned long long)__popcll(ev));
+    return false;
+  };
   // world position of corner word t's lane
   auto position = [&](const Job& J, int t, float x[3]) {
     const Grid& g = J.g;
@@ -427,6 +552,18 @@ __global__ __launch_bounds__(256, BF16 ? 2 : 1) void k_labels_mlp(const Job* __r
                        lds_block_sync();
                        for (int i = 0; i < count; ++i) {
                          const int t = 4 * (u0 + i * (int)gridDim.x) + wave;
+                         if (J.coarse_step) {
+                           // the four words are evaluated together if any needs it
+                           int need = 0;
+                           for (int d = 0; d < 4; ++d) {
+                             const int c = (t - wave + d) * 32 + (lane_id() & 31);
+                             int fill;
+                             need |= (t - wave + d < J.nw_c && c < J.g.nc &&
+                                      corner_needed(J, c, &fill));
+                           }
+                           need = __any(need);
+                           if (filled(J, t, need)) continue;
+                         }
                          float x[3];
                          position(J, t, x);
                          body(J, t, mlp_logit_bf16_pp(J.mlp, x, pp_lds, wave, S, W));
@@ -436,6 +573,7 @@ __global__ __launch_bounds__(256, BF16 ? 2 : 1) void k_labels_mlp(const Job* __r
     for_units(jobs, njobs, gwave(), nwaves(),
               [&](const Job& J) { return mine(J) ? J.nw_c : 0; },
               [&](const Job& J, int t) {
+                if (J.coarse_step && filled(J, t, false)) return;
                 float x[3];
                 position(J, t, x);
                 body(J, t, mlp_logit_fp32(J.mlp, x, act));
@@ -1657,6 +1795,10 @@ hipError_t launch_pipeline(const Job* d, int njobs, const PipelineShape& sh,
   k_clear_status<<<4, kBlock, 0, s>>>(d, njobs);
   if (sh.any_mlp) k_pack<<<cfg.pack_blocks, kBlock, 0, s>>>(d, njobs, d_weights);
   mark(0);
+  if (sh.any_coarse) {
+    k_coarse_labels<<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
+    k_coarse_mark<<<cfg.grid_blocks, kBlock, 0, s>>>(d, njobs);
+  }
   if (sh.any_csg) k_labels_csg<<<cfg.grid_blocks, kBlock, 0, s>>>(d, njobs);
   if (sh.any_mlp_fp32) k_labels_mlp<0><<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
   if (sh.any_mlp_bf16 || sh.any_mlp_x3)

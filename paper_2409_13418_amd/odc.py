@@ -47,7 +47,8 @@ class Params(C.Structure):
                 ("lin2", C.c_int32), ("bin2", C.c_int32), ("range1", C.c_float),
                 ("range2", C.c_float), ("qef_tau", C.c_float), ("fp64_cond", C.c_double),
                 ("precision", C.c_int32), ("guard_logit", C.c_float), ("ablation", C.c_int32),
-                ("clamp_vertices", C.c_int32)]
+                ("clamp_vertices", C.c_int32), ("coarse_step", C.c_int32),
+                ("coarse_band", C.c_float)]
 
 
 class MeshBuffers(C.Structure):
@@ -60,7 +61,7 @@ class MeshCounts(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "n_vertices", "n_triangles", "n_active_edges", "n_pairs", "n_active_cells", "n_case3",
         "n_flipped_faces", "n_fp64_cells", "n_guard_corners", "n_queries",
-        "n_search2d_queries", "n_search2d_needed")]
+        "n_search2d_queries", "n_search2d_needed", "n_corner_queries")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}

@@ -14,15 +14,18 @@ INTERMEDIATE_NAMES = ("labels", "edge_ids", "edge_t", "pairs", "pair_pf", "cell_
                       "cell_partmap", "cell_nf", "vertex_base", "edge_case", "edge_grad")
 
 
-def gpu_run(field, grid, precision=0, ctx=None, want_local=True, trace=True):
+def gpu_run(field, grid, precision=0, ctx=None, want_local=True, trace=True, **params_kw):
     """Meshes one field through the C ABI and copies every intermediate back;
-    with trace, also the searches' decision traces (for a replayed oracle)."""
+    with trace, also the searches' decision traces (for a replayed oracle).
+    params_kw set further odc_params fields (e.g. coarse_step)."""
     from paper_2409_13418_amd import odc
     if ctx is None:
         ctx = odc.Context(0)
     ctx.set_trace(trace)
     df = odc.DeviceField(field)
     params = odc.default_params(grid, precision)
+    for k, v in params_kw.items():
+        setattr(params, k, v)
     out = ctx.extract(df, params, want_local=want_local)
     r = {k: v for k, v in out.items() if not hasattr(v, "cpu")}
     r["vertices"] = out["vertices"].cpu().numpy()

@@ -110,7 +110,9 @@ bad_params = [dict(res=0), dict(res=513), dict(iters_1d=0), dict(iters_1d=24), d
               dict(qef_tau=1.0), dict(qef_tau=-0.1), dict(precision=3), dict(guard_logit=0.0),
               dict(guard_logit=float("nan")), dict(fp64_cond=0.0), dict(fp64_cond=float("nan")),
               dict(ablation=16), dict(ablation=8), dict(clamp_vertices=2), dict(size=0.0),
-              dict(size=float("inf"))]
+              dict(size=float("inf")), dict(coarse_step=3), dict(coarse_step=-1),
+              dict(coarse_step=65), dict(res=64, coarse_step=128), dict(coarse_band=-1.0),
+              dict(coarse_band=float("nan"))]
 for kw in bad_params:
     p = params(kw.get("res", 32), **{k: v for k, v in kw.items() if k != "res"})
     rc = L.odc_plan_scratch(C.byref(field(0)), C.byref(p), C.byref(b), None)
@@ -121,6 +123,11 @@ for kw, want in ((dict(width=128), 5), (dict(depth=9), 5), (dict(depth=0), 5), (
                  (dict(n_bands=7, in_dim=45), 0), (dict(n_bands=8, in_dim=51), 5),
                  (dict(weights=None), 1), (dict(spheres=None), 1), (dict(n_spheres=0), 1)):
     assert L.odc_plan_scratch(C.byref(field(1, **kw)), C.byref(params(16)), C.byref(b), None) == want, kw
+b2 = C.c_int64()
+assert L.odc_plan_scratch(C.byref(field(1)), C.byref(params(256, coarse_step=4, coarse_band=1.0)),
+                          C.byref(b2), None) == 0
+assert L.odc_plan_scratch(C.byref(field(1)), C.byref(params(256)), C.byref(b), None) == 0
+assert b2.value > b.value  # the coarse bit sets
 p = params(16, ablation=2)
 assert L.odc_plan_scratch(C.byref(field(0)), C.byref(p), C.byref(b), None) == 5
 assert L.odc_plan_scratch(None, C.byref(params(16)), C.byref(b), None) == 1
