@@ -367,7 +367,7 @@ void job_scalars(Job& J, const odc_field* f, const odc_params* p, int ce) {
 
 // Byte sizes of a job's scratch regions (each a multiple of 256).
 struct Layout {
-  size_t grid[16];
+  size_t grid[17];
   size_t active[19];
   size_t grid_total = 0, active_total = 0;
   size_t mlpw = 0, guard = 0, status = 0;
@@ -393,6 +393,7 @@ Layout job_layout(const Job& J, const odc_field* f, bool guard_full, bool trace)
   const size_t c1 = J.coarse_step ? (size_t)J.cn + 1 : 0;
   L.grid[13] = L.grid[14] = align_up((c1 * c1 * c1 + 31) / 32 * 4);
   L.grid[15] = J.coarse_step ? align_up(((size_t)J.cn * J.cn * J.cn + 63) / 64 * 8) : 0;
+  L.grid[16] = J.coarse_step ? align_up((size_t)J.nw_c * 4) : 0;  // listed fine words
   for (size_t x : L.grid) L.grid_total += x;
   const size_t ne = (size_t)J.cap_edges, np = (size_t)J.cap_pairs, nc = (size_t)J.cap_cells;
   const size_t asz[16] = {align_up(ne * 4),          align_up(ne * 4),
@@ -411,7 +412,7 @@ Layout job_layout(const Job& J, const odc_field* f, bool guard_full, bool trace)
   L.active[17] = trace ? align_up(ne * 4) : 0;
   L.active[18] = trace ? align_up(np * 16) : 0;
   L.active_total += L.active[16] + L.active[17] + L.active[18];
-  L.status = align_up(5 * sizeof(unsigned long long));
+  L.status = align_up(6 * sizeof(unsigned long long));
   if (f->kind == ODC_FIELD_MLP) {
     const int kb1f = kb1_fp32(f->in_dim), kb1b = kb1_bf16(f->in_dim), d = f->depth;
     L.n_w1f = (size_t)kb1f * 512;
@@ -435,15 +436,19 @@ Layout job_layout(const Job& J, const odc_field* f, bool guard_full, bool trace)
 // Points the job's arrays into its scratch regions.
 void job_bind(Job& J, const Layout& L, const odc_field* f, char* grid, char* active, char* mlpw,
               char* guard, char* status) {
-  uint32_t** gp[16] = {&J.labels, &J.emask,  &J.ecount,   &J.eprefix, &J.fact,  &J.famb,
+  uint32_t** gp[17] = {&J.labels, &J.emask,  &J.ecount,   &J.eprefix, &J.fact,  &J.famb,
                        &J.fflip,  &J.pcount, &J.pprefix,  &J.cmask,   &J.ccount, &J.cprefix,
-                       &J.scan_tmp, &J.cbits, &J.cnear,   &J.cmark};
+                       &J.scan_tmp, &J.cbits, &J.cnear,   &J.cmark,
+                       reinterpret_cast<uint32_t**>(&J.wlist)};
   size_t off = 0;
-  for (int i = 0; i < 16; ++i) {
+  for (int i = 0; i < 17; ++i) {
     *gp[i] = (uint32_t*)(grid + off);
     off += L.grid[i];
   }
-  if (!J.coarse_step) J.cbits = J.cnear = J.cmark = nullptr;
+  if (!J.coarse_step) {
+    J.cbits = J.cnear = J.cmark = nullptr;
+    J.wlist = nullptr;
+  }
   void** ap[19] = {(void**)&J.elist,    (void**)&J.et,    (void**)&J.ecase, (void**)&J.ntri,
                    (void**)&J.n3,       (void**)&J.tprefix, (void**)&J.c3prefix,
                    (void**)&J.quad,     (void**)&J.plist, (void**)&J.pf,    (void**)&J.clist,

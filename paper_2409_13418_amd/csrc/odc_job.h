@@ -43,6 +43,7 @@ struct Job {
   uint32_t* cbits;
   uint32_t* cnear;
   uint32_t* cmark;
+  int* wlist;  // the fine label words that need the field (count in status[5])
 
   int nw_c, nw_e, nw_f, nw_cell;       // words of the corner / edge / face / cell bit sets
   int cap_edges, cap_pairs, cap_cells;  // active-set scratch capacities
@@ -95,7 +96,7 @@ struct Job {
   int* out_vref;
 
   // [0] guard corners, [1] fp64 cells, [2] overflow, [3] 2D-search queries,
-  // [4] corner queries (adaptive evaluation)
+  // [4] corner queries, [5] listed fine words (adaptive evaluation)
   unsigned long long* status;
   uint32_t* guard_list;
   int guard_cap;

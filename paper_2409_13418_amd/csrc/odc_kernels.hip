@@ -317,6 +317,7 @@ __global__ void k_clear_status(const Job* __restrict__ jobs, int njobs) {
     jobs[k].status[2] = 0;
     jobs[k].status[3] = 0;
     jobs[k].status[4] = 0;
+    jobs[k].status[5] = 0;
   }
 }
 
@@ -415,53 +416,109 @@ __global__ __launch_bounds__(256) void k_coarse_mark(const Job* __restrict__ job
             });
 }
 
-// Whether fine corner c lies in a marked coarse cell; else *fill receives
-// the common label of the unmarked coarse cells holding it.
-__device__ __forceinline__ bool corner_needed(const Job& J, int c, int* fill) {
-  const int n1 = J.g.N + 1, S = J.coarse_step, cn = J.cn, c1 = cn + 1;
-  const int p[3] = {c % n1, (c / n1) % n1, c / (n1 * n1)};
-  int lo[3], hi[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = p[a] > 0 ? (p[a] - 1) / S : 0;
-    hi[a] = p[a] / S < cn - 1 ? p[a] / S : cn - 1;
+// Coarse cells holding fine coordinate p along an axis: lo..hi (two when p
+// lies on a coarse plane inside the grid).
+__device__ __forceinline__ void coarse_span(int p, int S, int cn, int& lo, int& hi) {
+  lo = p > 0 ? (p - 1) / S : 0;
+  hi = p / S < cn - 1 ? p / S : cn - 1;
+}
+
+// Whether some corner of fine corners c0..c1 (one word) lies in a marked
+// coarse cell: the word's row segments against the marked bit set.
+__device__ __forceinline__ bool word_needed(const Job& J, int c0, int c1) {
+  const int n1 = J.g.N + 1, S = J.coarse_step, cn = J.cn;
+  for (int r = c0 / n1; r <= c1 / n1; ++r) {
+    const int xa = r == c0 / n1 ? c0 % n1 : 0, xb = r == c1 / n1 ? c1 % n1 : n1 - 1;
+    int jl, jh, kl, kh, il, ih, t;
+    coarse_span(r % n1, S, cn, jl, jh);
+    coarse_span(r / n1, S, cn, kl, kh);
+    coarse_span(xa, S, cn, il, t);
+    coarse_span(xb, S, cn, t, ih);
+    for (int k = kl; k <= kh; ++k)
+      for (int j = jl; j <= jh; ++j)
+        for (int i = il; i <= ih; ++i)
+          if (bit_of(J.cmark, i + cn * (j + cn * k))) return true;
   }
-  bool need = false;
-  for (int k = lo[2]; k <= hi[2]; ++k)
-    for (int j = lo[1]; j <= hi[1]; ++j)
-      for (int i = lo[0]; i <= hi[0]; ++i) need |= bit_of(J.cmark, i + cn * (j + cn * k)) != 0;
-  *fill = bit_of(J.cbits, lo[0] + c1 * (lo[1] + c1 * lo[2]));
-  return need;
+  return false;
+}
+
+// The common coarse label of the unmarked coarse cells holding corner c.
+__device__ __forceinline__ int corner_fill(const Job& J, int c) {
+  const int n1 = J.g.N + 1, S = J.coarse_step, cn = J.cn, c1 = cn + 1;
+  int lo[3], hi;
+  coarse_span(c % n1, S, cn, lo[0], hi);
+  coarse_span((c / n1) % n1, S, cn, lo[1], hi);
+  coarse_span(c / (n1 * n1), S, cn, lo[2], hi);
+  return bit_of(J.cbits, lo[0] + c1 * (lo[1] + c1 * lo[2]));
+}
+
+// The fine words (32 corners) that need the field, i.e. hold a corner of a
+// marked coarse cell, are appended to J.wlist (count in status[5]); every
+// other word takes its corners' coarse labels here.
+__global__ __launch_bounds__(256) void k_fine_plan(const Job* __restrict__ jobs, int njobs) {
+  for_units(jobs, njobs, gwave(), nwaves(),
+            [](const Job& J) { return J.coarse_step ? (J.nw_c + 63) >> 6 : 0; },
+            [&](const Job& J, int u) {
+              const int lane = lane_id();
+              const int t = u * 64 + lane;
+              bool need = false;
+              if (t < J.nw_c) {
+                const int c0 = t * 32, c1 = (c0 + 32 < J.g.nc ? c0 + 32 : J.g.nc) - 1;
+                need = word_needed(J, c0, c1);
+                if (!need) {
+                  uint32_t w = 0;
+                  for (int c = c0; c <= c1; ++c) w |= (uint32_t)corner_fill(J, c) << (c - c0);
+                  J.labels[t] = w;
+                }
+              }
+              const uint64_t b = __ballot(need);
+              unsigned long long base = 0;
+              if (lane == 0 && b) {
+                base = atomicAdd(&J.status[5], (unsigned long long)__popcll(b));
+                // the listed words' corners are the fine corner queries (the
+                // last word of the grid may be partial)
+                const int lw = J.nw_c - 1 - u * 64;  // the grid's last word, if in this wave
+                const bool last = lw >= 0 && lw < 64 && ((b >> lw) & 1ull);
+                const int tail = J.g.nc - (J.nw_c - 1) * 32;
+                atomicAdd(&J.status[4],
+                          (unsigned long long)(32 * __popcll(b) - (last ? 32 - tail : 0)));
+              }
+              base = __shfl(base, 0);
+              if (need) J.wlist[base + __popcll(b & ((1ull << lane) - 1ull))] = t;
+            });
+}
+
+// Corner words of stage (a): all of them, or with adaptive evaluation the
+// listed ones (n of them); fine_word maps a unit's word index to the word
+// (past the end: nw_c, no word).
+__device__ __forceinline__ int fine_words(const Job& J) {
+  return J.coarse_step ? (int)J.status[5] : J.nw_c;
+}
+__device__ __forceinline__ int fine_word(const Job& J, int n, int i) {
+  return J.coarse_step ? (i < n ? J.wlist[i] : J.nw_c) : i;
 }
 
 // ------------------------------------------------------------- (a) labels
+// CSG corners, two words per wavefront (lane half h takes word 2u + h).
 __global__ __launch_bounds__(256) void k_labels_csg(const Job* __restrict__ jobs, int njobs) {
   for_units(jobs, njobs, gwave(), nwaves(),
-            [](const Job& J) { return J.kind == 0 ? (J.g.nc + 63) >> 6 : 0; },
+            [](const Job& J) { return J.kind == 0 ? (fine_words(J) + 1) >> 1 : 0; },
             [&](const Job& J, int u) {
               const Grid& g = J.g;
-              const int c = u * 64 + lane_id();
+              const int lane = lane_id();
+              const int t = fine_word(J, fine_words(J), 2 * u + (lane >> 5));
+              const int c = t * 32 + (lane & 31);
               int lab = 0;
-              if (c < g.nc) {
-                int fill = 0;
-                const bool need = !J.coarse_step || corner_needed(J, c, &fill);
-                if (need) {
-                  const int n1 = g.N + 1;
-                  const float gp[3] = {(float)(c % n1), (float)((c / n1) % n1),
-                                       (float)(c / (n1 * n1))};
-                  float x[3];
-                  grid_world(g, gp, x);
-                  lab = csg_inside(J.prims, J.n_prims, x);
-                } else {
-                  lab = fill;
-                }
-                if (J.coarse_step) {
-                  const uint64_t ev = __ballot(need);
-                  if (lane_id() == __ffsll((long long)__ballot(1)) - 1)
-                    atomicAdd(&J.status[4], (unsigned long long)__popcll(ev));
-                }
+              if (t < J.nw_c && c < g.nc) {
+                const int n1 = g.N + 1;
+                const float gp[3] = {(float)(c % n1), (float)((c / n1) % n1),
+                                     (float)(c / (n1 * n1))};
+                float x[3];
+                grid_world(g, gp, x);
+                lab = csg_inside(J.prims, J.n_prims, x);
               }
-              store_ballot(__ballot(lab), u * 64, J.nw_c, J.labels);
+              const uint64_t b = __ballot(lab);
+              if ((lane & 31) == 0 && t < J.nw_c) J.labels[t] = (uint32_t)(lane ? b >> 32 : b);
             });
 }
 
@@ -473,7 +530,10 @@ __global__ __launch_bounds__(256) void k_labels_csg(const Job* __restrict__ jobs
 // dummy) and every call is made by all four; two such workgroups share a
 // compute unit (one wavefront of each per SIMD), so one's matrix work fills
 // the other's waits.
-template <int BF16>
+// ADAPT: the jobs with adaptive corner evaluation (their listed words only),
+// else the others (every word); separate kernels keep the list handling out
+// of the plain pass's registers.
+template <int BF16, bool ADAPT>
 __global__ __launch_bounds__(256, BF16 ? 2 : 1) void k_labels_mlp(const Job* __restrict__ jobs,
                                                                  int njobs) {
   static_assert(kBlock == 256, "the bf16 evaluation takes four wavefronts");
@@ -505,24 +565,6 @@ __global__ __launch_bounds__(256, BF16 ? 2 : 1) void k_labels_mlp(const Job* __r
       }
     }
   };
-  // Adaptive evaluation (coarse_step > 1): whether any corner of word t
-  // needs the field; if none does, the word takes its corners' coarse labels
-  // and true is returned.  Else the evaluated corners are counted.
-  auto filled = [&](const Job& J, int t, bool any_needed_elsewhere) -> bool {
-    const int lane = lane_id();
-    const int c = t * 32 + (lane & 31);
-    const bool valid = t < J.nw_c && c < J.g.nc;
-    int fill = 0;
-    const bool need = valid && corner_needed(J, c, &fill);
-    if (!__any(need) && !any_needed_elsewhere) {
-      const uint64_t b = __ballot(valid && lane < 32 && fill);
-      if (t < J.nw_c && lane == 0) J.labels[t] = (uint32_t)b;
-      return true;
-    }
-    const uint64_t ev = __ballot(valid && lane < 32);
-    if (lane == 0 && ev) atomicAdd(&J.status[4], (unsigned long long)__popcll(ev));
-    return false;
-  };
   // world position of corner word t's lane
   auto position = [&](const Job& J, int t, float x[3]) {
     const Grid& g = J.g;
@@ -536,13 +578,18 @@ __global__ __launch_bounds__(256, BF16 ? 2 : 1) void k_labels_mlp(const Job* __r
   // their guard band in fp32 (k_relabel_fp32), so their corner signs are
   // the fp32 path's
   const auto mine = [](const Job& J) {
-    return J.kind == 1 && (BF16 ? J.precision >= 1 : J.precision == 0);
+    return J.kind == 1 && (BF16 ? J.precision >= 1 : J.precision == 0) &&
+           (J.coarse_step != 0) == ADAPT;
+  };
+  auto n_words = [](const Job& J) { return ADAPT ? (int)J.status[5] : J.nw_c; };
+  auto word_at = [](const Job& J, int n, int i) {
+    return ADAPT ? (i < n ? J.wlist[i] : J.nw_c) : i;
   };
   if constexpr (BF16) {
     // the field's biases and output weights are staged, and the weight ring
     // primed, once per job
     for_unit_streams(jobs, njobs, (int)blockIdx.x, (int)gridDim.x,
-                     [&](const Job& J) { return mine(J) ? (J.nw_c + 3) >> 2 : 0; },
+                     [&](const Job& J) { return mine(J) ? (n_words(J) + 3) >> 2 : 0; },
                      [&](const Job& J, int u0, int count) {
                        lds_block_sync();  // the previous job's reads are done
                        stage_bias_wout(J.mlp, pp_lds + kPPBiasOff);
@@ -550,20 +597,13 @@ __global__ __launch_bounds__(256, BF16 ? 2 : 1) void k_labels_mlp(const Job* __r
                        v8bf W[kPPRing][2];
                        pp_prime(S, W);
                        lds_block_sync();
+                       // the listed words' indices are read one call ahead
+                       const int nw = n_words(J);
+                       int tn = word_at(J, nw, 4 * u0 + wave);
                        for (int i = 0; i < count; ++i) {
-                         const int t = 4 * (u0 + i * (int)gridDim.x) + wave;
-                         if (J.coarse_step) {
-                           // the four words are evaluated together if any needs it
-                           int need = 0;
-                           for (int d = 0; d < 4; ++d) {
-                             const int c = (t - wave + d) * 32 + (lane_id() & 31);
-                             int fill;
-                             need |= (t - wave + d < J.nw_c && c < J.g.nc &&
-                                      corner_needed(J, c, &fill));
-                           }
-                           need = __any(need);
-                           if (filled(J, t, need)) continue;
-                         }
+                         const int t = tn;
+                         if (i + 1 < count)
+                           tn = word_at(J, nw, 4 * (u0 + (i + 1) * (int)gridDim.x) + wave);
                          float x[3];
                          position(J, t, x);
                          body(J, t, mlp_logit_bf16_pp(J.mlp, x, pp_lds, wave, S, W));
@@ -571,9 +611,9 @@ __global__ __launch_bounds__(256, BF16 ? 2 : 1) void k_labels_mlp(const Job* __r
                      });
   } else {
     for_units(jobs, njobs, gwave(), nwaves(),
-              [&](const Job& J) { return mine(J) ? J.nw_c : 0; },
-              [&](const Job& J, int t) {
-                if (J.coarse_step && filled(J, t, false)) return;
+              [&](const Job& J) { return mine(J) ? n_words(J) : 0; },
+              [&](const Job& J, int i) {
+                const int t = word_at(J, n_words(J), i);
                 float x[3];
                 position(J, t, x);
                 body(J, t, mlp_logit_fp32(J.mlp, x, act));
@@ -1798,11 +1838,16 @@ hipError_t launch_pipeline(const Job* d, int njobs, const PipelineShape& sh,
   if (sh.any_coarse) {
     k_coarse_labels<<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
     k_coarse_mark<<<cfg.grid_blocks, kBlock, 0, s>>>(d, njobs);
+    k_fine_plan<<<cfg.grid_blocks, kBlock, 0, s>>>(d, njobs);
   }
   if (sh.any_csg) k_labels_csg<<<cfg.grid_blocks, kBlock, 0, s>>>(d, njobs);
-  if (sh.any_mlp_fp32) k_labels_mlp<0><<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
+  if (sh.any_mlp_fp32) k_labels_mlp<0, false><<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
+  if (sh.any_mlp_fp32 && sh.any_coarse)
+    k_labels_mlp<0, true><<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
   if (sh.any_mlp_bf16 || sh.any_mlp_x3)
-    k_labels_mlp<1><<<2 * cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
+    k_labels_mlp<1, false><<<2 * cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
+  if ((sh.any_mlp_bf16 || sh.any_mlp_x3) && sh.any_coarse)
+    k_labels_mlp<1, true><<<2 * cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
   if (sh.any_mlp_bf16 || sh.any_mlp_x3)
     k_relabel_fp32<<<cfg.mlp_blocks, kBlock, 0, s>>>(d, njobs);
   mark(1);
