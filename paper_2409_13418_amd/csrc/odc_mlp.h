@@ -284,12 +284,20 @@ constexpr int kGroupsF32 = kHiddenBlocksF32 / 4;  // 32 groups of 4 K blocks
 // Output layer of either path from the last layer's pre-activations in the
 // accumulators: y = sum_n wout[n] relu(pre_n + bias_n), lane half h taking
 // neurons 8G + 4h + d in the order (G, d), then the sdf term.
+//
+// ob: lane l's share of the last layer's biases and the output weights
+// (vectors l of each, loaded by the caller well ahead); they go through the
+// wavefront's LDS region, free once the last layer's accumulators are
+// final, so that the output layer waits on LDS and not on memory.
 template <bool kTan = false>
-__device__ __forceinline__ float mlp_output(const Mlp& M, const v16f (&acc)[8], int h, int zero,
+__device__ __forceinline__ float mlp_output(const Mlp& M, const v16f (&acc)[8], int h,
+                                            const v4f (&ob)[2], v4f* __restrict__ act4,
                                             const float x[3]) {
   const int ch = lane_id() & 3;
-  const ODC_GLOBAL v4f* Bl = (const ODC_GLOBAL v4f*)gmem(M.bias) + (size_t)(M.depth - 1) * 64 + h + zero;
-  const ODC_GLOBAL v4f* Wo = (const ODC_GLOBAL v4f*)gmem(M.wout) + h + zero;
+  act4[lane_id()] = ob[0];
+  act4[64 + lane_id()] = ob[1];
+  const v4f* Bl = act4 + h;
+  const v4f* Wo = act4 + 64 + h;
   float part = 0.0f;
 #pragma unroll
   for (int G0 = 0; G0 < kGroupsF32; G0 += 8) {
@@ -387,7 +395,20 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
       }
     }
   }
+  // the output layer's biases and weights (this lane's vectors), loaded
+  // when the last layer starts
+  v4f ob[2] = {};
+  const ODC_GLOBAL v4f* Ob = (const ODC_GLOBAL v4f*)gmem(M.bias) + (size_t)(M.depth - 1) * 64 + zero;
+  const ODC_GLOBAL v4f* Ow = (const ODC_GLOBAL v4f*)gmem(M.wout) + zero;
+  if (M.depth == 1) {
+    ob[0] = Ob[lane];
+    ob[1] = Ow[lane];
+  }
   for (int l = 1; l < M.depth; ++l) {
+    if (l == M.depth - 1) {
+      ob[0] = Ob[lane];
+      ob[1] = Ow[lane];
+    }
     // park the pre-activations of layer l
 #pragma unroll
     for (int T = 0; T < 8; ++T)
@@ -427,7 +448,7 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
       }
     }
   }
-  return mlp_output<kTan>(M, acc, h, zero, x);
+  return mlp_output<kTan>(M, acc, h, ob, act4, x);
 }
 
 // bf16 evaluation (corner pass): a K block b of a hidden layer takes, in
