@@ -18,22 +18,35 @@ def odc():
     return m
 
 
+# field, grid, precision, further odc_params fields: CSG and MLP jobs at every
+# precision, one with adaptive corner evaluation
+ADAPTIVE = {"coarse_step": 4, "coarse_band": 1.5 * 20.0 * 3 ** 0.5 * 4 / 32}
+
+
 def _jobs():
     out = []
     for k, res in enumerate((24, 40, 32, 48)):
-        out.append((I.csg_random_field(5000 + k), I.unit_grid(res, 15), 0))
-    for k, (res, prec) in enumerate(((16, 0), (24, 1), (32, 1), (20, 0))):
-        out.append((I.mlp_field(5100 + k), I.unit_grid(res, 15), prec))
+        out.append((I.csg_random_field(5000 + k), I.unit_grid(res, 15), 0, {}))
+    for k, (res, prec, kw) in enumerate(((16, 0, {}), (24, 1, {}), (32, 1, ADAPTIVE),
+                                         (20, 2, {}))):
+        out.append((I.mlp_field(5100 + k), I.unit_grid(res, 15), prec, kw))
     f, g = I.sphere_case(32, 10)
-    out.append((f, g, 0))
+    out.append((f, g, 0, {}))
     return out
+
+
+def _params(odc, g, prec, kw):
+    p = odc.default_params(g, prec)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
 
 
 def _alone(odc, jobs):
     ctx = odc.Context(0)
     ref = []
-    for f, g, prec in jobs:
-        r = ctx.extract(odc.DeviceField(f), odc.default_params(g, prec))
+    for f, g, prec, kw in jobs:
+        r = ctx.extract(odc.DeviceField(f), _params(odc, g, prec, kw))
         ref.append((r["vertices"].cpu().numpy().copy(), r["triangles"].cpu().numpy().copy(),
                     r["n_active_cells"]))
     ctx.close()
@@ -54,8 +67,8 @@ def test_mix_equals_alone(odc):
     jobs = _jobs()
     ref = _alone(odc, jobs)
     ctx = odc.Context(0)
-    dfs = [odc.DeviceField(f) for f, _, _ in jobs]
-    ps = [odc.default_params(g, prec) for _, g, prec in jobs]
+    dfs = [odc.DeviceField(f) for f, _, _, _ in jobs]
+    ps = [_params(odc, g, prec, kw) for _, g, prec, kw in jobs]
     outs = [odc.OutputBuffers(len(v) + 16, len(t) + 16) for v, t, _ in ref]
     tmp = odc.Server(ctx, 1 << 30)
     fp = [tmp.footprint(d, p) for d, p in zip(dfs, ps)]
@@ -100,18 +113,18 @@ def test_served_jobs_against_oracle(odc, oracle_mod):
     from gpu_common import MLP_TIE, check_replayed, gpu_run, trace_of
     jobs = _jobs()
     ctx = odc.Context(0)
-    dfs = [odc.DeviceField(f) for f, _, _ in jobs]
-    ps = [odc.default_params(g, prec) for _, g, prec in jobs]
+    dfs = [odc.DeviceField(f) for f, _, _, _ in jobs]
+    ps = [_params(odc, g, prec, kw) for _, g, prec, kw in jobs]
     outs = [odc.OutputBuffers(8 * g.res ** 2 + 4096, 16 * g.res ** 2 + 8192, want_local=True)
-            for _, g, _ in jobs]
+            for _, g, _, _ in jobs]
     srv = odc.Server(ctx, 1 << 30, lanes=2, max_batch=3)
     tickets = [srv.submit(d, p, o) for d, p, o in zip(dfs, ps, outs)]
     served = [srv.wait(t) for t in tickets]
     srv.close()
-    for k, ((f, g, prec), res) in enumerate(zip(jobs, served)):
+    for k, ((f, g, prec, kw), res) in enumerate(zip(jobs, served)):
         assert res["status"] == odc.OK, (k, res)
         got = {n: t.cpu().numpy() for n, t in outs[k].views(res).items()}
-        r, _ = gpu_run(f, g, precision=prec, ctx=ctx)
+        r, _ = gpu_run(f, g, precision=prec, ctx=ctx, **kw)
         for n in ("vertices", "triangles", "vertices_local", "vertex_ref"):
             assert np.array_equal(got[n], r[n]), (k, n)
         tr = trace_of(oracle_mod, r)

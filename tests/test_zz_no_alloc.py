@@ -18,11 +18,13 @@ import odc_inputs as I
 pytestmark = pytest.mark.gpu
 
 
-def _extract(ctx, entry, field, grid, precision):
+def _extract(ctx, entry, field, grid, precision, **kw):
     from paper_2409_13418_amd import odc
     L = odc.load()
     df = odc.DeviceField(field)
     params = odc.default_params(grid, precision)
+    for k, v in kw.items():
+        setattr(params, k, v)
     n = grid.res
     out = odc.OutputBuffers(8 * n * n + 4096, 16 * n * n + 8192, want_local=True)
     print(f"{entry}: {field.name} res {n} precision {precision}", flush=True)
@@ -50,7 +52,7 @@ def _same(a, b, label):
         assert np.array_equal(a[k], b[k]), (label, k)
 
 
-@pytest.mark.parametrize("kind", ["mlp", "mlp_x3", "csg"])
+@pytest.mark.parametrize("kind", ["mlp", "mlp_x3", "mlp_adaptive", "csg"])
 def test_noalloc_equals_extract_twice(kind):
     from paper_2409_13418_amd import odc
     ctx = odc.Context(0)
@@ -60,12 +62,16 @@ def test_noalloc_equals_extract_twice(kind):
             field, prec, sizes = I.mlp_field(3), odc.PREC_BF16_GUARDED, (96, 40)
         elif kind == "mlp_x3":  # the split weight terms live in the array too
             field, prec, sizes = I.mlp_field(5), odc.PREC_BF16_X3, (64, 33)
+        elif kind == "mlp_adaptive":  # and the coarse bit sets and word list
+            field, prec, sizes = I.mlp_field(6), odc.PREC_BF16_GUARDED, (96, 48)
         else:
             field, prec, sizes = I.csg_random_field(2), odc.PREC_FP32, (128, 61)
         for res in sizes:  # the second call is smaller and reuses the array
             g = I.unit_grid(res, 15)
-            ref = _extract(ctx, "odc_mesh_extract", field, g, prec)
-            got = _extract(ctx, "odc_mesh_extract_noalloc", field, g, prec)
+            kw = ({"coarse_step": 4, "coarse_band": 1.5 * 20.0 * 3 ** 0.5 * 4 / res}
+                  if kind == "mlp_adaptive" else {})
+            ref = _extract(ctx, "odc_mesh_extract", field, g, prec, **kw)
+            got = _extract(ctx, "odc_mesh_extract_noalloc", field, g, prec, **kw)
             assert ref["counts"]["n_triangles"] > 0
             _same(ref, got, f"{kind}{res}")
     finally:
