@@ -1175,13 +1175,17 @@ struct PairSearch {
         // index of the query within its own ray
         const int k =
             step <= n1 ? step - 1 : (step <= n1 + n2 ? step - 1 - n1 : step - 1 - n1 - n2);
-        const float s = lb.param(k);
-        if (skip && k < lb.nl && lb.found) {  // the bookkeeping still runs (label unused)
-          lb.consume(k, s, 0);
+        if (skip && k < lb.nl && lb.found) {
+          // the ray's remaining linear samples cannot move the bracket: go
+          // straight to its last one, whose bookkeeping fixes the bracket
+          // (the label is unused)
+          step += lb.nl - 1 - k;
+          lb.consume(lb.nl - 1, 0.0f, 0);
           after(j);
           ++step;
           continue;
         }
+        const float s = lb.param(k);
         ck = k;
         cs = s;
         lb.point(s, P);
