@@ -355,7 +355,12 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
   const __amdgpu_buffer_rsrc_t ws = weight_stream(
       M.w1f, ((size_t)M.kb1f + (size_t)(M.depth - 1) * kHiddenBlocksF32 + kPrefetchF32) * 2048);
   const int voff = (lane + zero) * 16;
-  auto S = [&](int vec) -> v4f { return ring_load(ws, voff, vec * 1024); };
+  // vector base + c of the stream, base a multiple of 4 and c a constant:
+  // c mod 4 KB goes into the load's immediate offset, so the four vectors of
+  // two K blocks share one scalar offset (one scalar add per two blocks)
+  auto S = [&](int base, int c) -> v4f {
+    return ring_load(ws, voff + (c & 3) * 1024, (base + (c & ~3)) * 1024);
+  };
   // bias of layer l, group G, this lane half: vector (l * 64 + 2G + h)
   const ODC_GLOBAL v4f* Bv = (const ODC_GLOBAL v4f*)gmem(M.bias) + h + zero;
   v4f* act4 = reinterpret_cast<v4f*>(act);
@@ -367,7 +372,7 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
 #pragma unroll
   for (int d = 0; d < kPrefetchF32; ++d)
 #pragma unroll
-    for (int q = 0; q < 2; ++q) wr[d][q] = S(2 * d + q);
+    for (int q = 0; q < 2; ++q) wr[d][q] = S(0, 2 * d + q);
   const v16f zacc = {};
   v16f acc[8];
   // layer 1: B operand = Fourier features computed in registers; the first
@@ -390,7 +395,7 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
         bv = feature(b + 1);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int q = 0; q < 2; ++q) wr[d][q] = S((b + kPrefetchF32) * 2 + q);
+        for (int q = 0; q < 2; ++q) wr[d][q] = S(2 * kPrefetchF32, 2 * b + q);
         __builtin_amdgcn_sched_barrier(0);
       }
     }
@@ -417,6 +422,7 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
         act4[(4 * T + g) * 64 + lane] =
             (v4f){acc[T][4 * g], acc[T][4 * g + 1], acc[T][4 * g + 2], acc[T][4 * g + 3]};
     // block b of this layer is block kb1f + (l-1)*128 + b of the stream
+    // (kb1f is a multiple of 4, so wn is one of 8)
     const int wn = (M.kb1f + (l - 1) * kHiddenBlocksF32 + kPrefetchF32) * 2;
     const ODC_GLOBAL v4f* Bn = Bv + (size_t)(l - 1) * 64;
     v4f an = act4[lane];
@@ -442,7 +448,7 @@ __device__ __forceinline__ float mlp_logit_fp32(const Mlp& M, const float x[3],
         // last group: group 0 of the next layer, or of the output layer)
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int q = 0; q < 2; ++q) wr[d][q] = S(wn + b * 2 + q);
+        for (int q = 0; q < 2; ++q) wr[d][q] = S(wn, 2 * b + q);
         if (d == 0) bq[(G + 1) & 1] = G + 1 < kGroupsF32 ? Bn[2 * (G + 1)] : Bn[64];
         __builtin_amdgcn_sched_barrier(0);
       }
