@@ -176,4 +176,73 @@ __device__ __forceinline__ void for_unit_streams(const Job* __restrict__ jobs, i
   }
 }
 
+// Job-major distribution in contiguous chunks: body(J, u0, u1) gets units
+// [u0, u1) of every job, the worker's share of ceil(n / W) consecutive units
+// (for passes that walk their units in order, see BlockWalk).
+template <class NFn, class Body>
+__device__ __forceinline__ void for_unit_chunks(const Job* __restrict__ jobs, int njobs,
+                                                int worker, int W, const NFn& nunits,
+                                                const Body& body) {
+  const __attribute__((address_space(4))) Job* cj =
+      (const __attribute__((address_space(4))) Job*)jobs;
+  long long rot = 0;
+  for (int k = 0; k < njobs; ++k) {
+    const Job& J = *(const Job*)&cj[k];
+    const int n = nunits(J);
+    if (n <= 0) continue;
+    const int chunk = (n + W - 1) / W;
+    const int used = (n + chunk - 1) / chunk;
+    int w = (int)(((long long)worker - rot) % W);
+    if (w < 0) w += W;
+    if (w < used) {
+      const int u0 = w * chunk;
+      body(J, u0, n - u0 < chunk ? n : u0 + chunk);
+    }
+    rot += used;
+  }
+}
+
+// Grid position of element e of the edges (one block per axis: N along the
+// axis, N + 1 across it), the faces (N + 1 along the axis, N across) or the
+// cells (one N^3 block), x fastest: set once with divisions, then moved 64
+// elements at a time with carries.
+struct BlockWalk {
+  int N, kind;  // 0 edges, 1 faces, 2 cells
+  int a, p[3], n[3];
+  __device__ __forceinline__ void dims() {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) n[d] = kind == 2 ? N : (((d == a) == (kind == 0)) ? N : N + 1);
+  }
+  __device__ __forceinline__ void init(const Grid& g, int k, int e) {
+    N = g.N;
+    kind = k;
+    if (k == 0) {
+      edge_pos(g, e, a, p);
+    } else if (k == 1) {
+      face_pos(g, e, a, p);
+    } else {
+      a = 0;
+      p[0] = e % N;
+      p[1] = (e / N) % N;
+      p[2] = e / (N * N);
+    }
+    dims();
+  }
+  // the element 64 further on (past the last block the position is unused)
+  __device__ __forceinline__ void advance64() {
+    p[0] += 64;
+    while (p[0] >= n[0]) {
+      p[0] -= n[0];
+      if (++p[1] >= n[1]) {
+        p[1] = 0;
+        if (++p[2] >= n[2]) {
+          p[2] = 0;
+          ++a;
+          dims();
+        }
+      }
+    }
+  }
+};
+
 }  // namespace odc

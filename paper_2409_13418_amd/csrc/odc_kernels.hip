@@ -655,26 +655,35 @@ __global__ __launch_bounds__(256) void k_relabel_fp32(const Job* __restrict__ jo
 }
 
 // ---------------------------------------------------------- classification
+// The classification passes walk contiguous chunks of 64-element units,
+// each lane carrying its element's grid position from unit to unit
+// (BlockWalk): the per-element index divisions would otherwise dominate
+// these passes.
 __global__ __launch_bounds__(256) void k_classify_edges(const Job* __restrict__ jobs, int njobs) {
-  for_units(jobs, njobs, gwave(), nwaves(),
-            [](const Job& J) { return (3 * J.g.ea + 63) >> 6; },
-            [&](const Job& J, int u) {
-              const Grid& g = J.g;
-              const int e = u * 64 + lane_id();
-              int x = 0;
-              if (e < 3 * g.ea) {
-                int a, p[3];
-                edge_pos(g, e, a, p);
-                const int c0 = corner_index(g, p[0], p[1], p[2]);
-                const int step = a == 0 ? 1 : (a == 1 ? g.N + 1 : (g.N + 1) * (g.N + 1));
-                x = bit_of(J.labels, c0) != bit_of(J.labels, c0 + step);
-              }
-              const uint64_t b = __ballot(x);
-              store_ballot(b, u * 64, J.nw_e, J.emask);
-              const int lane = lane_id(), w0 = u * 2;
-              if (lane == 0 && w0 < J.nw_e) J.ecount[w0] = __popc((uint32_t)b);
-              if (lane == 32 && w0 + 1 < J.nw_e) J.ecount[w0 + 1] = __popc((uint32_t)(b >> 32));
-            });
+  for_unit_chunks(jobs, njobs, gwave(), nwaves(),
+                  [](const Job& J) { return (3 * J.g.ea + 63) >> 6; },
+                  [&](const Job& J, int u0, int u1) {
+                    const Grid& g = J.g;
+                    const int lane = lane_id();
+                    BlockWalk w;
+                    w.init(g, 0, u0 * 64 + lane);
+                    for (int u = u0; u < u1; ++u, w.advance64()) {
+                      const int e = u * 64 + lane;
+                      int x = 0;
+                      if (e < 3 * g.ea) {
+                        const int c0 = corner_index(g, w.p[0], w.p[1], w.p[2]);
+                        const int step =
+                            w.a == 0 ? 1 : (w.a == 1 ? g.N + 1 : (g.N + 1) * (g.N + 1));
+                        x = bit_of(J.labels, c0) != bit_of(J.labels, c0 + step);
+                      }
+                      const uint64_t b = __ballot(x);
+                      store_ballot(b, u * 64, J.nw_e, J.emask);
+                      const int w0 = u * 2;
+                      if (lane == 0 && w0 < J.nw_e) J.ecount[w0] = __popc((uint32_t)b);
+                      if (lane == 32 && w0 + 1 < J.nw_e)
+                        J.ecount[w0 + 1] = __popc((uint32_t)(b >> 32));
+                    }
+                  });
 }
 
 // labels of the 8 corners of cell (i,j,k): bit lc = x + 2y + 4z
@@ -725,52 +734,61 @@ __device__ inline int face_flip(const Grid& g, const uint32_t* __restrict__ L,
 
 __global__ __launch_bounds__(256) void k_classify_faces(const Job* __restrict__ jobs, int njobs,
                                                         const uint32_t* __restrict__ table) {
-  for_units(jobs, njobs, gwave(), nwaves(),
-            [](const Job& J) { return (3 * J.g.fa + 63) >> 6; },
-            [&](const Job& J, int u) {
-              const Grid& g = J.g;
-              const int f = u * 64 + lane_id();
-              int act = 0, amb = 0, flip = 0;
-              if (f < 3 * g.fa) {
-                int a, p[3], Lf[4];
-                face_pos(g, f, a, p);
-                face_labels(g, J.labels, a, p, Lf);
-                const int n = __popc(face_crossing_mask(Lf));
-                act = n > 0;
-                amb = n == 4;
-                if (amb) flip = face_flip(g, J.labels, table, a, p);
-              }
-              const uint64_t ba = __ballot(act), bb = __ballot(amb), bf = __ballot(flip);
-              store_ballot(ba, u * 64, J.nw_f, J.fact);
-              store_ballot(bb, u * 64, J.nw_f, J.famb);
-              store_ballot(bf, u * 64, J.nw_f, J.fflip);
-              const int lane = lane_id(), w0 = u * 2;
-              if (lane == 0 && w0 < J.nw_f)
-                J.pcount[w0] = __popc((uint32_t)ba) + __popc((uint32_t)bb);
-              if (lane == 32 && w0 + 1 < J.nw_f)
-                J.pcount[w0 + 1] = __popc((uint32_t)(ba >> 32)) + __popc((uint32_t)(bb >> 32));
-            });
+  for_unit_chunks(jobs, njobs, gwave(), nwaves(),
+                  [](const Job& J) { return (3 * J.g.fa + 63) >> 6; },
+                  [&](const Job& J, int u0, int u1) {
+                    const Grid& g = J.g;
+                    const int lane = lane_id();
+                    BlockWalk w;
+                    w.init(g, 1, u0 * 64 + lane);
+                    for (int u = u0; u < u1; ++u, w.advance64()) {
+                      const int f = u * 64 + lane;
+                      int act = 0, amb = 0, flip = 0;
+                      if (f < 3 * g.fa) {
+                        int Lf[4];
+                        face_labels(g, J.labels, w.a, w.p, Lf);
+                        const int n = __popc(face_crossing_mask(Lf));
+                        act = n > 0;
+                        amb = n == 4;
+                        if (amb) flip = face_flip(g, J.labels, table, w.a, w.p);
+                      }
+                      const uint64_t ba = __ballot(act), bb = __ballot(amb), bf = __ballot(flip);
+                      store_ballot(ba, u * 64, J.nw_f, J.fact);
+                      store_ballot(bb, u * 64, J.nw_f, J.famb);
+                      store_ballot(bf, u * 64, J.nw_f, J.fflip);
+                      const int w0 = u * 2;
+                      if (lane == 0 && w0 < J.nw_f)
+                        J.pcount[w0] = __popc((uint32_t)ba) + __popc((uint32_t)bb);
+                      if (lane == 32 && w0 + 1 < J.nw_f)
+                        J.pcount[w0 + 1] =
+                            __popc((uint32_t)(ba >> 32)) + __popc((uint32_t)(bb >> 32));
+                    }
+                  });
 }
 
 __global__ __launch_bounds__(256) void k_classify_cells(const Job* __restrict__ jobs, int njobs) {
-  for_units(jobs, njobs, gwave(), nwaves(),
-            [](const Job& J) { return (J.g.ncell + 63) >> 6; },
-            [&](const Job& J, int u) {
-              const Grid& g = J.g;
-              const int c = u * 64 + lane_id();
-              int x = 0;
-              if (c < g.ncell) {
-                const int N = g.N;
-                const int cfg = cell_config(g, J.labels, c % N, (c / N) % N, c / (N * N));
-                x = cfg != 0 && cfg != 255;
-              }
-              const uint64_t b = __ballot(x);
-              store_ballot(b, u * 64, J.nw_cell, J.cmask);
-              const int lane = lane_id(), w0 = u * 2;
-              if (lane == 0 && w0 < J.nw_cell) J.ccount[w0] = __popc((uint32_t)b);
-              if (lane == 32 && w0 + 1 < J.nw_cell)
-                J.ccount[w0 + 1] = __popc((uint32_t)(b >> 32));
-            });
+  for_unit_chunks(jobs, njobs, gwave(), nwaves(),
+                  [](const Job& J) { return (J.g.ncell + 63) >> 6; },
+                  [&](const Job& J, int u0, int u1) {
+                    const Grid& g = J.g;
+                    const int lane = lane_id();
+                    BlockWalk w;
+                    w.init(g, 2, u0 * 64 + lane);
+                    for (int u = u0; u < u1; ++u, w.advance64()) {
+                      const int c = u * 64 + lane;
+                      int x = 0;
+                      if (c < g.ncell) {
+                        const int cfg = cell_config(g, J.labels, w.p[0], w.p[1], w.p[2]);
+                        x = cfg != 0 && cfg != 255;
+                      }
+                      const uint64_t b = __ballot(x);
+                      store_ballot(b, u * 64, J.nw_cell, J.cmask);
+                      const int w0 = u * 2;
+                      if (lane == 0 && w0 < J.nw_cell) J.ccount[w0] = __popc((uint32_t)b);
+                      if (lane == 32 && w0 + 1 < J.nw_cell)
+                        J.ccount[w0 + 1] = __popc((uint32_t)(b >> 32));
+                    }
+                  });
 }
 
 // ------------------------------------------------------------ compaction
