@@ -110,7 +110,13 @@ __device__ __forceinline__ void grid_world(const Grid& g, const float gp[3], flo
 }
 
 // ------------------------------------------------------------- CSG labels
-__device__ __forceinline__ int prim_inside(const float* __restrict__ p, const float x[3]) {
+// Primitive records stay unchanged for a whole launch.  Read through the
+// constant address space, their (wave-uniform) fields come in through
+// scalar loads, also in kernels that store to global memory while they
+// evaluate the field.
+typedef const __attribute__((address_space(4))) float PrimF;
+
+__device__ __forceinline__ int prim_inside(const PrimF* __restrict__ p, const float x[3]) {
   const int type = (int)p[1];
   const float dx = x[0] - p[2];
   const float dy = x[1] - p[3];
@@ -137,11 +143,12 @@ __device__ __forceinline__ int prim_inside(const float* __restrict__ p, const fl
 
 // Left fold over the primitives; a primitive whose operation cannot change
 // the running result is skipped (booleans, so the result is unchanged).
-__device__ __forceinline__ int csg_inside(const float* __restrict__ prims, int n,
+__device__ __forceinline__ int csg_inside(const float* __restrict__ prims_, int n,
                                           const float x[3]) {
+  const PrimF* prims = (const PrimF*)prims_;
   int acc = prim_inside(prims, x);
   for (int i = 1; i < n; ++i) {
-    const float* p = prims + kPrimFloats * i;
+    const PrimF* p = prims + kPrimFloats * i;
     const int op = (int)p[0];
     if ((op == 0) == (acc != 0)) continue;  // union of true / subtract or intersect of false
     const int b = prim_inside(p, x);
@@ -158,7 +165,7 @@ __device__ __forceinline__ int csg_inside(const float* __restrict__ prims, int n
 // within their distance of a zero of it: |d| at a point bounds how close a
 // label change can be.  Used only to mark coarse cells (adaptive corner
 // evaluation); labels always come from csg_inside.
-__device__ __forceinline__ float prim_distance(const float* __restrict__ p, const float x[3]) {
+__device__ __forceinline__ float prim_distance(const PrimF* __restrict__ p, const float x[3]) {
   const int type = (int)p[1];
   const float dx = x[0] - p[2], dy = x[1] - p[3], dz = x[2] - p[4];
   if (type == 0) return sqrtf(dx * dx + dy * dy + dz * dz) - p[5];
@@ -177,11 +184,12 @@ __device__ __forceinline__ float prim_distance(const float* __restrict__ p, cons
   return (p[5] * dx + p[6] * dy + p[7] * dz) / nn;
 }
 
-__device__ __forceinline__ float csg_distance(const float* __restrict__ prims, int n,
+__device__ __forceinline__ float csg_distance(const float* __restrict__ prims_, int n,
                                               const float x[3]) {
+  const PrimF* prims = (const PrimF*)prims_;
   float acc = prim_distance(prims, x);
   for (int i = 1; i < n; ++i) {
-    const float* p = prims + kPrimFloats * i;
+    const PrimF* p = prims + kPrimFloats * i;
     const int op = (int)p[0];
     const float b = prim_distance(p, x);
     acc = op == 0 ? fminf(acc, b) : (op == 1 ? fmaxf(acc, -b) : fmaxf(acc, b));
