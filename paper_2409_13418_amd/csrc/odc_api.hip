@@ -1051,7 +1051,7 @@ extern "C" int32_t odc_autotune(odc_context* ctx, const odc_field* f, const odc_
   float st[8];
   TRY(time_stages(st));  // warm-up at the current configuration
   const int grid_c[4] = {512, 1024, 2048, 4096};
-  const int elem_c[4] = {256, 512, 1024, 2048};
+  const int elem_c[4] = {1024, 2048, 4096, 8192};
   const int mlp_c[2] = {256, 512};
   LaunchCfg best = ctx->cfg;
   float bt = 1e30f;

@@ -14,7 +14,7 @@ namespace odc {
 // by the autotuner.
 struct LaunchCfg {
   int grid_blocks = 2048;  // grid-wide passes: CSG labels, classification, compaction
-  int elem_blocks = 1024;  // thread-per-element passes over active sets
+  int elem_blocks = 4096;  // thread-per-element passes over active sets
   int mlp_blocks = 256;    // wavefront-per-32-elements MLP passes (LDS-bound: 1 block/CU)
   int scan_blocks = 512;
   int pack_blocks = 512;
