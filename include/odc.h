@@ -237,8 +237,7 @@ int32_t odc_mesh_sync(odc_context* ctx, odc_mesh_counts* counts);
  * does not: OUT_OF_MEMORY with the sizes, before anything is launched).
  * Asynchronous; wait with odc_mesh_sync, which then never regrows or reruns:
  * active sets or a bf16 guard queue that outgrow the array give
- * OUT_OF_MEMORY (the counts still hold what was found), and
- * n_flipped_faces is -1.  Every call on a GPU shares that GPU's array and
+ * OUT_OF_MEMORY (the counts still hold what was found).  Every call on a GPU shares that GPU's array and
  * leaves its contents there until the next call: calls on one GPU that
  * overlap (several contexts or streams) race, and an earlier extract's
  * intermediates are gone after the next one.  Same arguments and errors as
@@ -421,7 +420,7 @@ typedef struct {
 typedef struct {
   int32_t status;            /* odc_status of the job (CAPACITY: counts hold the sizes needed) */
   int32_t attempts;          /* launches of the job (> 1 after a scratch overflow) */
-  odc_mesh_counts counts;    /* n_flipped_faces is -1 */
+  odc_mesh_counts counts;
   double submit_ms;          /* host steady clock, ms since the server started */
   double admit_ms;           /* last admission into a lane */
   double done_ms;            /* completion seen by the scheduler */

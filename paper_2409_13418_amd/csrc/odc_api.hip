@@ -412,7 +412,7 @@ Layout job_layout(const Job& J, const odc_field* f, bool guard_full, bool trace)
   L.active[17] = trace ? align_up(ne * 4) : 0;
   L.active[18] = trace ? align_up(np * 16) : 0;
   L.active_total += L.active[16] + L.active[17] + L.active[18];
-  L.status = align_up(6 * sizeof(unsigned long long));
+  L.status = align_up(7 * sizeof(unsigned long long));
   if (f->kind == ODC_FIELD_MLP) {
     const int kb1f = kb1_fp32(f->in_dim), kb1b = kb1_bf16(f->in_dim), d = f->depth;
     L.n_w1f = (size_t)kb1f * 512;
@@ -854,17 +854,7 @@ void odc::fill_counts(const odc_context* ctx, int k, odc_mesh_counts* c) {
   c->n_queries = c->n_corner_queries + c->n_guard_corners +
                  c->n_active_edges * ((J.ablation & kAblLinear1D) ? 2 : J.iters_1d) +
                  c->n_search2d_queries;
-  c->n_flipped_faces = -1;
-}
-
-static int32_t count_flips(odc_context* ctx, int k, int64_t* out) {
-  const Job& J = ctx->hjobs[k];
-  std::vector<uint32_t> host((size_t)J.nw_f);
-  HIP_TRY(ctx, hipMemcpy(host.data(), J.fflip, (size_t)J.nw_f * 4, hipMemcpyDeviceToHost));
-  int64_t n = 0;
-  for (uint32_t w : host) n += __builtin_popcount(w);
-  *out = n;
-  return ODC_OK;
+  c->n_flipped_faces = (int64_t)o[10];
 }
 
 extern "C" int32_t odc_mesh_sync_batch(odc_context* ctx, int32_t n, odc_mesh_counts* counts) {
@@ -887,10 +877,7 @@ extern "C" int32_t odc_mesh_sync_batch(odc_context* ctx, int32_t n, odc_mesh_cou
 extern "C" int32_t odc_mesh_sync(odc_context* ctx, odc_mesh_counts* c) {
   if (!ctx || !c) return ODC_ERR_INVALID_ARG;
   if (ctx->pending != 1) return fail(ctx, ODC_ERR_INVALID_ARG, "no single extract pending");
-  int32_t rc = odc_mesh_sync_batch(ctx, 1, c);
-  if ((rc == ODC_OK || rc == ODC_ERR_CAPACITY) && !ctx->pending_fixed)
-    TRY(count_flips(ctx, 0, &c->n_flipped_faces));
-  return rc;
+  return odc_mesh_sync_batch(ctx, 1, c);
 }
 
 extern "C" int32_t odc_get_job_intermediate(odc_context* ctx, int32_t job, int32_t which,

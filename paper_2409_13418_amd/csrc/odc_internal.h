@@ -40,8 +40,9 @@ hipError_t launch_pipeline(const Job* d, int njobs, const PipelineShape& sh,
                            const LaunchCfg& cfg, hipEvent_t* ev, hipStream_t s);
 // kGatherWords x uint64 per job: edges, pairs, cells, partition vertices,
 // triangles, case-3 vertices, guard corners, fp64 cells | overflow << 32,
-// 2D-search queries made (MLP), corner queries (adaptive evaluation)
-constexpr int kGatherWords = 10;
+// 2D-search queries made (MLP), corner queries (adaptive evaluation),
+// flipped faces
+constexpr int kGatherWords = 11;
 hipError_t launch_gather(const Job* d, int njobs, unsigned long long* out, hipStream_t s);
 hipError_t launch_eval(const Job* d_job, const Job& h_job, const float* const* d_weights,
                        int precision, const float* xyz, int n, float* z, const LaunchCfg& cfg,

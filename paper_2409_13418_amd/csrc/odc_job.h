@@ -96,7 +96,8 @@ struct Job {
   int* out_vref;
 
   // [0] guard corners, [1] fp64 cells, [2] overflow, [3] 2D-search queries,
-  // [4] corner queries, [5] listed fine words (adaptive evaluation)
+  // [4] corner queries, [5] listed fine words (adaptive evaluation),
+  // [6] flipped faces
   unsigned long long* status;
   uint32_t* guard_list;
   int guard_cap;

@@ -318,6 +318,7 @@ __global__ void k_clear_status(const Job* __restrict__ jobs, int njobs) {
     jobs[k].status[3] = 0;
     jobs[k].status[4] = 0;
     jobs[k].status[5] = 0;
+    jobs[k].status[6] = 0;
   }
 }
 
@@ -338,6 +339,7 @@ __global__ void k_gather(const Job* __restrict__ jobs, int njobs,
     o[7] = J.status[1] | (J.status[2] << 32);
     o[8] = J.status[3];
     o[9] = J.status[4];
+    o[10] = J.status[6];
   }
 }
 
@@ -741,6 +743,7 @@ __global__ __launch_bounds__(256) void k_classify_faces(const Job* __restrict__ 
                     const int lane = lane_id();
                     BlockWalk w;
                     w.init(g, 1, u0 * 64 + lane);
+                    int flips = 0;  // wave-uniform
                     for (int u = u0; u < u1; ++u, w.advance64()) {
                       const int f = u * 64 + lane;
                       int act = 0, amb = 0, flip = 0;
@@ -756,6 +759,7 @@ __global__ __launch_bounds__(256) void k_classify_faces(const Job* __restrict__ 
                       store_ballot(ba, u * 64, J.nw_f, J.fact);
                       store_ballot(bb, u * 64, J.nw_f, J.famb);
                       store_ballot(bf, u * 64, J.nw_f, J.fflip);
+                      flips += __popcll(bf);
                       const int w0 = u * 2;
                       if (lane == 0 && w0 < J.nw_f)
                         J.pcount[w0] = __popc((uint32_t)ba) + __popc((uint32_t)bb);
@@ -763,6 +767,8 @@ __global__ __launch_bounds__(256) void k_classify_faces(const Job* __restrict__ 
                         J.pcount[w0 + 1] =
                             __popc((uint32_t)(ba >> 32)) + __popc((uint32_t)(bb >> 32));
                     }
+                    if (lane == 0 && flips)
+                      atomicAdd(&J.status[6], (unsigned long long)flips);
                   });
 }
 
