@@ -32,7 +32,17 @@ def test_edge_points_match_dense_sampling(oracle_mod):
     o = oracle_mod.Oracle(f, g)
     m = o.mesh()
     k = g.iters_1d
-    assert len(m["edge_id"]) == 142  # the survey's count for this grid
+    # crossing edges counted directly: corners lo + i h are exact in binary64
+    # on this grid, inside iff |x - c|^2 < r^2, and no corner lies within
+    # 1e-6 of the sphere (so binary32 rounding cannot flip a label)
+    c, r = f.prims[0, 2:5].astype(np.float64), float(f.prims[0, 5])
+    xs = [g.lo[a] + np.arange(g.res + 1) * (g.size / g.res) for a in range(3)]
+    X, Y, Z = np.meshgrid(*xs, indexing="ij")
+    d2 = (X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2
+    assert np.abs(d2 - r * r).min() > 1e-6
+    ins = d2 < r * r
+    n_cross = sum(int((np.diff(ins, axis=a) != 0).sum()) for a in range(3))
+    assert len(m["edge_id"]) == n_cross > 0
     for x, e in enumerate(m["edge_id"]):
         a, p = edge_origin(e, g.res)
         labs = []
