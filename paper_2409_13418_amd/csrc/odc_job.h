@@ -97,7 +97,7 @@ struct Job {
 
   // [0] guard corners, [1] fp64 cells, [2] overflow, [3] 2D-search queries,
   // [4] corner queries, [5] listed fine words (adaptive evaluation),
-  // [6] flipped faces
+  // [6] flipped faces, [7] 2D-search units taken
   unsigned long long* status;
   uint32_t* guard_list;
   int guard_cap;

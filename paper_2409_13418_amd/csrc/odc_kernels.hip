@@ -319,6 +319,7 @@ __global__ void k_clear_status(const Job* __restrict__ jobs, int njobs) {
     jobs[k].status[4] = 0;
     jobs[k].status[5] = 0;
     jobs[k].status[6] = 0;
+    jobs[k].status[7] = 0;
   }
 }
 
@@ -1311,15 +1312,31 @@ __global__ __launch_bounds__(256) void k_search2d_csg(const Job* __restrict__ jo
 // pair ends takes the next pair of the wavefront's stream at once, so lanes
 // do not wait for the slowest pair of a group, and each pair makes only the
 // queries it needs.  The stream is the pairs of the units this worker owns
-// (units of `per_unit` pairs; this wavefront's 32 of each start at `off`).
+// (units of `per_unit` pairs; this wavefront's 32 of each start at `off`):
+// units u0, u0 + W, ... (n_units of them), or, with kDyn, units of the job's
+// n_units taken from its counter `ctr` as the wavefront needs them, so
+// wavefronts that draw short pairs take more units and all end together.
 // `lab.any` ends the loop when no lane of the evaluating group has a query.
-template <class Lab>
+__device__ __forceinline__ int take_unit(unsigned long long* ctr) {
+  int v = 0;
+  if (lane_id() == 0) v = (int)atomicAdd(ctr, 1ull);
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+template <class Lab, bool kDyn = false>
 __device__ __forceinline__ void search_stream(const Job& J, const Lab& lab, int u0, int W,
-                                              int n_units, int per_unit, int off) {
+                                              int n_units, int per_unit, int off,
+                                              unsigned long long* ctr = nullptr) {
   const int np = n_pairs_of(J);
   const int lane = lane_id(), ln = lane & 31;
   const int slen = n_units * 32;
   int next = 0, have = 0, x = 0, need = 0;
+  // kDyn: the units of stream slots next / 32 and the one after
+  int ub0 = 0, ub1 = 0;
+  if (kDyn) {
+    ub0 = take_unit(ctr);
+    ub1 = take_unit(ctr);
+  }
   PairSearch ps;
   while (true) {
     float gp[3] = {0.0f, 0.0f, 0.0f};
@@ -1340,11 +1357,18 @@ __device__ __forceinline__ void search_stream(const Job& J, const Lab& lab, int 
     }
     // refill: the free lanes (the same in both halves) take the next pairs
     const uint32_t free_lanes = (uint32_t)__ballot(!have);
-    if (free_lanes != 0u && next < slen) {
+    if (free_lanes != 0u && (kDyn ? ub0 < n_units : next < slen)) {
       const int pos = next + __popc(free_lanes & ((1u << ln) - 1u));
+      const int slot0 = next >> 5;
       next += __popc(free_lanes);
-      if (!have && pos < slen) {
-        const int xi = (u0 + (pos >> 5) * W) * per_unit + off + (pos & 31);
+      // at most 32 lanes are free, so pos lies in slot0 or the slot after
+      const int unit = kDyn ? ((pos >> 5) == slot0 ? ub0 : ub1) : u0 + (pos >> 5) * W;
+      if (kDyn && (next >> 5) != slot0) {
+        ub0 = ub1;
+        ub1 = take_unit(ctr);
+      }
+      if (!have && (kDyn ? unit < n_units : pos < slen)) {
+        const int xi = unit * per_unit + off + (pos & 31);
         if (xi < np) {
           x = xi;
           const int rec = J.plist[x];
@@ -1362,21 +1386,21 @@ __device__ __forceinline__ void search_stream(const Job& J, const Lab& lab, int 
   if (lane == 0 && nsum) atomicAdd(&J.status[3], (unsigned long long)nsum);
 }
 
+// Every wavefront takes part in every job, drawing units of 32 pairs from
+// the job's counter (status[7]) until they run out.
 __global__ __launch_bounds__(256) void k_search2d_mlp(const Job* __restrict__ jobs, int njobs) {
   __shared__ __align__(16) float act_lds[kBlock / 64][kActWords];
   float* act = act_lds[threadIdx.x >> 6];
-  const int W = nwaves();
-  for_unit_streams(jobs, njobs, gwave(), W,
-                   [](const Job& J) {
-                     return (J.kind == 1 && J.precision != 2 &&
-                             !(J.ablation & kAblGradNormals))
-                                ? (n_pairs_of(J) + 31) >> 5
-                                : 0;
-                   },
-                   [&](const Job& J, int u0, int count) {
-                     MlpLabel lab{&J.g, &J.mlp, act};
-                     search_stream(J, lab, u0, W, count, 32, 0);
-                   });
+  const __attribute__((address_space(4))) Job* cj =
+      (const __attribute__((address_space(4))) Job*)jobs;
+  for (int k = 0; k < njobs; ++k) {
+    const Job& J = *(const Job*)&cj[k];
+    if (!(J.kind == 1 && J.precision != 2 && !(J.ablation & kAblGradNormals))) continue;
+    const int nu = (n_pairs_of(J) + 31) >> 5;
+    if (nu == 0) continue;
+    MlpLabel lab{&J.g, &J.mlp, act};
+    search_stream<MlpLabel, true>(J, lab, 0, 0, nu, 32, 0, &J.status[7]);
+  }
 }
 
 // Split-bf16 evaluation (precision 2): a workgroup keeps 128 pairs in
