@@ -412,7 +412,7 @@ Layout job_layout(const Job& J, const odc_field* f, bool guard_full, bool trace)
   L.active[17] = trace ? align_up(ne * 4) : 0;
   L.active[18] = trace ? align_up(np * 16) : 0;
   L.active_total += L.active[16] + L.active[17] + L.active[18];
-  L.status = align_up(8 * sizeof(unsigned long long));
+  L.status = align_up(9 * sizeof(unsigned long long));
   if (f->kind == ODC_FIELD_MLP) {
     const int kb1f = kb1_fp32(f->in_dim), kb1b = kb1_bf16(f->in_dim), d = f->depth;
     L.n_w1f = (size_t)kb1f * 512;

@@ -27,7 +27,7 @@ struct Slot {
   DevBuf active;  // active-set arrays
   DevBuf mlpw;    // packed MLP weights
   DevBuf guard;   // bf16 guard queue
-  DevBuf status;  // 8 x uint64
+  DevBuf status;  // 9 x uint64
   int cap_edges = 0;
   bool guard_full = false;
   char* ext = nullptr;

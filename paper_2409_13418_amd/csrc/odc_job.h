@@ -97,7 +97,7 @@ struct Job {
 
   // [0] guard corners, [1] fp64 cells, [2] overflow, [3] 2D-search queries,
   // [4] corner queries, [5] listed fine words (adaptive evaluation),
-  // [6] flipped faces, [7] 2D-search units taken
+  // [6] flipped faces, [7] 2D-search units taken, [8] bisection units taken
   unsigned long long* status;
   uint32_t* guard_list;
   int guard_cap;
@@ -174,6 +174,32 @@ __device__ __forceinline__ void for_unit_streams(const Job* __restrict__ jobs, i
     if (u0 < 0) u0 += W;
     if (u0 < n) body(J, u0, (n - u0 + W - 1) / W);
     rot += n;
+  }
+}
+
+// A unit index drawn by the wavefront from a counter in device memory
+// (wave-uniform; every lane must call it).
+__device__ __forceinline__ int take_unit(unsigned long long* ctr) {
+  int v = 0;
+  if (lane_id() == 0) v = (int)atomicAdd(ctr, 1ull);
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Job-major distribution by drawing: every wavefront takes part in every
+// job and draws its units from the job's counter ctr(J) (cleared before the
+// launch) until they run out, so wavefronts whose units run short take more
+// of them and all end together.  body(J, u) runs wave-uniformly.
+template <class NFn, class CFn, class Body>
+__device__ __forceinline__ void for_units_drawn(const Job* __restrict__ jobs, int njobs,
+                                                const NFn& nunits, const CFn& ctr,
+                                                const Body& body) {
+  const __attribute__((address_space(4))) Job* cj =
+      (const __attribute__((address_space(4))) Job*)jobs;
+  for (int k = 0; k < njobs; ++k) {
+    const Job& J = *(const Job*)&cj[k];
+    const int n = nunits(J);
+    if (n <= 0) continue;
+    for (int u = take_unit(ctr(J)); u < n; u = take_unit(ctr(J))) body(J, u);
   }
 }
 

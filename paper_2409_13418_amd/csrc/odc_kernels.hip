@@ -320,6 +320,7 @@ __global__ void k_clear_status(const Job* __restrict__ jobs, int njobs) {
     jobs[k].status[5] = 0;
     jobs[k].status[6] = 0;
     jobs[k].status[7] = 0;
+    jobs[k].status[8] = 0;
   }
 }
 
@@ -959,10 +960,11 @@ __device__ __forceinline__ float linear_edge_mlp(const Job& J, int e, float* act
 __global__ __launch_bounds__(256) void k_bisect_mlp(const Job* __restrict__ jobs, int njobs) {
   __shared__ __align__(16) float act_lds[kBlock / 64][kActWords];
   float* act = act_lds[threadIdx.x >> 6];
-  for_units(jobs, njobs, gwave(), nwaves(),
+  for_units_drawn(jobs, njobs,
             [](const Job& J) {
               return J.kind == 1 && J.precision != 2 ? (n_edges_of(J) + 31) >> 5 : 0;
             },
+            [](const Job& J) { return &J.status[8]; },
             [&](const Job& J, int t) {
               const int ne = n_edges_of(J);
               const int lane = lane_id();
@@ -1317,12 +1319,6 @@ __global__ __launch_bounds__(256) void k_search2d_csg(const Job* __restrict__ jo
 // n_units taken from its counter `ctr` as the wavefront needs them, so
 // wavefronts that draw short pairs take more units and all end together.
 // `lab.any` ends the loop when no lane of the evaluating group has a query.
-__device__ __forceinline__ int take_unit(unsigned long long* ctr) {
-  int v = 0;
-  if (lane_id() == 0) v = (int)atomicAdd(ctr, 1ull);
-  return __builtin_amdgcn_readfirstlane(v);
-}
-
 template <class Lab, bool kDyn = false>
 __device__ __forceinline__ void search_stream(const Job& J, const Lab& lab, int u0, int W,
                                               int n_units, int per_unit, int off,
