@@ -69,6 +69,9 @@ def compare_discrete(r, m):
         bad.append("partition counts differ")
     if not np.array_equal(r["cell_nf"] >> 4, m["cell_flipmask"]):
         bad.append("manifold flips differ")
+    if "n_flipped_faces" in r and r["n_flipped_faces"] != m["n_flipped_faces"]:
+        bad.append(f"flipped-face counts differ: {r['n_flipped_faces']} against "
+                   f"{m['n_flipped_faces']}")
     # partition maps compared on crossing edges only
     if not np.array_equal(r["cell_partmap"].astype(np.int64), m["cell_partmap"].astype(np.int64)):
         bad.append(f"partition maps differ in {int(np.sum(r['cell_partmap'] != m['cell_partmap']))} cells")
