@@ -184,15 +184,14 @@ typedef struct {
   int64_t n_fp64_cells;    /* QEF solves redone in binary64 */
   int64_t n_guard_corners; /* bf16 corner queries re-evaluated in fp32 */
   int64_t n_queries;       /* occupancy queries issued (corners, guard repeats, searches) */
-  int64_t n_search2d_queries; /* of which in the 2D searches: analytic fields every query of
-                                 each pair's sequence, n_pairs x (1 + lin1 + bin1 +
-                                 2 (lin2 + bin2)); MLP fields only the queries each pair
-                                 needs (= n_search2d_needed) */
-  int64_t n_search2d_needed;  /* MLP fields: the 2D-search queries the method itself needs,
-                                 summed over pairs (m; per ray the linear samples up to
-                                 the first label change and the halvings; no step-2 rays
-                                 when step 1 ends at m).  -1 for analytic fields and
-                                 gradient normals (not counted). */
+  int64_t n_search2d_queries; /* of which in the 2D searches: the queries each pair needs
+                                 (= n_search2d_needed) */
+  int64_t n_search2d_needed;  /* the 2D-search queries the method itself needs, summed
+                                 over pairs (m; per ray the linear samples up to the first
+                                 label change and the halvings; no step-2 rays when step 1
+                                 ends at m), at most n_pairs x (1 + lin1 + bin1 +
+                                 2 (lin2 + bin2)).  -1 with gradient normals (no 2D
+                                 searches). */
   int64_t n_corner_queries;   /* corner queries of stage (a): (res + 1)^3, or with
                                  coarse_step > 1 the coarse corners plus the fine corners
                                  evaluated (the bf16 guard's repeats not included) */

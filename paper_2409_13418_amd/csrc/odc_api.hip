@@ -842,14 +842,12 @@ void odc::fill_counts(const odc_context* ctx, int k, odc_mesh_counts* c) {
   c->n_guard_corners = (int64_t)o[6];
   c->n_fp64_cells = (int64_t)(o[7] & 0xFFFFFFFFull);
   // occupancy queries: every corner, the bf16 guard's fp32 repeats, the 1D
-  // points (two corner queries each for linear points), the 2D searches: for
-  // analytic fields every query of each pair's sequence, for MLP fields the
-  // queries the pairs needed, counted on the device (none with gradient
-  // normals, whose passes are not occupancy queries)
-  const int64_t per_pair = 1 + (J.lin1 + J.bin1) + 2 * (J.lin2 + J.bin2);
+  // points (two corner queries each for linear points), the 2D searches'
+  // queries, the ones the pairs needed, counted on the device (none with
+  // gradient normals, whose passes are not occupancy queries)
   const bool grad = (J.ablation & kAblGradNormals) != 0;
-  c->n_search2d_needed = (J.kind == 1 && !grad) ? (int64_t)o[8] : -1;
-  c->n_search2d_queries = grad ? 0 : (J.kind == 1 ? (int64_t)o[8] : c->n_pairs * per_pair);
+  c->n_search2d_needed = grad ? -1 : (int64_t)o[8];
+  c->n_search2d_queries = grad ? 0 : (int64_t)o[8];
   c->n_corner_queries = J.coarse_step ? (int64_t)o[9] : (int64_t)J.g.nc;
   c->n_queries = c->n_corner_queries + c->n_guard_corners +
                  c->n_active_edges * ((J.ablation & kAblLinear1D) ? 2 : J.iters_1d) +

@@ -1288,24 +1288,40 @@ struct PairSearch {
   }
 };
 
-// Analytic fields: one thread per pair, every query of the sequence made
-// (queries are cheap; the count stays n_pairs x the sequence length).
+// Analytic fields: one thread per pair, making the queries the pair needs
+// (the early exits of PairSearch), counted per wavefront into status[3].
+// The job-major distribution of for_units, written out so that the whole
+// wavefront sums its count after each job's pairs.
 __global__ __launch_bounds__(256) void k_search2d_csg(const Job* __restrict__ jobs, int njobs) {
-  for_units(jobs, njobs, gthread(), nthreads(),
-            [](const Job& J) { return J.kind == 0 ? n_pairs_of(J) : 0; },
-            [&](const Job& J, int x) {
-              CsgLabel lab{&J.g, J.prims, J.n_prims};
-              const int rec = J.plist[x];
-              PairSearch ps;
-              ps.init(J, rec >> 1, rec & 1);
-              float gp[3];
-              while (ps.next(J, false, gp)) ps.take(J, lab(gp));
-              J.pf[x] = ps.result();
-              if (J.ptrace) {
-                J.ptrace[2 * x] = ps.bits;
-                J.ptrace[2 * x + 1] = ps.evald;
-              }
-            });
+  const __attribute__((address_space(4))) Job* cj =
+      (const __attribute__((address_space(4))) Job*)jobs;
+  const int worker = gthread(), W = nthreads();
+  long long rot = 0;
+  for (int k = 0; k < njobs; ++k) {
+    const Job& J = *(const Job*)&cj[k];
+    const int n = J.kind == 0 ? n_pairs_of(J) : 0;
+    if (n <= 0) continue;
+    int u0 = (int)(((long long)worker - rot) % W);
+    if (u0 < 0) u0 += W;
+    int need = 0;
+    for (int x = u0; x < n; x += W) {
+      CsgLabel lab{&J.g, J.prims, J.n_prims};
+      const int rec = J.plist[x];
+      PairSearch ps;
+      ps.init(J, rec >> 1, rec & 1);
+      float gp[3];
+      while (ps.next(J, true, gp)) ps.take(J, lab(gp));
+      J.pf[x] = ps.result();
+      if (J.ptrace) {
+        J.ptrace[2 * x] = ps.bits;
+        J.ptrace[2 * x + 1] = ps.evald;
+      }
+      need += ps.need;
+    }
+    const int nsum = wave_sum(need);
+    if (lane_id() == 0 && nsum) atomicAdd(&J.status[3], (unsigned long long)nsum);
+    rot += n;
+  }
 }
 
 // MLP fields: a wavefront keeps 32 pairs in flight, one per lane (lanes

@@ -72,7 +72,7 @@ def test_csg_parity_uneven_search_lengths(ctx, oracle_mod, lin1, bin1, lin2, bin
     m = oracle_mod.Oracle(f, g, trace=tr).mesh()
     check_replayed(r, m, tr, 24, f"csg24 {lin1}/{bin1} {lin2}/{bin2}")
     per_pair = 1 + lin1 + bin1 + 2 * (lin2 + bin2)
-    assert r["n_search2d_queries"] == r["n_pairs"] * per_pair
+    assert r["n_search2d_queries"] == needed_search_queries(m, g) < r["n_pairs"] * per_pair
 
 
 def test_world_coordinates(ctx, oracle_mod):
@@ -168,16 +168,16 @@ def test_x3_topology_matches_fp32(ctx, res):
 
 
 def test_search2d_query_counts(ctx):
-    """MLP searches make only the queries each pair needs (a lane whose pair
-    ends takes the next pair; no linear sample after its ray's first label
-    change, no step 2 when step 1 ends at m); CSG searches make every query
-    of the sequence.  The MLP count per pair lies between the sequence's
-    shortest and its full length."""
+    """The searches make only the queries each pair needs (no linear sample
+    after its ray's first label change, no step 2 when step 1 ends at m; on
+    MLP fields a lane whose pair ends takes the next pair).  The count per
+    pair lies between the sequence's shortest and its full length."""
     g = I.unit_grid(40, 15)
     per_pair = 1 + (g.lin1 + g.bin1) + 2 * (g.lin2 + g.bin2)
     r, _ = gpu_run(I.csg_random_field(2), g, ctx=ctx, want_local=False)
-    assert r["n_search2d_queries"] == r["n_pairs"] * per_pair
-    assert r["n_search2d_needed"] == -1
+    n, q = r["n_pairs"], r["n_search2d_queries"]
+    print(f"csg40: {q} 2D-search queries for {n} pairs ({q / n:.2f} per pair of {per_pair})")
+    assert q == r["n_search2d_needed"] and n * (2 + g.bin1) <= q < n * per_pair
     for prec in (0, 2):
         r, _ = gpu_run(I.mlp_field(3), g, precision=prec, ctx=ctx, want_local=False)
         n, q, need = r["n_pairs"], r["n_search2d_queries"], r["n_search2d_needed"]
