@@ -1418,21 +1418,25 @@ __global__ __launch_bounds__(256) void k_search2d_mlp(const Job* __restrict__ jo
 // Split-bf16 evaluation (precision 2): a workgroup keeps 128 pairs in
 // flight, 32 per wavefront, and the four evaluate each round of queries
 // together; it stops when none of the four has a query left.
+// Every workgroup takes part in every job; each wavefront draws its units
+// of 32 pairs from the job's counter (status[7]) on its own, and the four
+// keep evaluating together until none of them has a query.
 __global__ __launch_bounds__(256) void k_search2d_x3(const Job* __restrict__ jobs, int njobs) {
   __shared__ __align__(16) char lds[kX3LdsBytes];
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int W = (int)gridDim.x;
-  for_unit_streams(jobs, njobs, (int)blockIdx.x, W,
-                   [](const Job& J) {
-                     return J.kind == 1 && J.precision == 2 ? (n_pairs_of(J) + 127) >> 7 : 0;
-                   },
-                   [&](const Job& J, int u0, int count) {
-                     lds_block_sync();  // the previous job's reads of the staged field are done
-                     x3_stage(J.mlp, lds);
-                     lds_block_sync();
-                     X3Label lab{&J.g, &J.mlp, lds, wave, 0};
-                     search_stream(J, lab, u0, W, count, 128, wave * 32);
-                   });
+  const __attribute__((address_space(4))) Job* cj =
+      (const __attribute__((address_space(4))) Job*)jobs;
+  for (int k = 0; k < njobs; ++k) {
+    const Job& J = *(const Job*)&cj[k];
+    if (!(J.kind == 1 && J.precision == 2)) continue;
+    const int nu = (n_pairs_of(J) + 31) >> 5;
+    if (nu == 0) continue;
+    lds_block_sync();  // the previous job's reads of the staged field are done
+    x3_stage(J.mlp, lds);
+    lds_block_sync();
+    X3Label lab{&J.g, &J.mlp, lds, wave, 0};
+    search_stream<X3Label, true>(J, lab, 0, 0, nu, 32, 0, &J.status[7]);
+  }
 }
 
 // ----------------------------------------------------- (d) partitions, QEF
