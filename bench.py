@@ -8,7 +8,7 @@ occupancy queries included) of that field with its inputs resident in HBM.
 Metric: active cells meshed per second.
 
 Prints one JSON line (--jsonl PATH also appends it, after per-step records,
-to a JSONL file).  --gpus above 1 is refused: this build runs on one GPU.
+to a JSONL file).  --gpus above 1 is refused: the library meshes on one GPU.
 Besides the timed steps, the line carries (all outside the timed region):
 the dominant kernel's roofline; the plain fp32 path's throughput on the same
 grid and whether its mesh equals the guarded path's (fp32_path); the same
@@ -559,7 +559,7 @@ def main():
                     help="also append the result (and per-step records) to this JSONL file")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build meshes on one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "the library meshes on one GPU only; run with --gpus 1"}))
         sys.exit(2)
 
     if args.mode == "batch":
