@@ -35,6 +35,9 @@ Other modes (not run by default):
                 two also with 3D points clamped to their cells) on the same
                 field: time, counts, manifold check, mean |phi - 1/2|,
                 self-intersecting triangle pairs.
+  --mode csg    the 72-primitive CSG field (48 boxes and 16 spheres, minus 8
+                boxes; seed 2) at --res cells per axis, timed as the default
+                line times the MLP field: cells/s, stage times, counts.
   --mode serve  Poisson arrivals (20 requests/s, 50/50 CSG/MLP, res 64/128/
                 256/512 with weights .4/.3/.2/.1) through the continuous-
                 batching server; p50/p99 latency (completion - arrival) and
@@ -439,6 +442,29 @@ def _ablation_mode(args):
         "rows": rows}, args)
 
 
+def _csg_mode(args):
+    """The analytic CSG field through the same path and timing as the
+    default line (its labels, bisection and searches run on the vector ALUs,
+    one query per thread)."""
+    from paper_2409_13418_amd import odc
+    field = I.csg_random_field(2)
+    grid = I.unit_grid(args.res, 15)
+    ctx = odc.Context(0)
+    df = odc.DeviceField(field)
+    params = odc.default_params(grid, odc.PREC_BF16_GUARDED)
+    ms_per_step, step_ms, stages, counts = _timed(ctx, df, params, args.steps, args.warmup)
+    emit({"metric": f"active cells meshed/sec at {args.res}^3 CSG occupancy",
+          "value": counts["n_active_cells"] / (ms_per_step / 1e3), "unit": "cells/s",
+          "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+          "data": "synthetic",
+          "config": {"workload": f"csg{args.res}", "res": args.res,
+                     "field": "union of 48 boxes and 16 spheres minus 8 boxes, seed 2",
+                     "iters_1d": grid.iters_1d},
+          "counts": {k: counts[k] for k in COUNT_KEYS}, "stages_ms": stages}, args,
+         [{"step": i, "ms": t, "workload": f"csg{args.res}"} for i, t in enumerate(step_ms)])
+
+
 def _copy_mode(args):
     import torch
     n = int(args.copy_mib) << 20
@@ -525,7 +551,7 @@ def _roofline(odc, field, grid, counts, stages, prec):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", choices=("single", "batch", "serve", "copy", "ablation"),
+    ap.add_argument("--mode", choices=("single", "batch", "serve", "copy", "ablation", "csg"),
                     default="single")
     ap.add_argument("--ablation-samples", type=int, default=1000000)
     ap.add_argument("--ablation-field", choices=("occupancy", "sdf"), default="occupancy")
@@ -568,6 +594,8 @@ def main():
         return _serve_mode(args)
     if args.mode == "copy":
         return _copy_mode(args)
+    if args.mode == "csg":
+        return _csg_mode(args)
     if args.mode == "ablation":
         return _ablation_mode(args)
 
